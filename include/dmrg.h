@@ -1,0 +1,243 @@
+/*
+ * dmrg.h -- C ABI of libdmrg, the MI355X (gfx950) superblock H*psi library.
+ *
+ * The library applies the DMRG superblock Hamiltonian of a grown system S'
+ * and a grown environment E' (paper Sec. 1 and Sec. 3.1, Fig. 2 steps (c)-(f))
+ *
+ *     y = ( H_S' (x) I + I (x) H_E' + sum_k c_k A_k (x) B_k ) psi
+ *
+ * without ever forming the superblock matrix (Sec. 3.3: the S'(x)E' product is
+ * a basis only; its Hamiltonian is applied on the fly from the S' and E'
+ * operators).  psi lives only in the targeted symmetry sector (Sec. 3.3:
+ * only the blocks with the targeted quantum numbers are diagonalised) and is
+ * stored block-sparse by effective quantum number (Sec. 3.2).  Every term is
+ * evaluated per symmetry block as Y_q += c_k A_k[q<-q'] Psi_q' B_k^T.
+ *
+ * Conventions common to all entry points
+ * --------------------------------------
+ * - Every function returns dmrg_status; none throws, aborts or prints.  On an
+ *   error the outputs are left untouched and dmrg_last_error() (per host
+ *   thread) describes the failure.
+ * - "_h" pointers are host memory, "_d" pointers are device memory on the
+ *   context's device.  Device buffers passed in are owned by the caller and
+ *   must stay valid until the work queued on the context's stream is done.
+ * - All device work is queued on the stream given to dmrg_ctx_create.
+ *   dmrg_hpsi and dmrg_hpsi_adjoint's psi gradient are asynchronous; the
+ *   calls that return host scalars synchronise that stream.
+ * - Precision: operator blocks and vectors cross the boundary in FP64.  The
+ *   block products run in the precision chosen at build time (FP64, FP32 on
+ *   the matrix cores, or BF16 hi/lo split x3); Lanczos vectors,
+ *   reorthogonalisation, the tridiagonal eigen-solve and the density-matrix
+ *   eigen-solve are always FP64.
+ */
+#ifndef DMRG_H
+#define DMRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DMRG_OK = 0,
+  DMRG_E_ARG = 1,          /* null pointer, negative size, bad enum value        */
+  DMRG_E_QN = 2,           /* quantum numbers inconsistent, or empty target      */
+  DMRG_E_SHAPE = 3,        /* a block's size disagrees with its sectors          */
+  DMRG_E_NOMEM = 4,        /* device or host allocation failed / over the cap    */
+  DMRG_E_DEVICE = 5,       /* HIP runtime error, or no device for this call      */
+  DMRG_E_NOCONV = 6,       /* Lanczos hit its iteration cap (partial result out) */
+  DMRG_E_UNSUPPORTED = 7   /* a term shape the fused kernel does not handle      */
+} dmrg_status;
+
+typedef enum {
+  DMRG_FP64 = 0,        /* FP64 matrix-core grouped kernel                          */
+  DMRG_FP32 = 1,        /* FP32 matrix-core grouped kernel, FP32 accumulate         */
+  DMRG_BF16X3 = 2,      /* BF16 hi/lo split, hi*hi + hi*lo + lo*hi, FP32 accumulate */
+  DMRG_FP64_PLAIN = 3   /* one launch per (term, symmetry block), FP64 FMA; the
+                           straightforward baseline                                 */
+} dmrg_prec;
+
+typedef struct dmrg_ctx_s* dmrg_ctx;   /* a device, a stream, workspace        */
+typedef struct dmrg_sb_s* dmrg_sb;     /* one superblock: plan + staged blocks */
+
+/* A basis split into symmetry sectors (Sec. 3.2: the effective quantum
+ * numbers in increasing order and the partition into equal-q runs).
+ *   nsec  number of sectors (>= 1)
+ *   q     [nsec] effective quantum numbers, strictly increasing
+ *   dim   [nsec] states per sector, each >= 1                                  */
+typedef struct {
+  int32_t nsec;
+  const int64_t* q;
+  const int32_t* dim;
+} dmrg_basis;
+
+/* A block-sparse operator on one basis.  Quantum numbers add under products
+ * (Sec. 3.2), so an operator shifts q by a fixed delta: block (r, c) may be
+ * present only if q[r] - q[c] == delta, and each row sector at most once.
+ *   delta    q(row) - q(col)
+ *   nblk     number of stored blocks
+ *   row_sec  [nblk] row sector index
+ *   col_sec  [nblk] column sector index
+ *   blk      [nblk] host FP64, row-major dim[row_sec] x dim[col_sec]
+ * Blocks whose rows hold at most one nonzero each (operators of the newest
+ * site, I (x) o) are stored by the library as a gather (index + scale); all
+ * others as dense blocks.  The caller's arrays are copied during
+ * dmrg_build_superblock and may be freed on return.                         */
+typedef struct {
+  int64_t delta;
+  int32_t nblk;
+  const int32_t* row_sec;
+  const int32_t* col_sec;
+  const double* const* blk;
+} dmrg_op;
+
+/* One term c * A (x) B of the superblock Hamiltonian (Sec. 3.3: the
+ * system part, the environment part and the system-environment connection;
+ * the connection is split into one term per bond operator product).
+ * A acts on S', B on E'; NULL means the identity.  delta(A) + delta(B) must
+ * be 0.  group is a free label carried for the caller (e.g. which coupling
+ * the term belongs to).                                                      */
+typedef struct {
+  double c;
+  const dmrg_op* A;
+  const dmrg_op* B;
+  int32_t group;
+} dmrg_term;
+
+/* Result of dmrg_rho_truncate (library-owned; valid until the next
+ * dmrg_rho_truncate on the same superblock or dmrg_sb_destroy).
+ *   trunc_err   sum of the discarded eigenvalues (Sec. 1, eps_tr)
+ *   kept        number of kept states
+ *   straddle    1 if the cut fell inside a cluster of tied eigenvalues
+ *   lambda      [kept] kept eigenvalues in selection order
+ *   lambda_sec  [kept] sector of each kept eigenvalue
+ *   nsec        sectors of the truncated side's basis
+ *   kept_per_sec[nsec] kept states per sector
+ *   W           [nsec] row-major dim[s] x kept_per_sec[s] eigenvector blocks,
+ *               columns in decreasing eigenvalue order (NULL if none kept)  */
+typedef struct {
+  double trunc_err;
+  int32_t kept;
+  int32_t straddle;
+  const double* lambda;
+  const int32_t* lambda_sec;
+  int32_t nsec;
+  const int32_t* kept_per_sec;
+  const double* const* W;
+} dmrg_trunc;
+
+/* ---------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`, queueing work on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream).  One context per host
+ * thread.                                                                  */
+dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx* out);
+void dmrg_ctx_destroy(dmrg_ctx ctx);
+
+/* Set the stream later work is queued on (e.g. the caller's current stream). */
+dmrg_status dmrg_ctx_set_stream(dmrg_ctx ctx, void* hip_stream);
+
+/* Message describing the last failure on this host thread ("" if none).   */
+const char* dmrg_last_error(void);
+
+/* Library version string.                                                   */
+const char* dmrg_version(void);
+
+/* Build a superblock: validate the quantum-number algebra (Sec. 3.2), match
+ * S' sector q with E' sector q_target - q (the target pairs, ordered by S'
+ * sector), lay out psi, classify blocks (dense / gather), build and
+ * cost-balance the work-tile schedule, and stage the operators on the device
+ * in `prec` (plus FP64 copies, used for FP64 refinement).
+ *   ctx may be NULL: then only the host plan is built (layout and statistics
+ *   can be queried; every device entry point returns DMRG_E_DEVICE).
+ * Errors: DMRG_E_QN (q not increasing, block breaks delta, term not
+ * q-neutral, no target pair), DMRG_E_SHAPE, DMRG_E_UNSUPPORTED (a term with
+ * dense blocks on both sides), DMRG_E_NOMEM, DMRG_E_DEVICE.              */
+dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_basis* E,
+                                  int64_t q_target, int32_t nterms, const dmrg_term* terms,
+                                  dmrg_prec prec, dmrg_sb* out);
+void dmrg_sb_destroy(dmrg_sb sb);
+
+/* psi layout (Eq. (1) restricted to the target): npairs blocks; block p is
+ * the row-major dim_S[s_sec[p]] x dim_E[e_sec[p]] matrix Psi_p starting at
+ * element off[p]; D = total length.  Arrays are library-owned.            */
+dmrg_status dmrg_sb_layout(dmrg_sb sb, int64_t* D, int32_t* npairs, const int64_t** off,
+                           const int32_t** s_sec, const int32_t** e_sec);
+
+/* Work statistics of one H*psi: algorithmic flops (dense blocks at their
+ * stored size, gathers at 2 flops per element touched), flops the matrix
+ * cores issue (padded tiles), algorithmic bytes (operators once in the
+ * compute precision, psi read and y read+written in FP64), and the number of
+ * work tiles.  Any pointer may be NULL.                                      */
+dmrg_status dmrg_sb_stats(dmrg_sb sb, double* flops_alg, double* flops_exec,
+                          double* bytes_alg, int32_t* ntiles);
+
+/* Replace the term coefficients c_k (nterms values, host) without a rebuild. */
+dmrg_status dmrg_sb_set_coeffs(dmrg_sb sb, const double* c_h);
+
+/* Select the block-product precision used by dmrg_hpsi (the superblock
+ * stages FP64 copies always, and `prec`'s copies if it was built with it
+ * or if this call stages them).                                            */
+dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec);
+
+/* y_d = alpha * H psi_d + beta * y_d (paper Sec. 3.3: the Lanczos solver's
+ * only need, x += H y, with alpha = beta = 1).  psi_d and y_d are device FP64
+ * arrays of length D in the dmrg_sb_layout order and must not overlap.
+ * Asynchronous on the context's stream.                                    */
+dmrg_status dmrg_hpsi(dmrg_sb sb, const double* psi_d, double* y_d, double alpha, double beta);
+
+/* Adjoint of the product, for differentiation:
+ *   gpsi_d = H^T g_d                 (device, length D, overwritten)
+ *   gc_h[k] = < g, (A_k (x) B_k) psi >  (host, nterms values; may be NULL)
+ * Synchronises the stream when gc_h is not NULL.                          */
+dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d,
+                              double* gpsi_d, double* gc_h);
+
+/* Lowest eigenpair of H in the target sector by Lanczos (Sec. 3.3), with
+ * FP64 vectors and full (twice-applied) reorthogonalisation.  When the
+ * superblock computes in reduced precision, each restart cycle begins with
+ * one FP64 product (Rayleigh quotient and residual in FP64) and continues in
+ * the reduced precision; cycles repeat until the FP64 residual
+ * || H psi - E psi || <= tol.
+ *   psi0_d    device FP64 [D] start vector (not modified; normalised inside)
+ *   max_iter  cap on the total number of products
+ *   E0_h      the FP64 Rayleigh quotient of the returned vector
+ *   psi_d     device FP64 [D] normalised ground state (may alias psi0_d)
+ *   iters_h   products used;  resid_h  final FP64 residual norm
+ * Returns DMRG_E_NOCONV (outputs still written) if the cap is reached.
+ * Synchronises the stream.                                                 */
+dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_iter, double tol,
+                                double* E0_h, double* psi_d, int32_t* iters_h, double* resid_h);
+
+/* Reduced density matrix of S' (side 0, Eq. (2): rho_S = Psi Psi^T) or E'
+ * (side 1, Eq. (3): rho_E = Psi^T Psi), formed per symmetry block on the
+ * device in FP64, diagonalised per block in FP64 on the host, eigenvalues
+ * ordered decreasingly with ties (relative gap <= 1e-6; values < 1e-13
+ * counted as 0) broken by (q ascending, in-sector index ascending); the first
+ * m are kept, all if m >= dimension (Sec. 1).  no_split != 0 extends the cut
+ * to the end of a straddled nonzero tie cluster.  Synchronises the stream. */
+dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int32_t m,
+                              int32_t no_split, dmrg_trunc* out);
+
+/* ---------------------------------------------------------------------- */
+/* Host utilities (no device needed): the FP64 eigen-solvers the library   */
+/* uses for the Lanczos tridiagonal matrix and the density-matrix blocks.  */
+
+/* All eigenpairs of the symmetric n x n row-major matrix a (host): w[n]
+ * receives the eigenvalues in ascending order, column c of a the
+ * eigenvector of w[c] (Householder tridiagonalisation, implicit QR with
+ * Wilkinson shifts).  DMRG_E_NOCONV if the sweeps do not converge.        */
+dmrg_status dmrg_host_sym_eigen(int32_t n, double* a, double* w);
+
+/* Lowest eigenpair of the symmetric tridiagonal matrix with diagonal
+ * alpha[n] and off-diagonal beta[n-1] (Sturm bisection + inverse
+ * iteration); u[n] normalised, first nonzero component positive.          */
+dmrg_status dmrg_host_tridiag_lowest(int32_t n, const double* alpha, const double* beta,
+                                     double* theta, double* u);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMRG_H */

@@ -256,3 +256,52 @@ def check_quantum_numbers(sb):
                     raise ValueError("block breaks the operator's q shift")
                 if blk.shape != (basis["dim"][r], basis["dim"][c]):
                     raise ValueError("block shape does not match the sectors")
+
+
+# ---------------------------------------------------------------------------
+# Single entries, for sampled checks at sizes where the full product is slow
+# ---------------------------------------------------------------------------
+
+def hpsi_element(sb, psi, i, j, m, n, absolute=False):
+    """Entry (m, n) of block (i, j) of H psi from the definition,
+    sum_k c_k sum_{a', b'} A_k[m, a'] Psi'[a', b'] B_k[n, b'].
+
+    With ``absolute`` every factor is replaced by its absolute value, which
+    gives the scale (|H| |psi|) that rounding errors are measured against.
+    """
+    pairs, _ = target_pairs(sb)
+    where = {(p[0], p[1]): p[2] for p in pairs}
+    dS, dE = sb["S"]["dim"], sb["E"]["dim"]
+    f = np.abs if absolute else (lambda x: x)
+    total = 0.0
+    for t in sb["terms"]:
+        i2, Ablk = _apply_side(_block_map(t["A"]), i)
+        j2, Bblk = _apply_side(_block_map(t["B"]), j)
+        if i2 is None or j2 is None or (i2, j2) not in where:
+            continue
+        o2 = where[(i2, j2)]
+        X = f(psi[o2:o2 + int(dS[i2]) * int(dE[j2])].reshape(int(dS[i2]), int(dE[j2])))
+        a = np.zeros(int(dS[i2]))
+        if Ablk is None:
+            a[m] = 1.0
+        else:
+            a = f(Ablk[m, :])
+        b = np.zeros(int(dE[j2]))
+        if Bblk is None:
+            b[n] = 1.0
+        else:
+            b = f(Bblk[n, :])
+        total += f(t["c"]) * float(a @ X @ b)
+    return total
+
+
+def abs_description(sb):
+    """The description with every coefficient and block entry replaced by its
+    absolute value (so that hpsi of |psi| gives |H| |psi|)."""
+    def op(o):
+        if o is None:
+            return None
+        return dict(delta=o["delta"], blocks=[(r, c, np.abs(b)) for (r, c, b) in o["blocks"]])
+    return dict(S=sb["S"], E=sb["E"], q_target=sb["q_target"],
+                terms=[dict(c=abs(t["c"]), A=op(t["A"]), B=op(t["B"]), group=t.get("group", 0))
+                       for t in sb["terms"]])

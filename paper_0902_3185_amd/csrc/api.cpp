@@ -1,0 +1,706 @@
+// C ABI of libdmrg: contexts, superblocks, the product, its adjoint, the
+// Lanczos ground state and density-matrix truncation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/dmrg.h"
+#include "eigen.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace dmrg;
+
+namespace {
+
+thread_local std::string g_err;
+
+dmrg_status fail(dmrg_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(DMRG_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// Device allocation owned by the library.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, std::max<size_t>(n, 256));
+    if (e == hipSuccess) bytes = std::max<size_t>(n, 256);
+    return e;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Sets the context's device for the duration of a call and restores the old one.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// A plan and its device copy.
+struct Staged {
+  Plan plan;
+  DevBuf tiles, segs, gsrc, gscale, dense64, dense32;
+  bool has32 = false;
+  int max_nseg = 0;
+  std::vector<std::pair<SegDesc, TileDesc>> plain;  // one entry per (block, term)
+};
+
+// Host copy of a superblock's input (needed to build the transposed plan).
+struct OpCopy {
+  int64_t delta = 0;
+  std::vector<int32_t> row, col;
+  std::vector<std::vector<double>> data;
+  std::vector<const double*> ptrs;
+  dmrg_op view{};
+};
+
+}  // namespace
+
+struct dmrg_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // Lanczos workspace (grow-only)
+  DevBuf V, w, partial, small;
+  double* host_small = nullptr;   // pinned, for per-iteration scalars
+  size_t host_small_n = 0;
+};
+
+struct dmrg_sb_s {
+  dmrg_ctx ctx = nullptr;
+  dmrg_prec prec = DMRG_FP64;
+  std::vector<int64_t> qS, qE;
+  std::vector<int32_t> dS, dE;
+  int64_t q_target = 0;
+  std::vector<double> coeff;
+  std::vector<int32_t> group;
+  std::vector<std::unique_ptr<OpCopy>> opA, opB;
+  Staged fwd;
+  std::unique_ptr<Staged> adj;
+  // density-matrix scratch and results
+  DevBuf rho_tiles, rho_segs, rho_out;
+  std::vector<double> tr_lambda;
+  std::vector<int32_t> tr_sec, tr_kps;
+  std::vector<std::vector<double>> tr_W;
+  std::vector<const double*> tr_Wp;
+};
+
+namespace {
+
+dmrg_status upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s) {
+  HIP_TRY(b.ensure(bytes));
+  if (bytes) HIP_TRY(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));
+  return DMRG_OK;
+}
+
+dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
+  const Plan& p = st.plan;
+  hipStream_t s = ctx->stream;
+  dmrg_status r;
+  if ((r = upload(st.tiles, p.tiles.data(), p.tiles.size() * sizeof(TileDesc), s)) != DMRG_OK) return r;
+  if ((r = upload(st.segs, p.segs.data(), p.segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return r;
+  if ((r = upload(st.gsrc, p.gsrc.data(), p.gsrc.size() * sizeof(int32_t), s)) != DMRG_OK) return r;
+  if ((r = upload(st.gscale, p.gscale.data(), p.gscale.size() * sizeof(double), s)) != DMRG_OK) return r;
+  if ((r = upload(st.dense64, p.dense.data(), p.dense.size() * sizeof(double), s)) != DMRG_OK) return r;
+  if (want32) {
+    std::vector<float> f(p.dense.size());
+    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)p.dense[i];
+    if ((r = upload(st.dense32, f.data(), f.size() * sizeof(float), s)) != DMRG_OK) return r;
+    HIP_TRY(hipStreamSynchronize(s));   // the host staging vector dies here
+    st.has32 = true;
+  }
+  st.max_nseg = 0;
+  st.plain.clear();
+  for (size_t q = 0; q < p.pair_s.size(); ++q) {
+    st.max_nseg = std::max(st.max_nseg, p.pair_nseg[q]);
+    TileDesc t{};
+    t.y_off = p.pair_off[q];
+    t.a = p.dS[p.pair_s[q]];
+    t.b = p.dE[p.pair_e[q]];
+    for (int32_t k = 0; k < p.pair_nseg[q]; ++k) st.plain.push_back({p.segs[p.pair_seg0[q] + k], t});
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return DMRG_OK;
+}
+
+int kernel_prec(dmrg_prec p) { return p == DMRG_FP32 ? kPrecF32 : kPrecF64; }
+
+// y = alpha H psi + beta y with a given plan and precision.
+dmrg_status run_product(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
+                        double alpha, double beta) {
+  hipStream_t s = sb->ctx->stream;
+  const Plan& p = st.plan;
+  if (prec == DMRG_FP64_PLAIN) {
+    HIP_TRY(launch_plain(st.plain, p.D, st.dense64.as<double>(), st.gsrc.as<int32_t>(),
+                         st.gscale.as<double>(), psi, y, alpha, beta, s));
+    return DMRG_OK;
+  }
+  if (prec == DMRG_BF16X3) return fail(DMRG_E_UNSUPPORTED, "BF16x3 product not built in this library");
+  const void* dense = st.dense64.p;
+  if (prec == DMRG_FP32) {
+    if (!st.has32) return fail(DMRG_E_ARG, "FP32 operators not staged (use dmrg_sb_set_prec)");
+    dense = st.dense32.p;
+  }
+  HIP_TRY(launch_hpsi(kernel_prec(prec), (int)p.tiles.size(), st.tiles.as<TileDesc>(),
+                      st.segs.as<SegDesc>(), dense, st.gsrc.as<int32_t>(), st.gscale.as<double>(),
+                      psi, y, alpha, beta, s));
+  return DMRG_OK;
+}
+
+dmrg_status need_device(dmrg_sb sb) {
+  if (sb == nullptr) return fail(DMRG_E_ARG, "null superblock");
+  if (sb->ctx == nullptr) return fail(DMRG_E_DEVICE, "superblock was built without a device context");
+  return DMRG_OK;
+}
+
+std::vector<dmrg_term> term_views(dmrg_sb sb) {
+  std::vector<dmrg_term> t(sb->coeff.size());
+  for (size_t k = 0; k < t.size(); ++k) {
+    t[k].c = sb->coeff[k];
+    t[k].group = sb->group[k];
+    t[k].A = sb->opA[k] ? &sb->opA[k]->view : nullptr;
+    t[k].B = sb->opB[k] ? &sb->opB[k]->view : nullptr;
+  }
+  return t;
+}
+
+dmrg_basis basis_view(const std::vector<int64_t>& q, const std::vector<int32_t>& d) {
+  dmrg_basis b;
+  b.nsec = (int32_t)q.size();
+  b.q = q.data();
+  b.dim = d.data();
+  return b;
+}
+
+std::unique_ptr<OpCopy> copy_op(const dmrg_op* op, const dmrg_basis* b) {
+  if (op == nullptr) return nullptr;
+  auto c = std::make_unique<OpCopy>();
+  c->delta = op->delta;
+  for (int32_t k = 0; k < op->nblk; ++k) {
+    c->row.push_back(op->row_sec[k]);
+    c->col.push_back(op->col_sec[k]);
+    const size_t n = (size_t)b->dim[op->row_sec[k]] * b->dim[op->col_sec[k]];
+    c->data.emplace_back(op->blk[k], op->blk[k] + n);
+  }
+  for (auto& d : c->data) c->ptrs.push_back(d.data());
+  c->view.delta = c->delta;
+  c->view.nblk = (int32_t)c->row.size();
+  c->view.row_sec = c->row.data();
+  c->view.col_sec = c->col.data();
+  c->view.blk = c->ptrs.data();
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dmrg_last_error(void) { return g_err.c_str(); }
+
+const char* dmrg_version(void) { return "libdmrg 0.1 (gfx950)"; }
+
+dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx* out) {
+  if (out == nullptr) return fail(DMRG_E_ARG, "null output pointer");
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return fail(DMRG_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= n) return fail(DMRG_E_ARG, "device index out of range");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(DMRG_E_DEVICE, std::string("libdmrg is built for gfx950, device is ") + prop.gcnArchName);
+  auto* c = new dmrg_ctx_s();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return DMRG_OK;
+}
+
+void dmrg_ctx_destroy(dmrg_ctx ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  if (ctx->host_small) (void)hipHostFree(ctx->host_small);
+  delete ctx;
+}
+
+dmrg_status dmrg_ctx_set_stream(dmrg_ctx ctx, void* hip_stream) {
+  if (!ctx) return fail(DMRG_E_ARG, "null context");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_basis* E,
+                                  int64_t q_target, int32_t nterms, const dmrg_term* terms,
+                                  dmrg_prec prec, dmrg_sb* out) {
+  if (out == nullptr) return fail(DMRG_E_ARG, "null output pointer");
+  if (prec < DMRG_FP64 || prec > DMRG_FP64_PLAIN) return fail(DMRG_E_ARG, "unknown precision");
+  if (prec == DMRG_BF16X3) return fail(DMRG_E_UNSUPPORTED, "BF16x3 product not built in this library");
+  auto sb = std::make_unique<dmrg_sb_s>();
+  std::string err;
+  dmrg_status st = build_plan(S, E, q_target, nterms, terms, false, sb->fwd.plan, err);
+  if (st != DMRG_OK) return fail(st, err);
+  sb->ctx = ctx;
+  sb->prec = prec;
+  sb->qS.assign(S->q, S->q + S->nsec);
+  sb->qE.assign(E->q, E->q + E->nsec);
+  sb->dS.assign(S->dim, S->dim + S->nsec);
+  sb->dE.assign(E->dim, E->dim + E->nsec);
+  sb->q_target = q_target;
+  for (int32_t k = 0; k < nterms; ++k) {
+    sb->coeff.push_back(terms[k].c);
+    sb->group.push_back(terms[k].group);
+    sb->opA.push_back(copy_op(terms[k].A, S));
+    sb->opB.push_back(copy_op(terms[k].B, E));
+  }
+  if (ctx) {
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(DMRG_E_DEVICE, "hipSetDevice failed");
+    if ((st = stage(ctx, sb->fwd, prec == DMRG_FP32)) != DMRG_OK) return st;
+  }
+  *out = sb.release();
+  return DMRG_OK;
+}
+
+void dmrg_sb_destroy(dmrg_sb sb) {
+  if (!sb) return;
+  if (sb->ctx) {
+    DeviceGuard g(sb->ctx->device);
+    (void)hipStreamSynchronize(sb->ctx->stream);
+    delete sb;
+  } else {
+    delete sb;
+  }
+}
+
+dmrg_status dmrg_sb_layout(dmrg_sb sb, int64_t* D, int32_t* npairs, const int64_t** off,
+                           const int32_t** s_sec, const int32_t** e_sec) {
+  if (!sb) return fail(DMRG_E_ARG, "null superblock");
+  const Plan& p = sb->fwd.plan;
+  if (D) *D = p.D;
+  if (npairs) *npairs = (int32_t)p.pair_s.size();
+  if (off) *off = p.pair_off.data();
+  if (s_sec) *s_sec = p.pair_s.data();
+  if (e_sec) *e_sec = p.pair_e.data();
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_sb_stats(dmrg_sb sb, double* flops_alg, double* flops_exec, double* bytes_alg,
+                          int32_t* ntiles) {
+  if (!sb) return fail(DMRG_E_ARG, "null superblock");
+  const Plan& p = sb->fwd.plan;
+  const int elem = sb->prec == DMRG_FP32 ? 4 : 8;
+  if (flops_alg) *flops_alg = p.flops_alg;
+  if (flops_exec) *flops_exec = p.flops_exec;
+  if (bytes_alg) *bytes_alg = plan_bytes_alg(p, elem);
+  if (ntiles) *ntiles = (int32_t)p.tiles.size();
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_sb_set_coeffs(dmrg_sb sb, const double* c_h) {
+  if (!sb || !c_h) return fail(DMRG_E_ARG, "null argument");
+  for (size_t k = 0; k < sb->coeff.size(); ++k) sb->coeff[k] = c_h[k];
+  Staged* plans[2] = {&sb->fwd, sb->adj.get()};
+  for (Staged* st : plans) {
+    if (!st) continue;
+    for (auto& s : st->plan.segs) s.c = c_h[s.term];
+    for (auto& w : st->plain) w.first.c = c_h[w.first.term];
+    if (sb->ctx) {
+      DeviceGuard g(sb->ctx->device);
+      HIP_TRY(hipMemcpyAsync(st->segs.p, st->plan.segs.data(), st->plan.segs.size() * sizeof(SegDesc),
+                             hipMemcpyHostToDevice, sb->ctx->stream));
+      HIP_TRY(hipStreamSynchronize(sb->ctx->stream));
+    }
+  }
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec) {
+  if (!sb) return fail(DMRG_E_ARG, "null superblock");
+  if (prec < DMRG_FP64 || prec > DMRG_FP64_PLAIN) return fail(DMRG_E_ARG, "unknown precision");
+  if (prec == DMRG_BF16X3) return fail(DMRG_E_UNSUPPORTED, "BF16x3 product not built in this library");
+  if (prec == DMRG_FP32 && sb->ctx && !sb->fwd.has32) {
+    DeviceGuard g(sb->ctx->device);
+    std::vector<float> f(sb->fwd.plan.dense.size());
+    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)sb->fwd.plan.dense[i];
+    dmrg_status r = upload(sb->fwd.dense32, f.data(), f.size() * sizeof(float), sb->ctx->stream);
+    if (r != DMRG_OK) return r;
+    HIP_TRY(hipStreamSynchronize(sb->ctx->stream));
+    sb->fwd.has32 = true;
+  }
+  sb->prec = prec;
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_hpsi(dmrg_sb sb, const double* psi_d, double* y_d, double alpha, double beta) {
+  dmrg_status st = need_device(sb);
+  if (st != DMRG_OK) return st;
+  if (!psi_d || !y_d) return fail(DMRG_E_ARG, "null vector");
+  if (psi_d == y_d) return fail(DMRG_E_ARG, "psi and y must not overlap");
+  DeviceGuard g(sb->ctx->device);
+  return run_product(sb, sb->fwd, sb->prec, psi_d, y_d, alpha, beta);
+}
+
+dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d, double* gpsi_d,
+                              double* gc_h) {
+  dmrg_status st = need_device(sb);
+  if (st != DMRG_OK) return st;
+  if (!psi_d || !g_d) return fail(DMRG_E_ARG, "null vector");
+  DeviceGuard guard(sb->ctx->device);
+  hipStream_t s = sb->ctx->stream;
+  if (gpsi_d) {
+    if (gpsi_d == g_d) return fail(DMRG_E_ARG, "g and grad_psi must not overlap");
+    if (!sb->adj) {
+      auto adj = std::make_unique<Staged>();
+      std::string err;
+      dmrg_basis bS = basis_view(sb->qS, sb->dS), bE = basis_view(sb->qE, sb->dE);
+      std::vector<dmrg_term> tv = term_views(sb);
+      st = build_plan(&bS, &bE, sb->q_target, (int32_t)tv.size(), tv.data(), true, adj->plan, err);
+      if (st != DMRG_OK) return fail(st, "adjoint plan: " + err);
+      if ((st = stage(sb->ctx, *adj, sb->fwd.has32)) != DMRG_OK) return st;
+      sb->adj = std::move(adj);
+    }
+    dmrg_prec p = sb->prec;
+    if (p == DMRG_FP32 && !sb->adj->has32) p = DMRG_FP64;
+    if ((st = run_product(sb, *sb->adj, p, g_d, gpsi_d, 1.0, 0.0)) != DMRG_OK) return st;
+  }
+  if (gc_h) {
+    Staged& f = sb->fwd;
+    const int nt = (int)f.plan.tiles.size();
+    const int stride = std::max(1, f.max_nseg);
+    DevBuf part;
+    HIP_TRY(part.ensure((size_t)nt * stride * sizeof(double)));
+    const bool use32 = sb->prec == DMRG_FP32 && f.has32;
+    HIP_TRY(launch_term_dots(use32 ? kPrecF32 : kPrecF64, nt, f.tiles.as<TileDesc>(),
+                             f.segs.as<SegDesc>(), use32 ? f.dense32.p : f.dense64.p,
+                             f.gsrc.as<int32_t>(), f.gscale.as<double>(), psi_d, g_d,
+                             part.as<double>(), stride, s));
+    std::vector<double> h((size_t)nt * stride);
+    HIP_TRY(hipMemcpyAsync(h.data(), part.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<double> acc(sb->coeff.size(), 0.0);
+    for (int t = 0; t < nt; ++t) {
+      const TileDesc& td = f.plan.tiles[t];
+      for (int q = 0; q < td.nseg; ++q) acc[f.plan.segs[td.seg0 + q].term] += h[(size_t)t * stride + q];
+    }
+    for (size_t k = 0; k < acc.size(); ++k) gc_h[k] = acc[k];
+  }
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_iter, double tol,
+                                double* E0_h, double* psi_d, int32_t* iters_h, double* resid_h) {
+  dmrg_status st = need_device(sb);
+  if (st != DMRG_OK) return st;
+  if (!psi0_d || !psi_d || !E0_h) return fail(DMRG_E_ARG, "null argument");
+  if (max_iter < 1 || !(tol >= 0.0)) return fail(DMRG_E_ARG, "max_iter must be >= 1 and tol >= 0");
+  dmrg_ctx ctx = sb->ctx;
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = ctx->stream;
+  const int64_t D = sb->fwd.plan.D;
+  const bool reduced = sb->prec == DMRG_FP32 || sb->prec == DMRG_BF16X3;
+  const int per_cycle = reduced ? 100 : std::min<int>(max_iter, 400);
+  const int nvec = per_cycle + 1;
+  const int nblk = vec_blocks(D);
+  HIP_TRY(ctx->V.ensure((size_t)nvec * D * sizeof(double)));
+  HIP_TRY(ctx->w.ensure((size_t)D * sizeof(double)));
+  HIP_TRY(ctx->partial.ensure((size_t)std::max(nvec, 1) * nblk * sizeof(double)));
+  // small: h1[nvec], h2[nvec], u[nvec], nrm2[1], ab[2*nvec]
+  const size_t nsmall = (size_t)5 * nvec + 8;
+  HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
+  if (ctx->host_small_n < nsmall) {
+    if (ctx->host_small) (void)hipHostFree(ctx->host_small);
+    ctx->host_small = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&ctx->host_small, nsmall * sizeof(double), hipHostMallocDefault));
+    ctx->host_small_n = nsmall;
+  }
+  double* V = ctx->V.as<double>();
+  double* w = ctx->w.as<double>();
+  double* part = ctx->partial.as<double>();
+  double* h1 = ctx->small.as<double>();
+  double* h2 = h1 + nvec;
+  double* ud = h2 + nvec;
+  double* nrm2 = ud + nvec;
+  double* ab = nrm2 + 8;
+  double* hs = ctx->host_small;
+
+  // v0 = psi0 / |psi0|
+  HIP_TRY(launch_multi_dot(psi0_d, 0, 1, psi0_d, D, part, nrm2, s));
+  HIP_TRY(launch_normalise(V, psi0_d, nrm2, D, s));
+  int total = 0;
+  double E = 0.0, res = INFINITY;
+  bool converged = false;
+  std::vector<double> alphas, betas, u;
+  while (!converged && total < max_iter) {
+    alphas.clear();
+    betas.clear();
+    double beta0 = 0.0;
+    int j = 0;
+    for (;; ++j) {
+      double* vj = V + (size_t)j * D;
+      const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
+      if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
+      ++total;
+      HIP_TRY(launch_multi_dot(V, D, j + 1, w, D, part, h1, s));
+      HIP_TRY(launch_multi_axpy_norm(w, V, D, j + 1, h1, D, part, nrm2, s));
+      HIP_TRY(launch_multi_dot(V, D, j + 1, w, D, part, h2, s));
+      HIP_TRY(launch_multi_axpy_norm(w, V, D, j + 1, h2, D, part, nrm2, s));
+      HIP_TRY(launch_record(h1, h2, j, nrm2, ab, 0, s));
+      if (j + 1 < nvec) HIP_TRY(launch_normalise(V + (size_t)(j + 1) * D, w, nrm2, D, s));
+      HIP_TRY(hipMemcpyAsync(hs, ab, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      const double a = hs[0], b = hs[1];
+      alphas.push_back(a);
+      if (j == 0) {
+        E = a;
+        res = b;
+        beta0 = b;
+        if (b <= tol) {
+          converged = true;
+          break;
+        }
+      }
+      double theta;
+      u.assign(j + 1, 0.0);
+      tridiag_lowest(j + 1, alphas.data(), betas.data(), &theta, u.data());
+      const double est = b * std::fabs(u[j]);
+      const double ctol = reduced ? std::max(tol, 1e-4 * beta0) : tol;
+      const bool breakdown = b <= 1e-13 * std::max(1.0, std::fabs(theta));
+      if (j > 0 && (est <= ctol || breakdown)) break;
+      if (j + 1 >= nvec - 1 || total >= max_iter) break;
+      betas.push_back(b);
+    }
+    if (converged) break;
+    // Ritz vector of the cycle -> start of the next one
+    const int nv = (int)u.size();
+    HIP_TRY(hipMemcpyAsync(ud, u.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_combine(w, V, D, nv, ud, D, s));
+    HIP_TRY(launch_multi_dot(w, 0, 1, w, D, part, nrm2, s));
+    HIP_TRY(launch_normalise(V, w, nrm2, D, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  HIP_TRY(hipMemcpyAsync(psi_d, V, (size_t)D * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *E0_h = E;
+  if (iters_h) *iters_h = total;
+  if (resid_h) *resid_h = res;
+  if (!converged) {
+    std::ostringstream os;
+    os << "Lanczos did not reach residual " << tol << " in " << max_iter << " products (last " << res << ")";
+    return fail(DMRG_E_NOCONV, os.str());
+  }
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int32_t m,
+                              int32_t no_split, dmrg_trunc* out) {
+  dmrg_status st = need_device(sb);
+  if (st != DMRG_OK) return st;
+  if (!psi_d || !out) return fail(DMRG_E_ARG, "null argument");
+  if (side != 0 && side != 1) return fail(DMRG_E_ARG, "side must be 0 (S') or 1 (E')");
+  if (m < 0) return fail(DMRG_E_ARG, "m must be >= 0");
+  DeviceGuard guard(sb->ctx->device);
+  hipStream_t s = sb->ctx->stream;
+  const Plan& p = sb->fwd.plan;
+  const std::vector<int64_t>& qs = side == 0 ? sb->qS : sb->qE;
+  const std::vector<int32_t>& ds = side == 0 ? sb->dS : sb->dE;
+  const int nsec = (int)qs.size();
+  // rho blocks of the sectors that appear in a target pair, on the matrix cores
+  std::vector<int64_t> rho_off(nsec, -1);
+  std::vector<TileDesc> tiles;
+  std::vector<SegDesc> segs;
+  int64_t total = 0;
+  for (size_t q = 0; q < p.pair_s.size(); ++q) {
+    const int32_t a = p.dS[p.pair_s[q]], b = p.dE[p.pair_e[q]];
+    const int32_t sec = side == 0 ? p.pair_s[q] : p.pair_e[q];
+    const int32_t n = side == 0 ? a : b;
+    rho_off[sec] = total;
+    SegDesc sg{};
+    sg.c = 1.0;
+    sg.term = 0;
+    sg.psi_off = p.pair_off[q];
+    sg.psi_ld = b;
+    sg.psi_rows = a;
+    sg.op_off = p.pair_off[q];
+    sg.op_ld = b;
+    sg.gA = -1;
+    sg.gB = -1;
+    if (side == 0) {          // rho[m][n] = sum_k Psi[m][k] Psi[n][k]
+      sg.kind = SEG_MK;
+      sg.K = b;
+    } else {                  // rho[m][n] = sum_k Psi[k][m] Psi[k][n]
+      sg.kind = SEG_KN;
+      sg.K = a;
+    }
+    const int32_t s0 = (int32_t)segs.size();
+    segs.push_back(sg);
+    for (int32_t m0 = 0; m0 < n; m0 += kTile)
+      for (int32_t n0 = 0; n0 < n; n0 += kTile) {
+        TileDesc t{};
+        t.y_off = total;
+        t.a = n;
+        t.b = n;
+        t.m0 = m0;
+        t.n0 = n0;
+        t.seg0 = s0;
+        t.nseg = 1;
+        tiles.push_back(t);
+      }
+    total += (int64_t)n * n;
+  }
+  if ((st = upload(sb->rho_tiles, tiles.data(), tiles.size() * sizeof(TileDesc), s)) != DMRG_OK) return st;
+  if ((st = upload(sb->rho_segs, segs.data(), segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return st;
+  HIP_TRY(sb->rho_out.ensure((size_t)std::max<int64_t>(total, 1) * sizeof(double)));
+  HIP_TRY(launch_hpsi(kPrecF64, (int)tiles.size(), sb->rho_tiles.as<TileDesc>(),
+                      sb->rho_segs.as<SegDesc>(), psi_d, nullptr, nullptr, psi_d,
+                      sb->rho_out.as<double>(), 1.0, 0.0, s));
+  std::vector<double> rho((size_t)total);
+  HIP_TRY(hipMemcpyAsync(rho.data(), sb->rho_out.p, rho.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+
+  // per-sector FP64 eigen; zero blocks for sectors without a target pair
+  struct Ent {
+    double lam;      // clamped
+    double raw;
+    int64_t q;
+    int32_t idx;     // position in the sector's decreasing order
+    int32_t sec;
+  };
+  std::vector<Ent> ents;
+  std::vector<std::vector<double>> vecs(nsec);
+  const double floor_ = 1e-13, rel_tie = 1e-6;
+  for (int sec = 0; sec < nsec; ++sec) {
+    const int n = ds[sec];
+    std::vector<double> A((size_t)n * n, 0.0), wv(n, 0.0);
+    if (rho_off[sec] >= 0) std::copy(rho.begin() + rho_off[sec], rho.begin() + rho_off[sec] + (size_t)n * n, A.begin());
+    for (int i = 0; i < n; ++i)   // symmetrise the computed block
+      for (int j = i + 1; j < n; ++j) {
+        const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+        A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
+      }
+    if (!sym_eigen(n, A.data(), wv.data())) return fail(DMRG_E_NOCONV, "density-matrix eigen-solve did not converge");
+    // decreasing order within the sector
+    std::vector<double> V((size_t)n * n);
+    for (int c = 0; c < n; ++c) {
+      const int src = n - 1 - c;
+      for (int r = 0; r < n; ++r) V[(size_t)r * n + c] = A[(size_t)r * n + src];
+      const double raw = wv[src];
+      ents.push_back({raw >= floor_ ? raw : 0.0, raw, qs[sec], c, sec});
+    }
+    vecs[sec].swap(V);
+  }
+  const int ntot = (int)ents.size();
+  std::vector<int> ord(ntot);
+  for (int i = 0; i < ntot; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    if (ents[x].lam != ents[y].lam) return ents[x].lam > ents[y].lam;
+    if (ents[x].q != ents[y].q) return ents[x].q < ents[y].q;
+    return ents[x].idx < ents[y].idx;
+  });
+  std::vector<int> cluster(ntot, 0);
+  for (int i = 1; i < ntot; ++i) {
+    const double a = ents[ord[i - 1]].lam, b = ents[ord[i]].lam;
+    const bool tied = (a == 0.0 && b == 0.0) || std::fabs(a - b) <= rel_tie * std::max(a, b);
+    cluster[i] = cluster[i - 1] + (tied ? 0 : 1);
+  }
+  for (int i = 0; i < ntot;) {
+    int e = i;
+    while (e < ntot && cluster[e] == cluster[i]) ++e;
+    std::stable_sort(ord.begin() + i, ord.begin() + e, [&](int x, int y) {
+      if (ents[x].q != ents[y].q) return ents[x].q < ents[y].q;
+      return ents[x].idx < ents[y].idx;
+    });
+    i = e;
+  }
+  int keep = m >= ntot ? ntot : m;
+  int straddle = 0;
+  if (keep < ntot && keep > 0) {
+    straddle = cluster[keep - 1] == cluster[keep] && ents[ord[keep]].lam > 0.0;
+    if (no_split && straddle)
+      while (keep < ntot && cluster[keep] == cluster[keep - 1]) ++keep;
+  }
+  double eps = 0.0;
+  for (int i = keep; i < ntot; ++i) eps += ents[ord[i]].lam;
+  sb->tr_lambda.clear();
+  sb->tr_sec.clear();
+  std::vector<std::vector<int>> per(nsec);
+  for (int i = 0; i < keep; ++i) {
+    const Ent& e = ents[ord[i]];
+    sb->tr_lambda.push_back(e.raw);
+    sb->tr_sec.push_back(e.sec);
+    per[e.sec].push_back(e.idx);
+  }
+  sb->tr_kps.assign(nsec, 0);
+  sb->tr_W.assign(nsec, std::vector<double>());
+  sb->tr_Wp.assign(nsec, nullptr);
+  for (int sec = 0; sec < nsec; ++sec) {
+    std::vector<int>& idx = per[sec];
+    std::sort(idx.begin(), idx.end());
+    const int n = ds[sec], k = (int)idx.size();
+    sb->tr_kps[sec] = k;
+    if (k == 0) continue;
+    std::vector<double>& W = sb->tr_W[sec];
+    W.assign((size_t)n * k, 0.0);
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < k; ++c) W[(size_t)r * k + c] = vecs[sec][(size_t)r * n + idx[c]];
+    sb->tr_Wp[sec] = W.data();
+  }
+  out->trunc_err = eps;
+  out->kept = keep;
+  out->straddle = straddle;
+  out->lambda = sb->tr_lambda.data();
+  out->lambda_sec = sb->tr_sec.data();
+  out->nsec = nsec;
+  out->kept_per_sec = sb->tr_kps.data();
+  out->W = sb->tr_Wp.data();
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_host_sym_eigen(int32_t n, double* a, double* w) {
+  if (n < 0 || (n > 0 && (!a || !w))) return fail(DMRG_E_ARG, "bad argument");
+  if (!sym_eigen(n, a, w)) return fail(DMRG_E_NOCONV, "QR sweeps did not converge");
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_host_tridiag_lowest(int32_t n, const double* alpha, const double* beta,
+                                     double* theta, double* u) {
+  if (n < 1 || !alpha || !theta || !u || (n > 1 && !beta)) return fail(DMRG_E_ARG, "bad argument");
+  tridiag_lowest(n, alpha, beta, theta, u);
+  return DMRG_OK;
+}
+
+}  // extern "C"

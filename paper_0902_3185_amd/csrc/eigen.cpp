@@ -1,0 +1,229 @@
+// Host FP64 eigen-solvers for the two small eigenproblems of the method:
+//
+// * the Lanczos tridiagonal matrix (Sec. 3.3): its lowest eigenvalue by
+//   Sturm-sequence bisection and the matching eigenvector by inverse
+//   iteration with a pivoted tridiagonal solve;
+// * the per-sector density-matrix blocks (Eqs. (2)-(3)): all eigenpairs by
+//   Householder reduction to tridiagonal form followed by implicitly shifted
+//   QR sweeps with Wilkinson shifts (Golub & Van Loan, Matrix Computations,
+//   Sec. 8.3), accumulating the transformations.
+#include "eigen.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <numeric>
+#include <vector>
+
+namespace dmrg {
+
+namespace {
+
+// Number of eigenvalues of the tridiagonal (a, b) below x (Sturm count).
+int sturm_count(int n, const double* a, const double* b, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  const double tiny = 1e-300;
+  for (int i = 0; i < n; ++i) {
+    const double off = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+    q = (a[i] - x) - (i > 0 ? off / q : 0.0);
+    if (q == 0.0) q = -tiny;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Solve (T - shift I) x = rhs for tridiagonal T by Gaussian elimination with
+// partial pivoting (the fill-in is one extra superdiagonal).  rhs overwritten.
+void tridiag_solve(int n, const double* a, const double* b, double shift, double* rhs) {
+  // row i: sb[i] at column i-1, dg[i] at i, sp[i] at i+1, sp2[i] at i+2 (fill-in)
+  std::vector<double> dg(n), sp(n, 0.0), sp2(n, 0.0), sb(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    dg[i] = a[i] - shift;
+    if (i + 1 < n) sp[i] = b[i];
+    if (i > 0) sb[i] = b[i - 1];
+  }
+  const double eps = std::numeric_limits<double>::epsilon();
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = std::max(scale, std::fabs(dg[i]) + std::fabs(sp[i]) + std::fabs(sb[i]));
+  if (scale == 0.0) scale = 1.0;
+  for (int i = 0; i + 1 < n; ++i) {
+    // rows i and i+1; row i+1 has sb[i+1] at column i
+    if (std::fabs(sb[i + 1]) > std::fabs(dg[i])) {
+      // swap rows i and i+1 (row i+1: [sb, dg, sp] at columns i, i+1, i+2)
+      std::swap(dg[i], sb[i + 1]);
+      std::swap(sp[i], dg[i + 1]);
+      std::swap(sp2[i], sp[i + 1]);
+      std::swap(rhs[i], rhs[i + 1]);
+    }
+    if (dg[i] == 0.0) dg[i] = eps * scale;
+    const double f = sb[i + 1] / dg[i];
+    sb[i + 1] = 0.0;
+    dg[i + 1] -= f * sp[i];
+    sp[i + 1] -= f * sp2[i];
+    rhs[i + 1] -= f * rhs[i];
+  }
+  if (dg[n - 1] == 0.0) dg[n - 1] = eps * scale;
+  for (int i = n - 1; i >= 0; --i) {
+    double s = rhs[i];
+    if (i + 1 < n) s -= sp[i] * rhs[i + 1];
+    if (i + 2 < n) s -= sp2[i] * rhs[i + 2];
+    rhs[i] = s / dg[i];
+  }
+}
+
+}  // namespace
+
+void tridiag_lowest(int n, const double* a, const double* b, double* theta, double* u) {
+  if (n == 1) {
+    *theta = a[0];
+    u[0] = 1.0;
+    return;
+  }
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  const double eps = std::numeric_limits<double>::epsilon();
+  const double scale = std::max(std::fabs(lo), std::fabs(hi));
+  for (int it = 0; it < 200 && hi - lo > 2.0 * eps * std::max(scale, 1e-300); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(n, a, b, mid) >= 1)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  *theta = 0.5 * (lo + hi);
+  // inverse iteration
+  std::vector<double> x(n);
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.001 * (double)((i * 7919) % 101) / 101.0;
+  for (int it = 0; it < 3; ++it) {
+    tridiag_solve(n, a, b, *theta, x.data());
+    double nn = 0.0;
+    for (double v : x) nn += v * v;
+    nn = std::sqrt(nn);
+    if (!(nn > 0.0) || !std::isfinite(nn)) break;
+    for (double& v : x) v /= nn;
+  }
+  // fixed sign: first nonzero component positive
+  double sgn = 1.0;
+  for (int i = 0; i < n; ++i)
+    if (std::fabs(x[i]) > 1e-300) {
+      sgn = x[i] > 0 ? 1.0 : -1.0;
+      break;
+    }
+  for (int i = 0; i < n; ++i) u[i] = sgn * x[i];
+}
+
+bool sym_eigen(int n, double* A, double* w) {
+  if (n <= 0) return true;
+  std::vector<double> Q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  std::vector<double> v(n), p(n), ww(n);
+  // Householder reduction: column k below the subdiagonal is annihilated.
+  for (int k = 0; k + 2 < n; ++k) {
+    double sigma = 0.0;
+    for (int i = k + 2; i < n; ++i) sigma += A[(size_t)i * n + k] * A[(size_t)i * n + k];
+    if (sigma == 0.0) continue;
+    const double x0 = A[(size_t)(k + 1) * n + k];
+    const double norm = std::sqrt(x0 * x0 + sigma);
+    const double alpha = x0 <= 0.0 ? norm : -norm;
+    std::fill(v.begin(), v.end(), 0.0);
+    v[k + 1] = x0 - alpha;
+    for (int i = k + 2; i < n; ++i) v[i] = A[(size_t)i * n + k];
+    const double vtv = v[k + 1] * v[k + 1] + sigma;
+    const double beta = 2.0 / vtv;
+    // p = beta * A v on the trailing block
+    double vtp = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += A[(size_t)i * n + j] * v[j];
+      p[i] = beta * s;
+      vtp += v[i] * p[i];
+    }
+    const double K = 0.5 * beta * vtp;
+    for (int i = k + 1; i < n; ++i) ww[i] = p[i] - K * v[i];
+    for (int i = k + 1; i < n; ++i)
+      for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= v[i] * ww[j] + ww[i] * v[j];
+    A[(size_t)(k + 1) * n + k] = alpha;
+    A[(size_t)k * n + (k + 1)] = alpha;
+    for (int i = k + 2; i < n; ++i) {
+      A[(size_t)i * n + k] = 0.0;
+      A[(size_t)k * n + i] = 0.0;
+    }
+    for (int r = 0; r < n; ++r) {
+      double s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += Q[(size_t)r * n + j] * v[j];
+      s *= beta;
+      for (int j = k + 1; j < n; ++j) Q[(size_t)r * n + j] -= s * v[j];
+    }
+  }
+  std::vector<double> d(n), e(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];
+  // Implicit symmetric QR with Wilkinson shifts; Q accumulates the rotations.
+  const double eps = std::numeric_limits<double>::epsilon();
+  int hi = n - 1;
+  long iters = 0;
+  const long cap = 60L * n + 100;
+  while (hi > 0) {
+    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi])) || e[hi - 1] == 0.0) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    if (lo > 0) e[lo - 1] = 0.0;
+    if (++iters > cap) return false;
+    const double aa = d[hi - 1], bb = e[hi - 1], cc = d[hi];
+    const double del = 0.5 * (aa - cc);
+    const double den = del + (del >= 0.0 ? 1.0 : -1.0) * std::hypot(del, bb);
+    const double mu = den != 0.0 ? cc - bb * bb / den : cc - std::fabs(bb);
+    double x = d[lo] - mu, z = e[lo], bulge = 0.0;
+    for (int k = lo; k < hi; ++k) {
+      if (k > lo) {
+        x = e[k - 1];
+        z = bulge;
+      }
+      const double r = std::hypot(x, z);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) {
+        c = x / r;
+        s = -z / r;
+      }
+      if (k > lo) e[k - 1] = r;
+      const double a0 = d[k], b0 = e[k], d1 = d[k + 1];
+      // M' = R^T M R with R = [[c, s], [-s, c]]
+      const double m00 = a0 * c - b0 * s, m01 = a0 * s + b0 * c;
+      const double m10 = b0 * c - d1 * s, m11 = b0 * s + d1 * c;
+      d[k] = c * m00 - s * m10;
+      e[k] = c * m01 - s * m11;
+      d[k + 1] = s * m01 + c * m11;
+      if (k + 1 < hi) {
+        bulge = -s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+      }
+      for (int row = 0; row < n; ++row) {
+        double* qr = &Q[(size_t)row * n];
+        const double zk = qr[k], zk1 = qr[k + 1];
+        qr[k] = c * zk - s * zk1;
+        qr[k + 1] = s * zk + c * zk1;
+      }
+    }
+  }
+  // sort ascending; eigenvectors as columns of A
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
+  for (int c = 0; c < n; ++c) {
+    w[c] = d[idx[c]];
+    for (int r = 0; r < n; ++r) A[(size_t)r * n + c] = Q[(size_t)r * n + idx[c]];
+  }
+  return true;
+}
+
+}  // namespace dmrg

@@ -1,0 +1,429 @@
+// Superblock product kernels for gfx950 (CDNA4).
+//
+// One workgroup of 4 wave64s owns one 32 x 32 output tile of one target
+// block Y_q and reduces every term that writes it (Y_q += c A Psi_q' B^T;
+// paper Sec. 3.3, blocking by effective symmetry).  The dense products run on
+// the matrix cores; the four waves split the contraction chunks of all of the
+// tile's terms and their partial tiles are summed in LDS in a fixed order, so
+// the result does not depend on scheduling.  Terms with identity or gather
+// operators on both sides are elementwise and are added in FP64 afterwards.
+// No atomics are used on y.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace dmrg {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Per-precision contraction of one segment's chunks into a wave's 32x32 tile.
+//
+// SEG_KN: Y[m][n] += c * sum_k A[m][k] * B[k][n], A stored k-major
+//         (At[k*lda + m]), B[k][n] = sB[n] * Psi'[k][srcB[n]].
+//         Lanes of one contraction index read consecutive m / n: coalesced.
+// SEG_MK: Y[m][n] += c * sum_k A[m][k] * Bop[n][k], A[m][k] = sA[m] *
+//         Psi'[srcA[m]][k], Bop row-major.  Each lane walks a row along k.
+// ---------------------------------------------------------------------------
+
+struct GatherLane {
+  int32_t src;
+  double s;
+  bool ok;
+};
+
+__device__ inline GatherLane gather_at(const int32_t* gsrc, const double* gscale, int32_t g,
+                                       int32_t idx, int32_t limit) {
+  GatherLane r;
+  r.ok = idx < limit;
+  r.src = idx;
+  r.s = 1.0;
+  if (r.ok && g >= 0) {
+    r.src = gsrc[g + idx];
+    r.s = gscale[g + idx];
+    r.ok = r.src >= 0;
+  }
+  return r;
+}
+
+// FP32 matrix cores: v_mfma_f32_32x32x2f32.  A[i][k] from lane i + 32k,
+// B[k][j] from lane j + 32k; D[i][j] in lane j + 32*((i/4)%2), register
+// (i%4) + 4*(i/8).
+struct CfgF32 {
+  using op_t = float;
+  struct Acc {
+    f32x16 d;
+  };
+  __device__ static void zero(Acc& a) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a.d[r] = 0.f;
+  }
+  __device__ static void seg(Acc& acc, const SegDesc& sg, const TileDesc& t, int ch0, int chs,
+                             const op_t* dense, const int32_t* gsrc, const double* gscale,
+                             const double* psi, int lane) {
+    const int i = lane & 31, kh = lane >> 5;
+    const double* P = psi + sg.psi_off;
+    const int64_t ldp = sg.psi_ld;
+    const int nch = (sg.K + kChunk - 1) / kChunk;
+    if (sg.kind == SEG_KN) {
+      const op_t* At = dense + sg.op_off;
+      const int64_t lda = sg.op_ld;
+      const int m = t.m0 + i;
+      const bool mok = m < t.a;
+      GatherLane gb = gather_at(gsrc, gscale, sg.gB, t.n0 + i, t.b);
+      const float cs = (float)sg.c, sb = (float)gb.s;
+      for (int ch = ch0; ch < nch; ch += chs) {
+        const int k0 = ch * kChunk;
+        float av[8], bv[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = k0 + 2 * s + kh;
+          const bool kok = k < sg.K;
+          av[s] = (mok && kok) ? cs * At[k * lda + m] : 0.f;
+          bv[s] = (gb.ok && kok) ? sb * (float)P[k * ldp + gb.src] : 0.f;
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc.d = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], bv[s], acc.d, 0, 0, 0);
+      }
+    } else {
+      GatherLane ga = gather_at(gsrc, gscale, sg.gA, t.m0 + i, t.a);
+      const double* Arow = P + (int64_t)(ga.ok ? ga.src : 0) * ldp;
+      const int n = t.n0 + i;
+      const bool nok = n < t.b;
+      const op_t* Brow = dense + sg.op_off + (int64_t)(nok ? n : 0) * sg.op_ld;
+      const float ca = (float)(sg.c * ga.s);
+      for (int ch = ch0; ch < nch; ch += chs) {
+        const int k0 = ch * kChunk + 8 * kh;
+        float av[8], bv[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = k0 + s;
+          const bool kok = k < sg.K;
+          av[s] = (ga.ok && kok) ? ca * (float)Arow[k] : 0.f;
+          bv[s] = (nok && kok) ? Brow[k] : 0.f;
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc.d = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], bv[s], acc.d, 0, 0, 0);
+      }
+    }
+  }
+  __device__ static double value(const Acc& a, int r) { return (double)a.d[r]; }
+  __device__ static void coords(int lane, int r, int& row, int& col) {
+    row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    col = lane & 31;
+  }
+  static constexpr int kRegs = 16;
+};
+
+// FP64 matrix cores: v_mfma_f64_16x16x4f64 on a 2 x 2 grid of 16x16 blocks.
+// A[i][k] from lane i + 16k, B[k][j] from lane j + 16k; D[i][j] in lane
+// j + 16*(i/4), register i%4.
+struct CfgF64 {
+  using op_t = double;
+  struct Acc {
+    f64x4 d[4];  // block (bi, bj) at d[2*bi + bj]
+  };
+  __device__ static void zero(Acc& a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a.d[b][r] = 0.0;
+  }
+  __device__ static void seg(Acc& acc, const SegDesc& sg, const TileDesc& t, int ch0, int chs,
+                             const op_t* dense, const int32_t* gsrc, const double* gscale,
+                             const double* psi, int lane) {
+    const int i = lane & 15, kq = lane >> 4;
+    const double* P = psi + sg.psi_off;
+    const int64_t ldp = sg.psi_ld;
+    const int nch = (sg.K + kChunk - 1) / kChunk;
+    if (sg.kind == SEG_KN) {
+      const op_t* At = dense + sg.op_off;
+      const int64_t lda = sg.op_ld;
+      const int m0 = t.m0 + i, m1 = t.m0 + 16 + i;
+      const bool mok0 = m0 < t.a, mok1 = m1 < t.a;
+      GatherLane g0 = gather_at(gsrc, gscale, sg.gB, t.n0 + i, t.b);
+      GatherLane g1 = gather_at(gsrc, gscale, sg.gB, t.n0 + 16 + i, t.b);
+      const double c = sg.c;
+      for (int ch = ch0; ch < nch; ch += chs) {
+        const int k0 = ch * kChunk;
+        double a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = k0 + 4 * s + kq;
+          const bool kok = k < sg.K;
+          a0[s] = (mok0 && kok) ? c * At[k * lda + m0] : 0.0;
+          a1[s] = (mok1 && kok) ? c * At[k * lda + m1] : 0.0;
+          b0[s] = (g0.ok && kok) ? g0.s * P[k * ldp + g0.src] : 0.0;
+          b1[s] = (g1.ok && kok) ? g1.s * P[k * ldp + g1.src] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          acc.d[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], acc.d[0], 0, 0, 0);
+          acc.d[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b1[s], acc.d[1], 0, 0, 0);
+          acc.d[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b0[s], acc.d[2], 0, 0, 0);
+          acc.d[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], acc.d[3], 0, 0, 0);
+        }
+      }
+    } else {
+      GatherLane ga0 = gather_at(gsrc, gscale, sg.gA, t.m0 + i, t.a);
+      GatherLane ga1 = gather_at(gsrc, gscale, sg.gA, t.m0 + 16 + i, t.a);
+      const double* A0 = P + (int64_t)(ga0.ok ? ga0.src : 0) * ldp;
+      const double* A1 = P + (int64_t)(ga1.ok ? ga1.src : 0) * ldp;
+      const int n0 = t.n0 + i, n1 = t.n0 + 16 + i;
+      const bool nok0 = n0 < t.b, nok1 = n1 < t.b;
+      const op_t* B0 = dense + sg.op_off + (int64_t)(nok0 ? n0 : 0) * sg.op_ld;
+      const op_t* B1 = dense + sg.op_off + (int64_t)(nok1 ? n1 : 0) * sg.op_ld;
+      const double c0 = sg.c * ga0.s, c1 = sg.c * ga1.s;
+      for (int ch = ch0; ch < nch; ch += chs) {
+        const int k0 = ch * kChunk + 4 * kq;
+        double a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = k0 + s;
+          const bool kok = k < sg.K;
+          a0[s] = (ga0.ok && kok) ? c0 * A0[k] : 0.0;
+          a1[s] = (ga1.ok && kok) ? c1 * A1[k] : 0.0;
+          b0[s] = (nok0 && kok) ? B0[k] : 0.0;
+          b1[s] = (nok1 && kok) ? B1[k] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          acc.d[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], acc.d[0], 0, 0, 0);
+          acc.d[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b1[s], acc.d[1], 0, 0, 0);
+          acc.d[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b0[s], acc.d[2], 0, 0, 0);
+          acc.d[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], acc.d[3], 0, 0, 0);
+        }
+      }
+    }
+  }
+  __device__ static double value(const Acc& a, int r) { return a.d[r >> 2][r & 3]; }
+  __device__ static void coords(int lane, int r, int& row, int& col) {
+    const int b = r >> 2, bi = b >> 1, bj = b & 1;
+    row = 16 * bi + 4 * (lane >> 4) + (r & 3);
+    col = 16 * bj + (lane & 15);
+  }
+  static constexpr int kRegs = 16;
+};
+
+// Elementwise term: c * sA[m] * sB[n] * Psi'[srcA[m]][srcB[n]].
+__device__ inline double gg_term(const SegDesc& sg, const TileDesc& t, int m, int n,
+                                 const int32_t* gsrc, const double* gscale, const double* psi) {
+  GatherLane ga = gather_at(gsrc, gscale, sg.gA, m, t.a);
+  GatherLane gb = gather_at(gsrc, gscale, sg.gB, n, t.b);
+  if (!ga.ok || !gb.ok) return 0.0;
+  return sg.c * ga.s * gb.s * psi[sg.psi_off + (int64_t)ga.src * sg.psi_ld + gb.src];
+}
+
+// ---------------------------------------------------------------------------
+// y = alpha * H psi + beta * y, one workgroup per output tile.
+// ---------------------------------------------------------------------------
+template <class Cfg>
+__global__ __launch_bounds__(256) void hpsi_grouped(const TileDesc* __restrict__ tiles,
+                                                    const SegDesc* __restrict__ segs,
+                                                    const typename Cfg::op_t* __restrict__ dense,
+                                                    const int32_t* __restrict__ gsrc,
+                                                    const double* __restrict__ gscale,
+                                                    const double* __restrict__ psi,
+                                                    double* __restrict__ y, double alpha,
+                                                    double beta) {
+  __shared__ double red[4][kTile * kTile];
+  const TileDesc t = tiles[blockIdx.x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  typename Cfg::Acc acc;
+  Cfg::zero(acc);
+  int ctr = 0;  // chunks handed out so far, over all segments of the tile
+  for (int s = 0; s < t.nseg; ++s) {
+    const SegDesc sg = segs[t.seg0 + s];
+    if (sg.kind == SEG_GG) continue;
+    const int nch = (sg.K + kChunk - 1) / kChunk;
+    const int first = (wave - (ctr & 3) + 4) & 3;
+    Cfg::seg(acc, sg, t, first, 4, dense, gsrc, gscale, psi, lane);
+    ctr += nch;
+  }
+#pragma unroll
+  for (int r = 0; r < Cfg::kRegs; ++r) {
+    int row, col;
+    Cfg::coords(lane, r, row, col);
+    red[wave][row * kTile + col] = Cfg::value(acc, r);
+  }
+  __syncthreads();
+  const int row = threadIdx.x >> 3, c4 = (threadIdx.x & 7) * 4;
+  const int m = t.m0 + row;
+  double v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = row * kTile + c4 + q;
+    v[q] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+  }
+  for (int s = 0; s < t.nseg; ++s) {
+    const SegDesc sg = segs[t.seg0 + s];
+    if (sg.kind != SEG_GG) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] += gg_term(sg, t, m, t.n0 + c4 + q, gsrc, gscale, psi);
+  }
+  if (m < t.a) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = t.n0 + c4 + q;
+      if (n < t.b) {
+        const int64_t idx = t.y_off + (int64_t)m * t.b + n;
+        y[idx] = beta == 0.0 ? alpha * v[q] : alpha * v[q] + beta * y[idx];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-term inner products <G, c_k^{-1} * term_k tile> for grad_c:
+// each wave takes whole segments of the tile; partial[blockIdx.x * stride + s].
+// The segment's own coefficient is divided out by computing with c = 1.
+// ---------------------------------------------------------------------------
+template <class Cfg>
+__global__ __launch_bounds__(256) void term_dots(const TileDesc* __restrict__ tiles,
+                                                 const SegDesc* __restrict__ segs,
+                                                 const typename Cfg::op_t* __restrict__ dense,
+                                                 const int32_t* __restrict__ gsrc,
+                                                 const double* __restrict__ gscale,
+                                                 const double* __restrict__ psi,
+                                                 const double* __restrict__ g,
+                                                 double* __restrict__ partial, int stride) {
+  const TileDesc t = tiles[blockIdx.x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int s = wave; s < t.nseg; s += 4) {
+    SegDesc sg = segs[t.seg0 + s];
+    sg.c = 1.0;
+    double sum = 0.0;
+    if (sg.kind == SEG_GG) {
+      for (int e = lane; e < kTile * kTile; e += 64) {
+        const int m = t.m0 + e / kTile, n = t.n0 + e % kTile;
+        if (m < t.a && n < t.b)
+          sum += g[t.y_off + (int64_t)m * t.b + n] * gg_term(sg, t, m, n, gsrc, gscale, psi);
+      }
+    } else {
+      typename Cfg::Acc acc;
+      Cfg::zero(acc);
+      Cfg::seg(acc, sg, t, 0, 1, dense, gsrc, gscale, psi, lane);
+#pragma unroll
+      for (int r = 0; r < Cfg::kRegs; ++r) {
+        int row, col;
+        Cfg::coords(lane, r, row, col);
+        const int m = t.m0 + row, n = t.n0 + col;
+        if (m < t.a && n < t.b) sum += g[t.y_off + (int64_t)m * t.b + n] * Cfg::value(acc, r);
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (lane == 0) partial[(int64_t)blockIdx.x * stride + s] = sum;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The plain FP64 baseline: y *= beta, then one launch per (term, target
+// block), each a 16 x 16 LDS-tiled FMA product or an elementwise pass.
+// ---------------------------------------------------------------------------
+__global__ void scale_vec(double* __restrict__ y, int64_t n, double beta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = beta == 0.0 ? 0.0 : beta * y[i];
+}
+
+__global__ __launch_bounds__(256) void plain_segment(SegDesc sg, TileDesc t,
+                                                     const double* __restrict__ dense,
+                                                     const int32_t* __restrict__ gsrc,
+                                                     const double* __restrict__ gscale,
+                                                     const double* __restrict__ psi,
+                                                     double* __restrict__ y, double alpha) {
+  __shared__ double As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m = blockIdx.y * 16 + ty, n = blockIdx.x * 16 + tx;
+  const double* P = psi + sg.psi_off;
+  double acc = 0.0;
+  if (sg.kind == SEG_GG) {
+    if (m < t.a && n < t.b) acc = gg_term(sg, t, m, n, gsrc, gscale, psi);
+  } else {
+    for (int k0 = 0; k0 < sg.K; k0 += 16) {
+      // A tile rows m (block rows), columns k; B tile rows k, columns n
+      {
+        const int mm = blockIdx.y * 16 + ty, kk = k0 + tx;
+        double v = 0.0;
+        if (mm < t.a && kk < sg.K) {
+          if (sg.kind == SEG_KN) {
+            v = dense[sg.op_off + (int64_t)kk * sg.op_ld + mm];
+          } else {
+            GatherLane ga = gather_at(gsrc, gscale, sg.gA, mm, t.a);
+            if (ga.ok) v = ga.s * P[(int64_t)ga.src * sg.psi_ld + kk];
+          }
+        }
+        As[ty][tx] = v;
+      }
+      {
+        const int kk = k0 + ty, nn = blockIdx.x * 16 + tx;
+        double v = 0.0;
+        if (nn < t.b && kk < sg.K) {
+          if (sg.kind == SEG_KN) {
+            GatherLane gb = gather_at(gsrc, gscale, sg.gB, nn, t.b);
+            if (gb.ok) v = gb.s * P[(int64_t)kk * sg.psi_ld + gb.src];
+          } else {
+            v = dense[sg.op_off + (int64_t)nn * sg.op_ld + kk];
+          }
+        }
+        Bs[ty][tx] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += As[ty][k] * Bs[k][tx];
+      __syncthreads();
+    }
+    acc *= sg.c;
+  }
+  if (m < t.a && n < t.b) y[t.y_off + (int64_t)m * t.b + n] += alpha * acc;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_hpsi(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,
+                       const void* dense, const int32_t* gsrc, const double* gscale,
+                       const double* psi, double* y, double alpha, double beta,
+                       hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  if (prec == kPrecF32) {
+    hipLaunchKernelGGL(hpsi_grouped<CfgF32>, dim3(ntiles), dim3(256), 0, stream, tiles, segs,
+                       (const float*)dense, gsrc, gscale, psi, y, alpha, beta);
+  } else {
+    hipLaunchKernelGGL(hpsi_grouped<CfgF64>, dim3(ntiles), dim3(256), 0, stream, tiles, segs,
+                       (const double*)dense, gsrc, gscale, psi, y, alpha, beta);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_term_dots(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,
+                            const void* dense, const int32_t* gsrc, const double* gscale,
+                            const double* psi, const double* g, double* partial, int stride,
+                            hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  if (prec == kPrecF32) {
+    hipLaunchKernelGGL(term_dots<CfgF32>, dim3(ntiles), dim3(256), 0, stream, tiles, segs,
+                       (const float*)dense, gsrc, gscale, psi, g, partial, stride);
+  } else {
+    hipLaunchKernelGGL(term_dots<CfgF64>, dim3(ntiles), dim3(256), 0, stream, tiles, segs,
+                       (const double*)dense, gsrc, gscale, psi, g, partial, stride);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plain(const std::vector<std::pair<SegDesc, TileDesc>>& work, int64_t D,
+                        const double* dense, const int32_t* gsrc, const double* gscale,
+                        const double* psi, double* y, double alpha, double beta,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(scale_vec, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, stream, y, D, beta);
+  for (const auto& w : work) {
+    const TileDesc& t = w.second;
+    dim3 grid((t.b + 15) / 16, (t.a + 15) / 16);
+    hipLaunchKernelGGL(plain_segment, grid, dim3(256), 0, stream, w.first, t, dense, gsrc, gscale,
+                       psi, y, alpha);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dmrg

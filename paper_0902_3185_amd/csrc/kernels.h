@@ -1,0 +1,63 @@
+// Kernel launchers shared by the host layer (api.cpp) and the .hip sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <utility>
+#include <vector>
+
+#include "plan.h"
+
+namespace dmrg {
+
+constexpr int kPrecF64 = 0;
+constexpr int kPrecF32 = 1;
+constexpr int kPrecBF16X3 = 2;
+
+// y = alpha * H psi + beta * y with the grouped kernel; `dense` holds the
+// operator pool in the kernel's precision (double for F64, float for F32,
+// interleaved bf16 hi/lo pairs for BF16X3).
+hipError_t launch_hpsi(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,
+                       const void* dense, const int32_t* gsrc, const double* gscale,
+                       const double* psi, double* y, double alpha, double beta,
+                       hipStream_t stream);
+
+// partial[tile * stride + s] = < G tile, segment s of the tile with c = 1 >
+hipError_t launch_term_dots(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,
+                            const void* dense, const int32_t* gsrc, const double* gscale,
+                            const double* psi, const double* g, double* partial, int stride,
+                            hipStream_t stream);
+
+// The straightforward baseline: y *= beta, then one launch per (term, block).
+hipError_t launch_plain(const std::vector<std::pair<SegDesc, TileDesc>>& work, int64_t D,
+                        const double* dense, const int32_t* gsrc, const double* gscale,
+                        const double* psi, double* y, double alpha, double beta,
+                        hipStream_t stream);
+
+// --- FP64 vector kernels for the Lanczos recursion (vec.hip) ---------------
+
+// Number of partial sums the reductions below use for a vector of length n.
+int vec_blocks(int64_t n);
+
+// h[j] = < V_j, w >, j < nv (V_j = V + j*ldv); partial needs nv*vec_blocks(n).
+hipError_t launch_multi_dot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
+                            double* partial, double* h, hipStream_t stream);
+
+// w -= sum_j h[j] V_j, then nrm2[0] = ||w||^2 (partial: vec_blocks(n)).
+hipError_t launch_multi_axpy_norm(double* w, const double* V, int64_t ldv, int nv,
+                                  const double* h, int64_t n, double* partial, double* nrm2,
+                                  hipStream_t stream);
+
+// out = sum_j u[j] V_j  (u in device memory)
+hipError_t launch_combine(double* out, const double* V, int64_t ldv, int nv, const double* u,
+                          int64_t n, hipStream_t stream);
+
+// dst = src * (1 / sqrt(*nrm2))   (the norm read on the device)
+hipError_t launch_normalise(double* dst, const double* src, const double* nrm2, int64_t n,
+                            hipStream_t stream);
+
+// Record alpha_j = h1[j] + h2[j] and beta_j = sqrt(nrm2) into ab[2*it], ab[2*it+1].
+hipError_t launch_record(const double* h1, const double* h2, int j, const double* nrm2,
+                         double* ab, int it, hipStream_t stream);
+
+}  // namespace dmrg

@@ -1,0 +1,313 @@
+// Host plan of one superblock product: sector matching, psi layout, block
+// classification, segment lists and the cost-sorted tile schedule.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <sstream>
+
+namespace dmrg {
+
+namespace {
+
+struct SideBlock {
+  int32_t src_sec = -1;   // source sector (column sector of the block)
+  bool dense = false;
+  bool empty = false;
+  int64_t op_off = -1;    // dense pool offset
+  int32_t op_ld = 0;
+  int32_t g_off = -1;     // gather pool offset
+};
+
+dmrg_status check_basis(const dmrg_basis* b, const char* name, std::string& err) {
+  std::ostringstream os;
+  if (b == nullptr || b->q == nullptr || b->dim == nullptr || b->nsec < 1) {
+    os << name << ": null or empty basis";
+    err = os.str();
+    return DMRG_E_ARG;
+  }
+  for (int32_t s = 0; s < b->nsec; ++s) {
+    if (b->dim[s] < 1) {
+      os << name << ": sector " << s << " has dimension " << b->dim[s];
+      err = os.str();
+      return DMRG_E_SHAPE;
+    }
+    if (s > 0 && b->q[s] <= b->q[s - 1]) {
+      os << name << ": quantum numbers not strictly increasing at sector " << s;
+      err = os.str();
+      return DMRG_E_QN;
+    }
+  }
+  return DMRG_OK;
+}
+
+// Element (r, c) of block `k` of `op`, transposed if requested.
+inline double elem(const dmrg_op* op, int k, int32_t ncols_stored, bool tr, int32_t r,
+                   int32_t c) {
+  return tr ? op->blk[k][(int64_t)c * ncols_stored + r] : op->blk[k][(int64_t)r * ncols_stored + c];
+}
+
+// Validates one side's operator and stages its blocks.  For the A side the
+// dense blocks are stored k-major (column-major of the block) for SEG_KN; for
+// the B side row-major for SEG_MK.
+dmrg_status stage_side(const dmrg_op* op, const dmrg_basis* b, bool a_side, bool tr,
+                       const char* name, int term, std::vector<SideBlock>& by_row, Plan& plan,
+                       std::string& err) {
+  std::ostringstream os;
+  by_row.assign(b->nsec, SideBlock());
+  if (op == nullptr) return DMRG_OK;
+  if (op->nblk < 0 || (op->nblk > 0 && (op->row_sec == nullptr || op->col_sec == nullptr ||
+                                        op->blk == nullptr))) {
+    os << "term " << term << " " << name << ": null block arrays";
+    err = os.str();
+    return DMRG_E_ARG;
+  }
+  std::vector<char> seen(b->nsec, 0);
+  for (int32_t k = 0; k < op->nblk; ++k) {
+    int32_t r0 = op->row_sec[k], c0 = op->col_sec[k];
+    if (r0 < 0 || r0 >= b->nsec || c0 < 0 || c0 >= b->nsec) {
+      os << "term " << term << " " << name << ": block " << k << " sector out of range";
+      err = os.str();
+      return DMRG_E_ARG;
+    }
+    if (op->blk[k] == nullptr) {
+      os << "term " << term << " " << name << ": block " << k << " is null";
+      err = os.str();
+      return DMRG_E_ARG;
+    }
+    if (b->q[r0] - b->q[c0] != op->delta) {
+      os << "term " << term << " " << name << ": block " << k << " maps q=" << b->q[c0]
+         << " to q=" << b->q[r0] << " but the operator's shift is " << op->delta;
+      err = os.str();
+      return DMRG_E_QN;
+    }
+    // logical block after the optional transpose
+    int32_t r = tr ? c0 : r0, c = tr ? r0 : c0;
+    if (seen[r]) {
+      os << "term " << term << " " << name << ": two blocks in row sector " << r;
+      err = os.str();
+      return DMRG_E_QN;
+    }
+    seen[r] = 1;
+    const int32_t rows = b->dim[r], cols = b->dim[c];
+    const int32_t stored_cols = b->dim[c0];
+    bool gather = true, empty = true;
+    for (int32_t i = 0; i < rows && gather; ++i) {
+      int nz = 0;
+      for (int32_t j = 0; j < cols; ++j)
+        if (elem(op, k, stored_cols, tr, i, j) != 0.0) ++nz;
+      if (nz > 1) gather = false;
+      if (nz > 0) empty = false;
+    }
+    SideBlock sb;
+    sb.src_sec = c;
+    if (empty) {
+      sb.empty = true;
+    } else if (gather) {
+      sb.g_off = (int32_t)plan.gsrc.size();
+      for (int32_t i = 0; i < rows; ++i) {
+        int32_t src = -1;
+        double v = 0.0;
+        for (int32_t j = 0; j < cols; ++j) {
+          double x = elem(op, k, stored_cols, tr, i, j);
+          if (x != 0.0) {
+            src = j;
+            v = x;
+          }
+        }
+        plan.gsrc.push_back(src);
+        plan.gscale.push_back(v);
+      }
+    } else {
+      sb.dense = true;
+      sb.op_off = (int64_t)plan.dense.size();
+      if (a_side) {
+        // k-major: element (m, kk) of the block at [kk * rows + m]
+        sb.op_ld = rows;
+        plan.dense.resize(plan.dense.size() + (size_t)rows * cols);
+        double* dst = plan.dense.data() + sb.op_off;
+        for (int32_t i = 0; i < rows; ++i)
+          for (int32_t j = 0; j < cols; ++j) dst[(int64_t)j * rows + i] = elem(op, k, stored_cols, tr, i, j);
+      } else {
+        // row-major: element (n, kk) at [n * cols + kk]
+        sb.op_ld = cols;
+        plan.dense.resize(plan.dense.size() + (size_t)rows * cols);
+        double* dst = plan.dense.data() + sb.op_off;
+        for (int32_t i = 0; i < rows; ++i)
+          for (int32_t j = 0; j < cols; ++j) dst[(int64_t)i * cols + j] = elem(op, k, stored_cols, tr, i, j);
+      }
+    }
+    by_row[r] = sb;
+  }
+  return DMRG_OK;
+}
+
+}  // namespace
+
+dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_target,
+                       int32_t nterms, const dmrg_term* terms, bool transpose, Plan& plan,
+                       std::string& err) {
+  dmrg_status st;
+  if ((st = check_basis(S, "S'", err)) != DMRG_OK) return st;
+  if ((st = check_basis(E, "E'", err)) != DMRG_OK) return st;
+  if (nterms < 0 || (nterms > 0 && terms == nullptr)) {
+    err = "null or negative term list";
+    return DMRG_E_ARG;
+  }
+  plan = Plan();
+  plan.qS.assign(S->q, S->q + S->nsec);
+  plan.qE.assign(E->q, E->q + E->nsec);
+  plan.dS.assign(S->dim, S->dim + S->nsec);
+  plan.dE.assign(E->dim, E->dim + E->nsec);
+  plan.q_target = q_target;
+  plan.nterms = nterms;
+
+  // target pairs: S' sector i with the E' sector of q = q_target - q_i
+  std::vector<int32_t> pair_of_s(S->nsec, -1);
+  int64_t off = 0;
+  for (int32_t i = 0; i < S->nsec; ++i) {
+    const int64_t want = q_target - S->q[i];
+    const int64_t* it = std::lower_bound(E->q, E->q + E->nsec, want);
+    if (it != E->q + E->nsec && *it == want) {
+      pair_of_s[i] = (int32_t)plan.pair_s.size();
+      plan.pair_s.push_back(i);
+      plan.pair_e.push_back((int32_t)(it - E->q));
+      plan.pair_off.push_back(off);
+      off += (int64_t)S->dim[i] * E->dim[it - E->q];
+    }
+  }
+  if (plan.pair_s.empty()) {
+    err = "no S'/E' sector pair reaches the target quantum number";
+    return DMRG_E_QN;
+  }
+  plan.D = off;
+  const int32_t npairs = (int32_t)plan.pair_s.size();
+
+  // stage operators
+  std::vector<std::vector<SideBlock>> Aside(nterms), Bside(nterms);
+  for (int32_t k = 0; k < nterms; ++k) {
+    const dmrg_term& t = terms[k];
+    int64_t dA = t.A ? t.A->delta : 0, dB = t.B ? t.B->delta : 0;
+    if (dA + dB != 0) {
+      std::ostringstream os;
+      os << "term " << k << " changes the total quantum number by " << dA + dB;
+      err = os.str();
+      return DMRG_E_QN;
+    }
+    if ((st = stage_side(t.A, S, true, transpose, "A", k, Aside[k], plan, err)) != DMRG_OK) return st;
+    if ((st = stage_side(t.B, E, false, transpose, "B", k, Bside[k], plan, err)) != DMRG_OK) return st;
+    plan.coeff.push_back(t.c);
+  }
+
+  // segments per output pair
+  plan.pair_seg0.resize(npairs);
+  plan.pair_nseg.resize(npairs);
+  for (int32_t p = 0; p < npairs; ++p) {
+    const int32_t i = plan.pair_s[p], j = plan.pair_e[p];
+    plan.pair_seg0[p] = (int32_t)plan.segs.size();
+    for (int32_t k = 0; k < nterms; ++k) {
+      SideBlock a, b;
+      if (terms[k].A) {
+        a = Aside[k][i];
+        if (a.src_sec < 0 || a.empty) continue;
+      } else {
+        a.src_sec = i;
+      }
+      if (terms[k].B) {
+        b = Bside[k][j];
+        if (b.src_sec < 0 || b.empty) continue;
+      } else {
+        b.src_sec = j;
+      }
+      const int32_t p2 = pair_of_s[a.src_sec];
+      if (p2 < 0 || plan.pair_e[p2] != b.src_sec) continue;  // source block outside the target
+      SegDesc sg{};
+      sg.c = terms[k].c;
+      sg.term = k;
+      sg.psi_off = plan.pair_off[p2];
+      sg.psi_ld = plan.dE[b.src_sec];
+      sg.psi_rows = plan.dS[a.src_sec];
+      sg.op_off = -1;
+      sg.op_ld = 0;
+      sg.gA = a.g_off;
+      sg.gB = b.g_off;
+      if (a.dense && b.dense) {
+        std::ostringstream os;
+        os << "term " << k << " has dense blocks on both sides (not supported by the fused kernel)";
+        err = os.str();
+        return DMRG_E_UNSUPPORTED;
+      } else if (a.dense) {
+        sg.kind = SEG_KN;
+        sg.K = plan.dS[a.src_sec];
+        sg.op_off = a.op_off;
+        sg.op_ld = a.op_ld;
+        sg.gA = -1;
+      } else if (b.dense) {
+        sg.kind = SEG_MK;
+        sg.K = plan.dE[b.src_sec];
+        sg.op_off = b.op_off;
+        sg.op_ld = b.op_ld;
+        sg.gB = -1;
+      } else {
+        sg.kind = SEG_GG;
+        sg.K = 0;
+      }
+      plan.segs.push_back(sg);
+    }
+    plan.pair_nseg[p] = (int32_t)plan.segs.size() - plan.pair_seg0[p];
+  }
+
+  // tiles, most expensive first (list scheduling in dispatch order)
+  std::vector<std::pair<int64_t, int32_t>> order;
+  for (int32_t p = 0; p < npairs; ++p) {
+    const int32_t a = plan.dS[plan.pair_s[p]], b = plan.dE[plan.pair_e[p]];
+    int64_t cost = 0, kpad = 0;
+    for (int32_t s = 0; s < plan.pair_nseg[p]; ++s) {
+      const SegDesc& sg = plan.segs[plan.pair_seg0[p] + s];
+      const double c2 = 2.0 * a * b;
+      if (sg.kind == SEG_GG) {
+        cost += 2;
+        plan.flops_alg += c2;
+      } else {
+        const int64_t kp = (sg.K + kChunk - 1) / kChunk * kChunk;
+        kpad += kp;
+        cost += kp / kChunk * 4;
+        plan.flops_alg += c2 * sg.K;
+        const int32_t gathered = sg.kind == SEG_KN ? (sg.gB >= 0) : (sg.gA >= 0);
+        if (gathered) plan.flops_alg += 2.0 * sg.K * (sg.kind == SEG_KN ? b : a);
+      }
+    }
+    for (int32_t m0 = 0; m0 < a; m0 += kTile)
+      for (int32_t n0 = 0; n0 < b; n0 += kTile) {
+        TileDesc t{};
+        t.y_off = plan.pair_off[p];
+        t.a = a;
+        t.b = b;
+        t.m0 = m0;
+        t.n0 = n0;
+        t.seg0 = plan.pair_seg0[p];
+        t.nseg = plan.pair_nseg[p];
+        order.push_back({cost, (int32_t)plan.tiles.size()});
+        plan.tiles.push_back(t);
+        plan.flops_exec += 2.0 * kTile * kTile * (double)kpad;
+        plan.gemm_elems += kpad;
+      }
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                     return x.first > y.first;
+                   });
+  std::vector<TileDesc> sorted;
+  sorted.reserve(plan.tiles.size());
+  for (auto& o : order) sorted.push_back(plan.tiles[o.second]);
+  plan.tiles.swap(sorted);
+  plan.bytes_dense = 8.0 * plan.dense.size();
+  return DMRG_OK;
+}
+
+double plan_bytes_alg(const Plan& p, int elem_bytes) {
+  return (double)elem_bytes * p.dense.size() + 12.0 * p.gsrc.size() + 24.0 * p.D;
+}
+
+}  // namespace dmrg

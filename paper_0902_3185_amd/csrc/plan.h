@@ -1,0 +1,87 @@
+// Host-side plan of one superblock product (no HIP calls; builds with any
+// C++17 compiler).
+//
+// The plan is the integer part of H*psi: which S' sector pairs with which E'
+// sector (effective q adds, Sec. 3.2: q_S + q_E = q_target), where each block
+// of psi starts, and, for every output block and term, which source block
+// and operator blocks feed it (Y_q += c A[q<-q'] Psi_q' B^T).  Operator
+// blocks whose rows hold at most one nonzero are turned into gathers
+// (index + scale); the rest stay dense.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dmrg.h"
+
+namespace dmrg {
+
+// Kinds of per-block work.
+enum SegKind : int32_t {
+  SEG_KN = 0,   // Y += c * Aop * (Psi' G_B^T): dense A (stored k-major), B side identity/gather
+  SEG_MK = 1,   // Y += c * (G_A Psi') * Bop^T: A side identity/gather, dense B (stored row-major)
+  SEG_GG = 2    // Y += c * (G_A Psi' G_B^T): elementwise, both sides identity/gather
+};
+
+// One (term, output block) contribution.  Offsets are in elements.
+struct SegDesc {
+  int32_t kind;
+  int32_t K;          // contraction length (SEG_KN: a', SEG_MK: b'); 0 for SEG_GG
+  double c;           // term coefficient
+  int64_t psi_off;    // source block Psi' offset
+  int32_t psi_ld;     // columns of Psi' (b')
+  int32_t psi_rows;   // rows of Psi' (a')
+  int64_t op_off;     // dense pool offset of the operator block (-1: none)
+  int32_t op_ld;      // leading dimension of the stored operator block
+  int32_t gA;         // gather pool offset for output rows (-1: identity)
+  int32_t gB;         // gather pool offset for output columns (-1: identity)
+  int32_t term;       // term index k
+};
+
+// One 32 x 32 output tile of one target block.
+struct TileDesc {
+  int64_t y_off;      // output block offset
+  int32_t a, b;       // output block rows, columns
+  int32_t m0, n0;     // tile origin inside the block
+  int32_t seg0, nseg; // the block's segments
+};
+
+constexpr int kTile = 32;    // output tile edge
+constexpr int kChunk = 16;   // contraction chunk
+
+struct Plan {
+  // bases
+  std::vector<int64_t> qS, qE;
+  std::vector<int32_t> dS, dE;
+  int64_t q_target = 0;
+  // target pairs (ordered by S' sector)
+  std::vector<int32_t> pair_s, pair_e;
+  std::vector<int64_t> pair_off;
+  int64_t D = 0;
+  // terms
+  int32_t nterms = 0;
+  std::vector<double> coeff;
+  // work
+  std::vector<SegDesc> segs;      // grouped by output pair
+  std::vector<int32_t> pair_seg0, pair_nseg;
+  std::vector<TileDesc> tiles;    // sorted by decreasing cost
+  // staged operator data (FP64; converted at upload)
+  std::vector<double> dense;      // dense pool
+  std::vector<int32_t> gsrc;      // gather pool: source index (-1: zero row)
+  std::vector<double> gscale;     // gather pool: scale
+  // statistics of one product
+  double flops_alg = 0, flops_exec = 0, bytes_dense = 0;
+  int64_t gemm_elems = 0;         // sum of padded K over tiles (for reporting)
+};
+
+// Builds `plan` (and, with transpose=true, the plan of H^T = sum c A^T (x) B^T).
+// Returns DMRG_OK or an error code with `err` set.
+dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_target,
+                       int32_t nterms, const dmrg_term* terms, bool transpose, Plan& plan,
+                       std::string& err);
+
+// Recomputes statistics for an element size of the staged operators.
+double plan_bytes_alg(const Plan& p, int elem_bytes);
+
+}  // namespace dmrg

@@ -1,0 +1,219 @@
+"""Python binding of libdmrg: argument marshalling around the C ABI.
+
+A superblock description is plain data (numpy arrays):
+
+    {"S": {"q": int64[nsec], "dim": int[nsec]},  "E": {...},
+     "q_target": int,
+     "terms": [{"c": float, "A": op | None, "B": op | None, "group": int}, ...]}
+    op = {"delta": int, "blocks": [(row_sec, col_sec, float64 2-D array), ...]}
+
+Device vectors are torch float64 CUDA tensors of length D in the library's
+psi layout.  Every computation runs in libdmrg; this module only converts
+arguments and owns handles.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import PREC, check, lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A libdmrg context on a CUDA (HIP) device, queueing on a torch stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self._stream = stream
+        h = C.c_void_p()
+        check(lib().dmrg_ctx_create(self.device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def set_stream(self, stream):
+        self._stream = stream
+        check(lib().dmrg_ctx_set_stream(self.handle, C.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dmrg_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Marshal:
+    """Keeps the ctypes views of a description alive during a build call."""
+
+    def __init__(self, sb):
+        self.keep = []
+        self.S = self._basis(sb["S"])
+        self.E = self._basis(sb["E"])
+        terms = sb["terms"]
+        self.nterms = len(terms)
+        arr = (_lib.dmrg_term * max(1, self.nterms))()
+        for k, t in enumerate(terms):
+            arr[k].c = float(t["c"])
+            arr[k].group = int(t.get("group", 0))
+            arr[k].A = self._op(t["A"])
+            arr[k].B = self._op(t["B"])
+        self.terms = arr
+
+    def _basis(self, b):
+        q = np.ascontiguousarray(b["q"], dtype=np.int64)
+        d = np.ascontiguousarray(b["dim"], dtype=np.int32)
+        self.keep += [q, d]
+        return _lib.dmrg_basis(len(q), q.ctypes.data_as(C.POINTER(C.c_int64)),
+                               d.ctypes.data_as(C.POINTER(C.c_int32)))
+
+    def _op(self, op):
+        if op is None:
+            return C.POINTER(_lib.dmrg_op)()
+        blocks = op["blocks"]
+        n = len(blocks)
+        rows = np.ascontiguousarray([b[0] for b in blocks], dtype=np.int32)
+        cols = np.ascontiguousarray([b[1] for b in blocks], dtype=np.int32)
+        data = [np.ascontiguousarray(b[2], dtype=np.float64) for b in blocks]
+        ptrs = (C.POINTER(C.c_double) * max(1, n))(*[d.ctypes.data_as(C.POINTER(C.c_double)) for d in data])
+        o = _lib.dmrg_op(int(op["delta"]), n, rows.ctypes.data_as(C.POINTER(C.c_int32)),
+                         cols.ctypes.data_as(C.POINTER(C.c_int32)), ptrs)
+        self.keep += [rows, cols, data, ptrs, o]
+        return C.pointer(o)
+
+
+class Superblock:
+    """A superblock built in libdmrg (dmrg_build_superblock).
+
+    ``ctx=None`` builds the host plan only (layout and statistics).
+    """
+
+    def __init__(self, desc, prec="fp32", ctx=None):
+        self.ctx = ctx
+        self.prec = prec
+        self.nterms = len(desc["terms"])
+        m = _Marshal(desc)
+        h = C.c_void_p()
+        check(lib().dmrg_build_superblock(ctx.handle if ctx is not None else None,
+                                          C.byref(m.S), C.byref(m.E), int(desc["q_target"]),
+                                          m.nterms, m.terms, PREC[prec], C.byref(h)))
+        self.handle = h
+        self._dims = (np.asarray(desc["S"]["dim"]), np.asarray(desc["E"]["dim"]))
+        D = C.c_int64()
+        npairs = C.c_int32()
+        off = C.POINTER(C.c_int64)()
+        ss = C.POINTER(C.c_int32)()
+        es = C.POINTER(C.c_int32)()
+        check(lib().dmrg_sb_layout(h, C.byref(D), C.byref(npairs), C.byref(off), C.byref(ss),
+                                   C.byref(es)))
+        self.D = int(D.value)
+        n = npairs.value
+        self.offsets = np.array([off[i] for i in range(n)], dtype=np.int64)
+        self.s_sec = np.array([ss[i] for i in range(n)], dtype=np.int32)
+        self.e_sec = np.array([es[i] for i in range(n)], dtype=np.int32)
+
+    # -- queries -------------------------------------------------------------
+    def stats(self):
+        fa, fe, ba = C.c_double(), C.c_double(), C.c_double()
+        nt = C.c_int32()
+        check(lib().dmrg_sb_stats(self.handle, C.byref(fa), C.byref(fe), C.byref(ba), C.byref(nt)))
+        return dict(flops_alg=fa.value, flops_exec=fe.value, bytes_alg=ba.value, ntiles=nt.value)
+
+    def set_coeffs(self, c):
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        if c.shape != (self.nterms,):
+            raise ValueError("need one coefficient per term")
+        check(lib().dmrg_sb_set_coeffs(self.handle, c.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def set_prec(self, prec):
+        check(lib().dmrg_sb_set_prec(self.handle, PREC[prec]))
+        self.prec = prec
+
+    # -- device work -----------------------------------------------------------
+    def _vec(self, t, name):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and t.numel() == self.D):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of length {self.D}")
+        return t
+
+    def hpsi(self, psi, y=None, alpha=1.0, beta=0.0):
+        import torch
+        self._vec(psi, "psi")
+        if y is None:
+            y = torch.empty_like(psi)
+            beta = 0.0
+        self._vec(y, "y")
+        check(lib().dmrg_hpsi(self.handle, _ptr(psi), _ptr(y), float(alpha), float(beta)))
+        return y
+
+    def adjoint(self, psi, g, want_psi=True, want_c=True):
+        import torch
+        self._vec(psi, "psi")
+        self._vec(g, "g")
+        gpsi = torch.empty_like(psi) if want_psi else None
+        gc = np.zeros(max(1, self.nterms)) if want_c else None
+        check(lib().dmrg_hpsi_adjoint(self.handle, _ptr(psi), _ptr(g),
+                                      _ptr(gpsi) if want_psi else None,
+                                      gc.ctypes.data_as(C.POINTER(C.c_double)) if want_c else None))
+        return gpsi, (gc[:self.nterms] if want_c else None)
+
+    def lanczos(self, psi0, max_iter=300, tol=1e-10, out=None, raise_noconv=True):
+        import torch
+        self._vec(psi0, "psi0")
+        if out is None:
+            out = torch.empty_like(psi0)
+        E = C.c_double()
+        it = C.c_int32()
+        res = C.c_double()
+        st = lib().dmrg_lanczos_ground(self.handle, _ptr(psi0), int(max_iter), float(tol),
+                                       C.byref(E), _ptr(out), C.byref(it), C.byref(res))
+        if st != _lib.DMRG_OK and (raise_noconv or st != 6):
+            check(st)
+        return dict(energy=E.value, psi=out, iters=it.value, resid=res.value, converged=st == 0)
+
+    def rho_truncate(self, psi, side, m, no_split=False):
+        self._vec(psi, "psi")
+        tr = _lib.dmrg_trunc()
+        check(lib().dmrg_rho_truncate(self.handle, _ptr(psi), int(side), int(m), int(bool(no_split)),
+                                      C.byref(tr)))
+        kept = tr.kept
+        kps = [tr.kept_per_sec[i] for i in range(tr.nsec)]
+        W = {}
+        for s in range(tr.nsec):
+            if kps[s] > 0:
+                W[s] = np.ctypeslib.as_array(tr.W[s], shape=(self._dim(side, s) * kps[s],)).reshape(
+                    self._dim(side, s), kps[s]).copy()
+        return dict(eps=tr.trunc_err, kept=kept, straddle=bool(tr.straddle),
+                    lam=np.array([tr.lambda_[i] for i in range(kept)]),
+                    lam_sec=np.array([tr.lambda_sec[i] for i in range(kept)], dtype=np.int64),
+                    kept_per_sec=np.array(kps), W=W)
+
+    def _dim(self, side, s):
+        return int(self._dims[side][s])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().dmrg_sb_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_superblock(desc, prec="fp32", ctx=None):
+    return Superblock(desc, prec=prec, ctx=ctx)

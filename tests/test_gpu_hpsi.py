@@ -1,0 +1,147 @@
+"""GPU parity of the superblock product and its adjoint against the oracle.
+
+Both sides get the same seeded superblocks and vectors (workloads).  The
+tolerance is relative to || |H| |psi| ||: FP64 products carry the rounding of
+a K-term FP64 sum (K <= ~600), bounded here by 1e-14; FP32 products round
+the operands once (2^-24 each) and accumulate K terms in FP32, which for
+random-sign rounding errors is ~(2 + sqrt(K)) 2^-24 <= 1.6e-6 at K = 600;
+the test allows 4e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import superblock as OS
+from workloads import WORKLOADS, seeded_vector, workload_superblock
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-14, "fp64_plain": 1e-14, "fp32": 4e-6}
+
+# reduced sizes: several 32-wide tiles per block and ragged tails
+CASES = [("heisenberg_L16_m32", None), ("heisenberg_L100_m256", 64),
+         ("hubbard_L64_U4_m512", 96), ("ladder_2x32_m1024", 80), ("j1j2_L64_m256", 64)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_0902_3185_amd.superblock import Context
+    assert torch.cuda.is_available()
+    return Context(0)
+
+
+def _dev(x):
+    import torch
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _scale(desc, psi):
+    return np.linalg.norm(OS.hpsi_blocks(OS.abs_description(desc), np.abs(psi)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64_plain"])
+@pytest.mark.parametrize("name,m", CASES, ids=[c[0] for c in CASES])
+def test_hpsi_parity(ctx, name, m, prec):
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock(name, m=m, seed=1)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    psi = seeded_vector(sb.D, 11)
+    y0 = seeded_vector(sb.D, 12)
+    ref = 0.7 * OS.hpsi_blocks(desc, psi) - 0.3 * y0
+    y = _host(sb.hpsi(_dev(psi), _dev(y0), alpha=0.7, beta=-0.3))
+    err = np.linalg.norm(y - ref)
+    assert err <= TOL[prec] * _scale(desc, psi), (name, prec, err)
+    # beta = 0 must not read y (fill it with NaN first)
+    import torch
+    yn = torch.full((sb.D,), float("nan"), dtype=torch.float64, device="cuda")
+    y2 = _host(sb.hpsi(_dev(psi), yn, alpha=1.0, beta=0.0))
+    assert np.all(np.isfinite(y2))
+    assert np.linalg.norm(y2 - OS.hpsi_blocks(desc, psi)) <= TOL[prec] * _scale(desc, psi)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_headline_sampled(ctx, prec):
+    """Hubbard L=64, U=4, m=512 centre superblock: sampled entries."""
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("hubbard_L64_U4_m512", seed=0)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    psi = seeded_vector(sb.D, 21)
+    y = _host(sb.hpsi(_dev(psi)))
+    rng = np.random.default_rng(5)
+    pairs, _ = OS.target_pairs(desc)
+    worst = 0.0
+    for _ in range(150):
+        p = int(rng.integers(len(pairs)))
+        i, j, off = pairs[p]
+        a, b = int(desc["S"]["dim"][i]), int(desc["E"]["dim"][j])
+        m, n = int(rng.integers(a)), int(rng.integers(b))
+        ref = OS.hpsi_element(desc, psi, i, j, m, n)
+        scale = OS.hpsi_element(desc, np.abs(psi), i, j, m, n, absolute=True)
+        got = y[off + m * b + n]
+        worst = max(worst, abs(got - ref) / max(scale, 1e-300))
+    assert worst <= {"fp64": 1e-13, "fp32": 2e-5}[prec], worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_deterministic_and_hermitian(ctx, prec):
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("ladder_2x32_m1024", m=64, seed=2)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    x = seeded_vector(sb.D, 1)
+    yv = seeded_vector(sb.D, 2)
+    h1 = _host(sb.hpsi(_dev(x)))
+    h2 = _host(sb.hpsi(_dev(x)))
+    assert np.array_equal(h1, h2)
+    hy = _host(sb.hpsi(_dev(yv)))
+    lhs, rhs = np.dot(yv, h1), np.dot(hy, x)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert abs(lhs - rhs) <= tol * (np.linalg.norm(h1) * np.linalg.norm(yv))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,m", [("j1j2_L64_m256", 48), ("ladder_2x32_m1024", 48),
+                                    ("hubbard_L64_U4_m512", 64)])
+def test_adjoint_parity(ctx, name, m, prec):
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock(name, m=m, seed=3)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    psi = seeded_vector(sb.D, 31)
+    g = seeded_vector(sb.D, 32)
+    gp_ref, gc_ref = OS.hpsi_adjoint_blocks(desc, psi, g)
+    gp, gc = sb.adjoint(_dev(psi), _dev(g))
+    gp = _host(gp)
+    assert np.linalg.norm(gp - gp_ref) <= TOL[prec] * _scale(desc, np.abs(g))
+    scale = np.linalg.norm(g) * np.linalg.norm(psi) * max(1.0, max(abs(t["c"]) for t in desc["terms"]))
+    assert np.max(np.abs(gc - gc_ref)) <= (1e-12 if prec == "fp64" else 1e-5) * scale * 10
+
+
+def test_set_coeffs_is_linear(ctx):
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("j1j2_L64_m256", m=48, seed=4)
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    psi = seeded_vector(sb.D, 41)
+    c = np.array([t["c"] for t in desc["terms"]])
+    c2 = c * np.linspace(0.5, 1.5, len(c))
+    sb.set_coeffs(c2)
+    y = _host(sb.hpsi(_dev(psi)))
+    ref = OS.hpsi_blocks(desc, psi, coeffs=c2)
+    assert np.linalg.norm(y - ref) <= 1e-14 * _scale(desc, psi) * 2
+
+
+def test_argument_errors(ctx):
+    from paper_0902_3185_amd import _lib
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("heisenberg_L16_m32", seed=0)
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    x = _dev(seeded_vector(sb.D, 1))
+    import ctypes as C
+    st = _lib.lib().dmrg_hpsi(sb.handle, C.c_void_p(x.data_ptr()), C.c_void_p(x.data_ptr()), 1.0, 0.0)
+    assert _lib.STATUS[st] == "DMRG_E_ARG"
+    with pytest.raises(ValueError):
+        sb.hpsi(_dev(np.zeros(sb.D + 1)))

@@ -1,0 +1,143 @@
+"""GPU parity of the Lanczos ground state, density-matrix truncation and
+autograd against the oracle.
+
+Energies: |dE| <= 1e-9 per site (L the workload's chain length) against the
+oracle's FP64 Lanczos on the same superblock, for FP64 and for the FP32
+product with FP64 restart cycles.
+"""
+import numpy as np
+import pytest
+
+from oracle import lanczos as OL
+from oracle import rho as OR
+from oracle import superblock as OS
+from workloads import seeded_vector, workload_superblock
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_0902_3185_amd.superblock import Context
+    assert torch.cuda.is_available()
+    return Context(0)
+
+
+def _dev(x):
+    import torch
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _oracle_ground(desc, seed):
+    _, D = OS.target_pairs(desc)
+    E, psi, it, res = OL.lanczos_ground(lambda v: OS.hpsi_blocks(desc, v), seeded_vector(D, seed),
+                                        max_iter=400, tol=1e-11)
+    return E, psi
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64_plain"])
+@pytest.mark.parametrize("name,m", [("heisenberg_L16_m32", None), ("hubbard_L64_U4_m512", 64),
+                                    ("j1j2_L64_m256", 48)])
+def test_lanczos_energy(ctx, name, m, prec):
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock(name, m=m, seed=5)
+    L = desc["meta"]["L"]
+    E_ref, psi_ref = _oracle_ground(desc, 7)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    r = sb.lanczos(_dev(seeded_vector(sb.D, 7)), max_iter=600, tol=1e-9)
+    assert r["converged"] and r["resid"] <= 1e-9
+    assert abs(r["energy"] - E_ref) <= 1e-9 * L, (r["energy"], E_ref)
+    psi = _host(r["psi"])
+    assert abs(np.linalg.norm(psi) - 1) < 1e-12
+    assert 1 - abs(np.dot(psi, psi_ref)) < 1e-8
+
+
+def test_lanczos_full_size_headline(ctx):
+    """FP32 product + FP64 cycles at the full Hubbard m=512 superblock."""
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("hubbard_L64_U4_m512", seed=0)
+    sb = Superblock(desc, prec="fp32", ctx=ctx)
+    r = sb.lanczos(_dev(seeded_vector(sb.D, 3)), max_iter=2000, tol=1e-8)
+    assert r["converged"]
+    psi = _host(r["psi"])
+    # properties that hold at any size: the FP64 residual and Rayleigh quotient
+    hp = OS.hpsi_blocks(desc, psi)
+    E = float(np.dot(psi, hp))
+    assert np.linalg.norm(hp - E * psi) <= 2e-8
+    assert abs(E - r["energy"]) <= 1e-9 * 64
+    # and the oracle's own Lanczos from the same start
+    E_ref, _ = _oracle_ground(desc, 3)
+    assert abs(r["energy"] - E_ref) <= 1e-9 * 64, (r["energy"], E_ref)
+
+
+def test_lanczos_cap_reports_noconv(ctx):
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("heisenberg_L16_m32", seed=0)
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    r = sb.lanczos(_dev(seeded_vector(sb.D, 1)), max_iter=2, tol=1e-12, raise_noconv=False)
+    assert not r["converged"] and r["iters"] == 2 and np.isfinite(r["energy"])
+
+
+def test_lanczos_exact_eigenvector_stops_at_once(ctx):
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("heisenberg_L16_m32", seed=0)
+    E_ref, psi_ref = _oracle_ground(desc, 2)
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    r = sb.lanczos(_dev(psi_ref), max_iter=50, tol=1e-9)
+    assert r["converged"] and r["iters"] == 1 and abs(r["energy"] - E_ref) < 1e-12
+
+
+@pytest.mark.parametrize("no_split", [False, True])
+@pytest.mark.parametrize("name,m,keep", [("hubbard_L64_U4_m512", 64, 100),
+                                         ("heisenberg_L100_m256", 64, 40),
+                                         ("heisenberg_L16_m32", None, 1000)])
+def test_rho_truncate_parity(ctx, name, m, keep, no_split):
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock(name, m=m, seed=6)
+    E_ref, psi = _oracle_ground(desc, 9)
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    for side in (0, 1):
+        ref = OR.truncate(desc, psi, side, keep, no_split=no_split)
+        got = sb.rho_truncate(_dev(psi), side, keep, no_split=no_split)
+        assert got["kept"] == ref["kept"] and got["straddle"] == ref["straddle"]
+        assert abs(got["eps"] - ref["eps"]) <= 1e-13
+        assert np.allclose(got["lam"], ref["lam"], atol=1e-14)
+        assert list(got["lam_sec"]) == list(ref["lam_sec"])
+        assert set(got["W"]) == set(ref["W"])
+        for s, W in got["W"].items():
+            Wr = ref["W"][s]
+            assert W.shape == Wr.shape
+            assert np.allclose(W.T @ W, np.eye(W.shape[1]), atol=1e-12)
+            # same kept space (eigenvector signs and rotations inside exact
+            # degeneracies are free)
+            assert np.allclose(W @ W.T, Wr @ Wr.T, atol=1e-8)
+
+
+def test_autograd_hellmann_feynman(ctx):
+    """dE/dc_k = <psi|A_k (x) B_k|psi> at the ground state, through autograd."""
+    import torch
+    from paper_0902_3185_amd.autograd import hpsi
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("j1j2_L64_m256", m=48, seed=8)
+    E_ref, psi_ref = _oracle_ground(desc, 4)
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    c = torch.tensor([t["c"] for t in desc["terms"]], dtype=torch.float64, requires_grad=True)
+    psi = _dev(psi_ref)
+    E = torch.dot(psi, hpsi(psi, c, sb))
+    E.backward()
+    _, gc_ref = OS.hpsi_adjoint_blocks(desc, psi_ref, psi_ref)
+    assert abs(E.item() - E_ref) < 1e-10
+    assert np.allclose(c.grad.numpy(), gc_ref, atol=1e-12)
+    # grad with respect to psi: (H + H^T) psi = 2 E psi at an eigenvector
+    psi2 = _dev(psi_ref).requires_grad_(True)
+    E2 = torch.dot(psi2.detach(), hpsi(psi2, c.detach(), sb))
+    E2.backward()
+    gp = _host(psi2.grad)
+    assert np.linalg.norm(gp - E_ref * psi_ref) < 1e-9
