@@ -52,6 +52,8 @@ _SIGS = {
     "dmrg_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "dmrg_ctx_destroy": (None, [_P]),
     "dmrg_ctx_set_stream": (C.c_int, [_P, _P]),
+    "dmrg_ctx_set_timing": (C.c_int, [_P, C.c_int32]),
+    "dmrg_ctx_timing": (C.c_int, [_P, C.c_int32, _D, C.POINTER(C.c_int64), C.c_int32]),
     "dmrg_last_error": (C.c_char_p, []),
     "dmrg_version": (C.c_char_p, []),
     "dmrg_build_superblock": (C.c_int, [_P, C.POINTER(dmrg_basis), C.POINTER(dmrg_basis), C.c_int64,
@@ -73,6 +75,23 @@ _SIGS = {
 }
 
 _lib = None
+_shutting_down = False
+
+
+def _at_exit():
+    global _shutting_down
+    _shutting_down = True
+
+
+import atexit  # noqa: E402
+
+atexit.register(_at_exit)
+
+
+def alive():
+    """False once the interpreter is shutting down (handles are then leaked,
+    not freed, so no HIP call races the runtime's own teardown)."""
+    return not _shutting_down
 
 
 def lib():

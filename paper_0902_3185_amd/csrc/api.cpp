@@ -96,6 +96,14 @@ struct OpCopy {
 struct dmrg_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  // optional per-launch timing of the product kernels (HIP events on `stream`)
+  bool timing = false;
+  struct Mark {
+    hipEvent_t a, b;
+    int prec;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> spare;
   // Lanczos workspace (grow-only)
   DevBuf V, w, partial, small;
   double* host_small = nullptr;   // pinned, for per-iteration scalars
@@ -104,6 +112,8 @@ struct dmrg_ctx_s {
 
 struct dmrg_sb_s {
   dmrg_ctx ctx = nullptr;
+  int device = -1;              // copies, so destruction does not need the context
+  hipStream_t stream = nullptr;
   dmrg_prec prec = DMRG_FP64;
   std::vector<int64_t> qS, qE;
   std::vector<int32_t> dS, dE;
@@ -161,9 +171,36 @@ dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
 
 int kernel_prec(dmrg_prec p) { return p == DMRG_FP32 ? kPrecF32 : kPrecF64; }
 
-// y = alpha H psi + beta y with a given plan and precision.
+hipError_t take_event(dmrg_ctx c, hipEvent_t* e) {
+  if (!c->spare.empty()) {
+    *e = c->spare.back();
+    c->spare.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
+                              double alpha, double beta);
+
+// y = alpha H psi + beta y with a given plan and precision (timed if asked).
 dmrg_status run_product(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
                         double alpha, double beta) {
+  dmrg_ctx c = sb->ctx;
+  if (!c->timing) return run_product_inner(sb, st, prec, psi, y, alpha, beta);
+  dmrg_ctx_s::Mark mk;
+  HIP_TRY(take_event(c, &mk.a));
+  HIP_TRY(take_event(c, &mk.b));
+  mk.prec = (int)prec;
+  HIP_TRY(hipEventRecord(mk.a, c->stream));
+  dmrg_status st2 = run_product_inner(sb, st, prec, psi, y, alpha, beta);
+  HIP_TRY(hipEventRecord(mk.b, c->stream));
+  c->marks.push_back(mk);
+  return st2;
+}
+
+dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
+                              double alpha, double beta) {
   hipStream_t s = sb->ctx->stream;
   const Plan& p = st.plan;
   if (prec == DMRG_FP64_PLAIN) {
@@ -254,8 +291,46 @@ dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx* out) {
 void dmrg_ctx_destroy(dmrg_ctx ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& mk : ctx->marks) {
+    (void)hipEventDestroy(mk.a);
+    (void)hipEventDestroy(mk.b);
+  }
+  for (auto e : ctx->spare) (void)hipEventDestroy(e);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   delete ctx;
+}
+
+dmrg_status dmrg_ctx_set_timing(dmrg_ctx ctx, int32_t enable) {
+  if (!ctx) return fail(DMRG_E_ARG, "null context");
+  ctx->timing = enable != 0;
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_ctx_timing(dmrg_ctx ctx, int32_t prec, double* ms_total, int64_t* launches,
+                            int32_t reset) {
+  if (!ctx || !ms_total || !launches) return fail(DMRG_E_ARG, "null argument");
+  DeviceGuard g(ctx->device);
+  double tot = 0.0;
+  int64_t n = 0;
+  if (!ctx->marks.empty()) HIP_TRY(hipEventSynchronize(ctx->marks.back().b));
+  for (auto& mk : ctx->marks) {
+    if (mk.prec != prec) continue;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, mk.a, mk.b));
+    tot += ms;
+    ++n;
+  }
+  *ms_total = tot;
+  *launches = n;
+  if (reset) {
+    for (auto& mk : ctx->marks) {
+      ctx->spare.push_back(mk.a);
+      ctx->spare.push_back(mk.b);
+    }
+    ctx->marks.clear();
+  }
+  return DMRG_OK;
 }
 
 dmrg_status dmrg_ctx_set_stream(dmrg_ctx ctx, void* hip_stream) {
@@ -275,6 +350,10 @@ dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_
   dmrg_status st = build_plan(S, E, q_target, nterms, terms, false, sb->fwd.plan, err);
   if (st != DMRG_OK) return fail(st, err);
   sb->ctx = ctx;
+  if (ctx) {
+    sb->device = ctx->device;
+    sb->stream = ctx->stream;
+  }
   sb->prec = prec;
   sb->qS.assign(S->q, S->q + S->nsec);
   sb->qE.assign(E->q, E->q + E->nsec);
@@ -298,9 +377,9 @@ dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_
 
 void dmrg_sb_destroy(dmrg_sb sb) {
   if (!sb) return;
-  if (sb->ctx) {
-    DeviceGuard g(sb->ctx->device);
-    (void)hipStreamSynchronize(sb->ctx->stream);
+  if (sb->device >= 0) {
+    DeviceGuard g(sb->device);
+    (void)hipStreamSynchronize(sb->stream);
     delete sb;
   } else {
     delete sb;

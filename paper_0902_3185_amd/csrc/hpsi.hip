@@ -118,7 +118,7 @@ struct CfgF32 {
 
 // FP64 matrix cores: v_mfma_f64_16x16x4f64 on a 2 x 2 grid of 16x16 blocks.
 // A[i][k] from lane i + 16k, B[k][j] from lane j + 16k; D[i][j] in lane
-// j + 16*(i/4), register i%4.
+// j + 16*(i%4), register i/4 (rows interleaved over the four lane groups).
 struct CfgF64 {
   using op_t = double;
   struct Acc {
@@ -200,7 +200,7 @@ struct CfgF64 {
   __device__ static double value(const Acc& a, int r) { return a.d[r >> 2][r & 3]; }
   __device__ static void coords(int lane, int r, int& row, int& col) {
     const int b = r >> 2, bi = b >> 1, bj = b & 1;
-    row = 16 * bi + 4 * (lane >> 4) + (r & 3);
+    row = 16 * bi + 4 * (r & 3) + (lane >> 4);
     col = 16 * bj + (lane & 15);
   }
   static constexpr int kRegs = 16;

@@ -42,10 +42,20 @@ class Context:
         self._stream = stream
         check(lib().dmrg_ctx_set_stream(self.handle, C.c_void_p(stream.cuda_stream)))
 
+    def set_timing(self, enable=True):
+        check(lib().dmrg_ctx_set_timing(self.handle, int(bool(enable))))
+
+    def timing(self, prec, reset=True):
+        """(summed event ms, launches) of the product kernels of one precision."""
+        ms = C.c_double()
+        n = C.c_int64()
+        check(lib().dmrg_ctx_timing(self.handle, PREC[prec], C.byref(ms), C.byref(n), int(bool(reset))))
+        return ms.value, n.value
+
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib.alive():
             lib().dmrg_ctx_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -204,9 +214,9 @@ class Superblock:
         return int(self._dims[side][s])
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib.alive():
             lib().dmrg_sb_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
