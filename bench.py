@@ -115,17 +115,28 @@ def main():
     log(f"[bench] {args.workload}: D={sb.D} pairs={len(sb.s_sec)} terms={sb.nterms} "
         f"tiles={st['ntiles']} F_alg={F:.3e} flop/product build={build_ms:.0f} ms")
 
+    parts = {"lanczos": 0.0, "rho_S": 0.0, "rho_E": 0.0, "adjoint": 0.0}
+
     def step():
+        t = time.perf_counter()
         r = sb.lanczos(psi0, max_iter=4000, tol=1e-8)
+        t1 = time.perf_counter()
         sb.rho_truncate(r["psi"], 0, m)
+        t2 = time.perf_counter()
         sb.rho_truncate(r["psi"], 1, m)
+        t3 = time.perf_counter()
         sb.adjoint(r["psi"], r["psi"], want_psi=False, want_c=True)
+        t4 = time.perf_counter()
+        for k, v in zip(parts, (t1 - t, t2 - t1, t3 - t2, t4 - t3)):
+            parts[k] += v
         return r
 
     for i in range(args.warmup):
         r = step()
         log(f"[bench] warmup {i}: E0={r['energy']:.12f} products={r['iters']} resid={r['resid']:.2e}")
     torch.cuda.synchronize()
+    for k in parts:
+        parts[k] = 0.0
     ctx.timing("fp32", reset=True)
     ctx.set_timing(True)
     torch.cuda.synchronize()
@@ -176,6 +187,7 @@ def main():
         "energy": {"E0_fp32_refined": E32, "E0_fp64": r64["energy"], "abs_dE_per_site": dE / L,
                    "wavefunction_err": wf_err, "products_per_solve": r["iters"]},
         "build_ms": round(build_ms, 1),
+        "step_breakdown_ms": {k: round(1e3 * v / args.steps, 3) for k, v in parts.items()},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc, F, args.cpu_seconds)

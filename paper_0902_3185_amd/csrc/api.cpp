@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <cstring>
 #include <memory>
 #include <sstream>
@@ -76,7 +78,7 @@ struct DeviceGuard {
 // A plan and its device copy.
 struct Staged {
   Plan plan;
-  DevBuf tiles, segs, gsrc, gscale, dense64, dense32;
+  DevBuf order, tiles, segs, gsrc, gscale, dense64, dense32;
   bool has32 = false;
   int max_nseg = 0;
   std::vector<std::pair<SegDesc, TileDesc>> plain;  // one entry per (block, term)
@@ -143,6 +145,7 @@ dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
   const Plan& p = st.plan;
   hipStream_t s = ctx->stream;
   dmrg_status r;
+  if ((r = upload(st.order, p.order.data(), p.order.size() * sizeof(int32_t), s)) != DMRG_OK) return r;
   if ((r = upload(st.tiles, p.tiles.data(), p.tiles.size() * sizeof(TileDesc), s)) != DMRG_OK) return r;
   if ((r = upload(st.segs, p.segs.data(), p.segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return r;
   if ((r = upload(st.gsrc, p.gsrc.data(), p.gsrc.size() * sizeof(int32_t), s)) != DMRG_OK) return r;
@@ -214,9 +217,9 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
     if (!st.has32) return fail(DMRG_E_ARG, "FP32 operators not staged (use dmrg_sb_set_prec)");
     dense = st.dense32.p;
   }
-  HIP_TRY(launch_hpsi(kernel_prec(prec), (int)p.tiles.size(), st.tiles.as<TileDesc>(),
-                      st.segs.as<SegDesc>(), dense, st.gsrc.as<int32_t>(), st.gscale.as<double>(),
-                      psi, y, alpha, beta, s));
+  HIP_TRY(launch_hpsi(kernel_prec(prec), (int)p.order.size(), st.order.as<int32_t>(),
+                      st.tiles.as<TileDesc>(), st.segs.as<SegDesc>(), dense, st.gsrc.as<int32_t>(),
+                      st.gscale.as<double>(), psi, y, alpha, beta, s));
   return DMRG_OK;
 }
 
@@ -512,15 +515,18 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   hipStream_t s = ctx->stream;
   const int64_t D = sb->fwd.plan.D;
   const bool reduced = sb->prec == DMRG_FP32 || sb->prec == DMRG_BF16X3;
+  // vectors per restart cycle; the host looks at alpha/beta every kCheck steps
   const int per_cycle = reduced ? 100 : std::min<int>(max_iter, 400);
   const int nvec = per_cycle + 1;
-  const int nblk = vec_blocks(D);
+  constexpr int kCheck = 4;
+  const int nblk = std::max(lz_blocks(D), vec_blocks(D));
   HIP_TRY(ctx->V.ensure((size_t)nvec * D * sizeof(double)));
   HIP_TRY(ctx->w.ensure((size_t)D * sizeof(double)));
-  HIP_TRY(ctx->partial.ensure((size_t)std::max(nvec, 1) * nblk * sizeof(double)));
-  // small: h1[nvec], h2[nvec], u[nvec], nrm2[1], ab[2*nvec]
-  const size_t nsmall = (size_t)5 * nvec + 8;
+  HIP_TRY(ctx->partial.ensure((size_t)nvec * nblk * sizeof(double)));
+  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec], counter
+  const size_t nsmall = (size_t)5 * nvec + 16;
   HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
+  HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));   // counter starts at 0
   if (ctx->host_small_n < nsmall) {
     if (ctx->host_small) (void)hipHostFree(ctx->host_small);
     ctx->host_small = nullptr;
@@ -535,6 +541,7 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   double* ud = h2 + nvec;
   double* nrm2 = ud + nvec;
   double* ab = nrm2 + 8;
+  unsigned int* counter = reinterpret_cast<unsigned int*>(ab + 2 * nvec);
   double* hs = ctx->host_small;
 
   // v0 = psi0 / |psi0|
@@ -545,47 +552,61 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   bool converged = false;
   std::vector<double> alphas, betas, u;
   while (!converged && total < max_iter) {
-    alphas.clear();
-    betas.clear();
     double beta0 = 0.0;
-    int j = 0;
-    for (;; ++j) {
+    int nv = 0;      // basis vectors that enter the Ritz vector of this cycle
+    int seen = 0;    // steps whose alpha/beta the host has read
+    u.clear();
+    for (int j = 0;; ++j) {
       double* vj = V + (size_t)j * D;
       const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
       if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
       ++total;
-      HIP_TRY(launch_multi_dot(V, D, j + 1, w, D, part, h1, s));
-      HIP_TRY(launch_multi_axpy_norm(w, V, D, j + 1, h1, D, part, nrm2, s));
-      HIP_TRY(launch_multi_dot(V, D, j + 1, w, D, part, h2, s));
-      HIP_TRY(launch_multi_axpy_norm(w, V, D, j + 1, h2, D, part, nrm2, s));
-      HIP_TRY(launch_record(h1, h2, j, nrm2, ab, 0, s));
-      if (j + 1 < nvec) HIP_TRY(launch_normalise(V + (size_t)(j + 1) * D, w, nrm2, D, s));
-      HIP_TRY(hipMemcpyAsync(hs, ab, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, counter, ab + 2 * j,
+                             j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, s));
+      const bool last = j + 2 >= nvec || total >= max_iter;
+      if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
+      HIP_TRY(hipMemcpyAsync(hs + 2 * seen, ab + 2 * seen, 2 * (j + 1 - seen) * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
-      const double a = hs[0], b = hs[1];
-      alphas.push_back(a);
+      seen = j + 1;
+      alphas.assign(hs, hs + 0);
+      betas.clear();
+      // the recursion is valid up to the first vanishing beta
+      int m = 0;
+      for (; m <= j; ++m) {
+        alphas.push_back(hs[2 * m]);
+        const double b = hs[2 * m + 1];
+        if (m == j || b <= 1e-13 * std::max(1.0, std::fabs(hs[2 * m]))) {
+          betas.push_back(b);
+          ++m;
+          break;
+        }
+        betas.push_back(b);
+      }
+      const int steps = (int)alphas.size();
       if (j == 0) {
-        E = a;
-        res = b;
-        beta0 = b;
-        if (b <= tol) {
+        E = alphas[0];
+        res = betas[0];
+        beta0 = betas[0];
+        if (res <= tol) {
           converged = true;
+          nv = 1;
           break;
         }
       }
       double theta;
-      u.assign(j + 1, 0.0);
-      tridiag_lowest(j + 1, alphas.data(), betas.data(), &theta, u.data());
-      const double est = b * std::fabs(u[j]);
+      u.assign(steps, 0.0);
+      tridiag_lowest(steps, alphas.data(), betas.data(), &theta, u.data());
+      nv = steps;
+      const double bl = betas[steps - 1];
+      const double est = bl * std::fabs(u[steps - 1]);
       const double ctol = reduced ? std::max(tol, 1e-4 * beta0) : tol;
-      const bool breakdown = b <= 1e-13 * std::max(1.0, std::fabs(theta));
+      const bool breakdown = bl <= 1e-13 * std::max(1.0, std::fabs(theta)) || steps < j + 1;
       if (j > 0 && (est <= ctol || breakdown)) break;
-      if (j + 1 >= nvec - 1 || total >= max_iter) break;
-      betas.push_back(b);
+      if (last) break;
     }
     if (converged) break;
     // Ritz vector of the cycle -> start of the next one
-    const int nv = (int)u.size();
     HIP_TRY(hipMemcpyAsync(ud, u.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_combine(w, V, D, nv, ud, D, s));
     HIP_TRY(launch_multi_dot(w, 0, 1, w, D, part, nrm2, s));
@@ -645,6 +666,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
       sg.kind = SEG_KN;
       sg.K = a;
     }
+    sg.ch0 = 0;
     const int32_t s0 = (int32_t)segs.size();
     segs.push_back(sg);
     for (int32_t m0 = 0; m0 < n; m0 += kTile)
@@ -657,6 +679,8 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
         t.n0 = n0;
         t.seg0 = s0;
         t.nseg = 1;
+        t.nchunk = (sg.K + kChunk - 1) / kChunk;
+        t.ngemm = 1;
         tiles.push_back(t);
       }
     total += (int64_t)n * n;
@@ -664,7 +688,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   if ((st = upload(sb->rho_tiles, tiles.data(), tiles.size() * sizeof(TileDesc), s)) != DMRG_OK) return st;
   if ((st = upload(sb->rho_segs, segs.data(), segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return st;
   HIP_TRY(sb->rho_out.ensure((size_t)std::max<int64_t>(total, 1) * sizeof(double)));
-  HIP_TRY(launch_hpsi(kPrecF64, (int)tiles.size(), sb->rho_tiles.as<TileDesc>(),
+  HIP_TRY(launch_hpsi(kPrecF64, (int)tiles.size(), nullptr, sb->rho_tiles.as<TileDesc>(),
                       sb->rho_segs.as<SegDesc>(), psi_d, nullptr, nullptr, psi_d,
                       sb->rho_out.as<double>(), 1.0, 0.0, s));
   std::vector<double> rho((size_t)total);
@@ -680,28 +704,56 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     int32_t sec;
   };
   std::vector<Ent> ents;
-  std::vector<std::vector<double>> vecs(nsec);
+  std::vector<std::vector<double>> vecs(nsec), vals(nsec);
   const double floor_ = 1e-13, rel_tie = 1e-6;
-  for (int sec = 0; sec < nsec; ++sec) {
-    const int n = ds[sec];
-    std::vector<double> A((size_t)n * n, 0.0), wv(n, 0.0);
-    if (rho_off[sec] >= 0) std::copy(rho.begin() + rho_off[sec], rho.begin() + rho_off[sec] + (size_t)n * n, A.begin());
-    for (int i = 0; i < n; ++i)   // symmetrise the computed block
-      for (int j = i + 1; j < n; ++j) {
-        const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
-        A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
+  // Sectors are independent: solve them on host threads, largest first.
+  std::vector<int> work(nsec);
+  for (int i = 0; i < nsec; ++i) work[i] = i;
+  std::stable_sort(work.begin(), work.end(), [&](int x, int y) { return ds[x] > ds[y]; });
+  std::atomic<int> next(0), bad(0);
+  auto solve = [&]() {
+    for (;;) {
+      const int w = next.fetch_add(1);
+      if (w >= nsec) return;
+      const int sec = work[w];
+      const int n = ds[sec];
+      std::vector<double> A((size_t)n * n, 0.0), wv(n, 0.0);
+      if (rho_off[sec] >= 0)
+        std::copy(rho.begin() + rho_off[sec], rho.begin() + rho_off[sec] + (size_t)n * n, A.begin());
+      for (int i = 0; i < n; ++i)   // symmetrise the computed block
+        for (int j = i + 1; j < n; ++j) {
+          const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+          A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
+        }
+      if (!sym_eigen(n, A.data(), wv.data())) {
+        bad.fetch_add(1);
+        continue;
       }
-    if (!sym_eigen(n, A.data(), wv.data())) return fail(DMRG_E_NOCONV, "density-matrix eigen-solve did not converge");
-    // decreasing order within the sector
-    std::vector<double> V((size_t)n * n);
-    for (int c = 0; c < n; ++c) {
-      const int src = n - 1 - c;
-      for (int r = 0; r < n; ++r) V[(size_t)r * n + c] = A[(size_t)r * n + src];
-      const double raw = wv[src];
+      // decreasing order within the sector
+      std::vector<double> V((size_t)n * n), L(n);
+      for (int c = 0; c < n; ++c) {
+        const int src = n - 1 - c;
+        for (int r = 0; r < n; ++r) V[(size_t)r * n + c] = A[(size_t)r * n + src];
+        L[c] = wv[src];
+      }
+      vecs[sec].swap(V);
+      vals[sec].swap(L);
+    }
+  };
+  {
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int nthr = std::min({hw, nsec, 32});
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthr; ++t) pool.emplace_back(solve);
+    solve();
+    for (auto& th : pool) th.join();
+  }
+  if (bad.load() > 0) return fail(DMRG_E_NOCONV, "density-matrix eigen-solve did not converge");
+  for (int sec = 0; sec < nsec; ++sec)
+    for (int c = 0; c < ds[sec]; ++c) {
+      const double raw = vals[sec][c];
       ents.push_back({raw >= floor_ ? raw : 0.0, raw, qs[sec], c, sec});
     }
-    vecs[sec].swap(V);
-  }
   const int ntot = (int)ents.size();
   std::vector<int> ord(ntot);
   for (int i = 0; i < ntot; ++i) ord[i] = i;

@@ -120,9 +120,12 @@ void tridiag_lowest(int n, const double* a, const double* b, double* theta, doub
 
 bool sym_eigen(int n, double* A, double* w) {
   if (n <= 0) return true;
-  std::vector<double> Q((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
-  std::vector<double> v(n), p(n), ww(n);
+  // QT holds the accumulated orthogonal transformation transposed: row j of
+  // QT is column j of Q, so both the reflector and the rotation updates walk
+  // contiguous memory.
+  std::vector<double> QT((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) QT[(size_t)i * n + i] = 1.0;
+  std::vector<double> v(n), p(n), ww(n), sr(n);
   // Householder reduction: column k below the subdiagonal is annihilated.
   for (int k = 0; k + 2 < n; ++k) {
     double sigma = 0.0;
@@ -154,11 +157,18 @@ bool sym_eigen(int n, double* A, double* w) {
       A[(size_t)i * n + k] = 0.0;
       A[(size_t)k * n + i] = 0.0;
     }
-    for (int r = 0; r < n; ++r) {
-      double s = 0.0;
-      for (int j = k + 1; j < n; ++j) s += Q[(size_t)r * n + j] * v[j];
-      s *= beta;
-      for (int j = k + 1; j < n; ++j) Q[(size_t)r * n + j] -= s * v[j];
+    // Q <- Q H: s_r = beta * sum_j Q[r][j] v[j]; Q[r][j] -= s_r v[j]
+    std::fill(sr.begin(), sr.end(), 0.0);
+    for (int j = k + 1; j < n; ++j) {
+      const double vj = v[j];
+      const double* q = &QT[(size_t)j * n];
+      for (int r = 0; r < n; ++r) sr[r] += q[r] * vj;
+    }
+    for (int r = 0; r < n; ++r) sr[r] *= beta;
+    for (int j = k + 1; j < n; ++j) {
+      const double vj = v[j];
+      double* q = &QT[(size_t)j * n];
+      for (int r = 0; r < n; ++r) q[r] -= sr[r] * vj;
     }
   }
   std::vector<double> d(n), e(n, 0.0);
@@ -207,11 +217,12 @@ bool sym_eigen(int n, double* A, double* w) {
         bulge = -s * e[k + 1];
         e[k + 1] = c * e[k + 1];
       }
+      double* qk = &QT[(size_t)k * n];
+      double* qk1 = &QT[(size_t)(k + 1) * n];
       for (int row = 0; row < n; ++row) {
-        double* qr = &Q[(size_t)row * n];
-        const double zk = qr[k], zk1 = qr[k + 1];
-        qr[k] = c * zk - s * zk1;
-        qr[k + 1] = s * zk + c * zk1;
+        const double zk = qk[row], zk1 = qk1[row];
+        qk[row] = c * zk - s * zk1;
+        qk1[row] = s * zk + c * zk1;
       }
     }
   }
@@ -221,7 +232,8 @@ bool sym_eigen(int n, double* A, double* w) {
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
   for (int c = 0; c < n; ++c) {
     w[c] = d[idx[c]];
-    for (int r = 0; r < n; ++r) A[(size_t)r * n + c] = Q[(size_t)r * n + idx[c]];
+    const double* q = &QT[(size_t)idx[c] * n];
+    for (int r = 0; r < n; ++r) A[(size_t)r * n + c] = q[r];
   }
   return true;
 }

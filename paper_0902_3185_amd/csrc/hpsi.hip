@@ -216,60 +216,287 @@ __device__ inline double gg_term(const SegDesc& sg, const TileDesc& t, int m, in
 }
 
 // ---------------------------------------------------------------------------
-// y = alpha * H psi + beta * y, one workgroup per output tile.
+// y = alpha * H psi + beta * y.  Workgroup slot b takes tile order[b]
+// (-1: idle slot), so that the blocks of one target pair share an XCD.
+//
+// Phase 0  the gather entries of the tile's 32 rows / columns for every
+//          matrix-core segment go to LDS; the elementwise (gather-gather)
+//          terms of each thread's output elements are loaded.
+// Phase 1  the tile's contraction chunks (all matrix-core segments, in
+//          order) are dealt round-robin to the waves; each wave loads its
+//          next chunk while the current one runs on the matrix cores.
+// Phase 2  the waves' 32x32 partial tiles are summed through LDS in wave
+//          order, the elementwise terms added in FP64, and y written.
 // ---------------------------------------------------------------------------
-template <class Cfg>
-__global__ __launch_bounds__(256) void hpsi_grouped(const TileDesc* __restrict__ tiles,
-                                                    const SegDesc* __restrict__ segs,
-                                                    const typename Cfg::op_t* __restrict__ dense,
-                                                    const int32_t* __restrict__ gsrc,
-                                                    const double* __restrict__ gscale,
-                                                    const double* __restrict__ psi,
-                                                    double* __restrict__ y, double alpha,
-                                                    double beta) {
-  __shared__ double red[4][kTile * kTile];
-  const TileDesc t = tiles[blockIdx.x];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  typename Cfg::Acc acc;
-  Cfg::zero(acc);
-  int ctr = 0;  // chunks handed out so far, over all segments of the tile
-  for (int s = 0; s < t.nseg; ++s) {
-    const SegDesc sg = segs[t.seg0 + s];
-    if (sg.kind == SEG_GG) continue;
-    const int nch = (sg.K + kChunk - 1) / kChunk;
-    const int first = (wave - (ctr & 3) + 4) & 3;
-    Cfg::seg(acc, sg, t, first, 4, dense, gsrc, gscale, psi, lane);
-    ctr += nch;
+constexpr int kMaxSeg = 32;   // segments per target block (checked by the host)
+constexpr int kMaxGG = 8;     // elementwise segments whose operands are loaded early
+
+struct TileShared {
+  int32_t gsrc[kMaxSeg][kTile];
+  float gscl[kMaxSeg][kTile];
+};
+
+// Gather entry of index idx (row or column of the output block) for segment sg.
+__device__ inline void gather_entry(const SegDesc& sg, const TileDesc& t, int i,
+                                    const int32_t* gsrc, const double* gscale, int32_t& src,
+                                    float& scl) {
+  const bool kn = sg.kind == SEG_KN;
+  const int idx = (kn ? t.n0 : t.m0) + i;
+  const int limit = kn ? t.b : t.a;
+  const int32_t g = kn ? sg.gB : sg.gA;
+  src = -1;
+  scl = 0.f;
+  if (idx < limit) {
+    if (g < 0) {
+      src = idx;
+      scl = 1.f;
+    } else {
+      src = gsrc[g + idx];
+      scl = (float)gscale[g + idx];
+    }
   }
+}
+
+struct F32Tile {
+  using op_t = float;
+  using red_t = float;
+  static constexpr int kWaves = 16;
+  struct Acc {
+    f32x16 d;
+  };
+  struct Regs {
+    float a[8], b[8];
+  };
+  __device__ static void zero(Acc& a) {
 #pragma unroll
-  for (int r = 0; r < Cfg::kRegs; ++r) {
-    int row, col;
-    Cfg::coords(lane, r, row, col);
-    red[wave][row * kTile + col] = Cfg::value(acc, r);
+    for (int r = 0; r < 16; ++r) a.d[r] = 0.f;
+  }
+  __device__ static void load(Regs& R, const SegDesc& sg, const TileDesc& t, int ch, int si,
+                              const TileShared& sh, const op_t* dense, const double* psi,
+                              int lane) {
+    const int i = lane & 31, kh = lane >> 5;
+    const double* P = psi + sg.psi_off;
+    const int64_t ldp = sg.psi_ld;
+    const int32_t src = sh.gsrc[si][i];
+    const float scl = sh.gscl[si][i];
+    if (sg.kind == SEG_KN) {
+      const op_t* At = dense + sg.op_off;
+      const int64_t lda = sg.op_ld;
+      const int m = t.m0 + i;
+      const bool mok = m < t.a;
+      const bool nok = src >= 0;
+      const float cs = (float)sg.c;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int k = ch * kChunk + 2 * s + kh;
+        const bool kok = k < sg.K;
+        R.a[s] = (mok && kok) ? cs * At[k * lda + m] : 0.f;
+        R.b[s] = (nok && kok) ? scl * (float)P[k * ldp + src] : 0.f;
+      }
+    } else {
+      const bool mok = src >= 0;
+      const double* Arow = P + (int64_t)(mok ? src : 0) * ldp;
+      const int n = t.n0 + i;
+      const bool nok = n < t.b;
+      const op_t* Brow = dense + sg.op_off + (int64_t)(nok ? n : 0) * sg.op_ld;
+      const float ca = (float)sg.c * scl;
+      const int k0 = ch * kChunk + 8 * kh;
+      if (k0 + 8 <= sg.K) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          R.a[s] = mok ? ca * (float)Arow[k0 + s] : 0.f;
+          R.b[s] = nok ? Brow[k0 + s] : 0.f;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const bool kok = k0 + s < sg.K;
+          R.a[s] = (mok && kok) ? ca * (float)Arow[k0 + s] : 0.f;
+          R.b[s] = (nok && kok) ? Brow[k0 + s] : 0.f;
+        }
+      }
+    }
+  }
+  __device__ static void mma(Acc& acc, const Regs& R) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc.d = __builtin_amdgcn_mfma_f32_32x32x2f32(R.a[s], R.b[s], acc.d, 0, 0, 0);
+  }
+  static constexpr int kRegs = 16;
+  __device__ static float value(const Acc& a, int r) { return a.d[r]; }
+  __device__ static void coords(int lane, int r, int& row, int& col) {
+    row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    col = lane & 31;
+  }
+};
+
+struct F64Tile {
+  using op_t = double;
+  using red_t = double;
+  static constexpr int kWaves = 8;
+  struct Acc {
+    f64x4 d[4];
+  };
+  struct Regs {
+    double a0[4], a1[4], b0[4], b1[4];
+  };
+  __device__ static void zero(Acc& a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a.d[b][r] = 0.0;
+  }
+  __device__ static void load(Regs& R, const SegDesc& sg, const TileDesc& t, int ch, int si,
+                              const TileShared& sh, const op_t* dense, const double* psi,
+                              int lane) {
+    const int i = lane & 15, kq = lane >> 4;
+    const double* P = psi + sg.psi_off;
+    const int64_t ldp = sg.psi_ld;
+    const int32_t src0 = sh.gsrc[si][i], src1 = sh.gsrc[si][16 + i];
+    const double scl0 = sh.gscl[si][i], scl1 = sh.gscl[si][16 + i];
+    if (sg.kind == SEG_KN) {
+      const op_t* At = dense + sg.op_off;
+      const int64_t lda = sg.op_ld;
+      const int m0 = t.m0 + i, m1 = t.m0 + 16 + i;
+      const bool mok0 = m0 < t.a, mok1 = m1 < t.a;
+      const double c = sg.c;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = ch * kChunk + 4 * s + kq;
+        const bool kok = k < sg.K;
+        R.a0[s] = (mok0 && kok) ? c * At[k * lda + m0] : 0.0;
+        R.a1[s] = (mok1 && kok) ? c * At[k * lda + m1] : 0.0;
+        R.b0[s] = (src0 >= 0 && kok) ? scl0 * P[k * ldp + src0] : 0.0;
+        R.b1[s] = (src1 >= 0 && kok) ? scl1 * P[k * ldp + src1] : 0.0;
+      }
+    } else {
+      const double* A0 = P + (int64_t)(src0 >= 0 ? src0 : 0) * ldp;
+      const double* A1 = P + (int64_t)(src1 >= 0 ? src1 : 0) * ldp;
+      const int n0 = t.n0 + i, n1 = t.n0 + 16 + i;
+      const bool nok0 = n0 < t.b, nok1 = n1 < t.b;
+      const op_t* B0 = dense + sg.op_off + (int64_t)(nok0 ? n0 : 0) * sg.op_ld;
+      const op_t* B1 = dense + sg.op_off + (int64_t)(nok1 ? n1 : 0) * sg.op_ld;
+      const double c0 = sg.c * scl0, c1 = sg.c * scl1;
+      const int k0 = ch * kChunk + 4 * kq;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bool kok = k0 + s < sg.K;
+        R.a0[s] = (src0 >= 0 && kok) ? c0 * A0[k0 + s] : 0.0;
+        R.a1[s] = (src1 >= 0 && kok) ? c1 * A1[k0 + s] : 0.0;
+        R.b0[s] = (nok0 && kok) ? B0[k0 + s] : 0.0;
+        R.b1[s] = (nok1 && kok) ? B1[k0 + s] : 0.0;
+      }
+    }
+  }
+  __device__ static void mma(Acc& acc, const Regs& R) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      acc.d[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a0[s], R.b0[s], acc.d[0], 0, 0, 0);
+      acc.d[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a0[s], R.b1[s], acc.d[1], 0, 0, 0);
+      acc.d[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a1[s], R.b0[s], acc.d[2], 0, 0, 0);
+      acc.d[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a1[s], R.b1[s], acc.d[3], 0, 0, 0);
+    }
+  }
+  static constexpr int kRegs = 16;
+  __device__ static double value(const Acc& a, int r) { return a.d[r >> 2][r & 3]; }
+  __device__ static void coords(int lane, int r, int& row, int& col) {
+    const int b = r >> 2, bi = b >> 1, bj = b & 1;
+    row = 16 * bi + 4 * (r & 3) + (lane >> 4);
+    col = 16 * bj + (lane & 15);
+  }
+};
+
+// Matrix-core segment holding global chunk g of the tile.
+__device__ inline int seg_of_chunk(const SegDesc* segs, const TileDesc& t, int g) {
+  int found = 0;
+  for (int s = 1; s < t.ngemm; ++s)
+    if (g >= segs[t.seg0 + s].ch0) found = s;
+  return found;
+}
+
+template <class Cfg>
+__global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_grouped(
+    const int32_t* __restrict__ order, const TileDesc* __restrict__ tiles,
+    const SegDesc* __restrict__ segs, const typename Cfg::op_t* __restrict__ dense,
+    const int32_t* __restrict__ gsrc, const double* __restrict__ gscale,
+    const double* __restrict__ psi, double* __restrict__ y, double alpha, double beta) {
+  constexpr int kW = Cfg::kWaves;
+  constexpr int kT = kW * 64;
+  constexpr int kPer = kTile * kTile / kT;   // output elements per thread
+  __shared__ TileShared sh;
+  __shared__ typename Cfg::red_t red[kW][kTile * kTile];
+  const int ti = order ? order[blockIdx.x] : (int)blockIdx.x;
+  if (ti < 0) return;
+  const TileDesc t = tiles[ti];
+  // the wave index is uniform in a wave: say so, so that chunk and segment
+  // bookkeeping stays in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+
+  // phase 0: gather entries of the matrix-core segments; elementwise operands
+  for (int x = threadIdx.x; x < t.ngemm * kTile; x += kT) {
+    const int s = x / kTile, i = x % kTile;
+    gather_entry(segs[t.seg0 + s], t, i, gsrc, gscale, sh.gsrc[s][i], sh.gscl[s][i]);
+  }
+  const int ngg = t.nseg - t.ngemm;
+  double gg[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int el = threadIdx.x + e * kT;
+    const int m = t.m0 + el / kTile, n = t.n0 + el % kTile;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxGG; ++q)
+      if (q < ngg) v += gg_term(segs[t.seg0 + t.ngemm + q], t, m, n, gsrc, gscale, psi);
+    gg[e] = v;
   }
   __syncthreads();
-  const int row = threadIdx.x >> 3, c4 = (threadIdx.x & 7) * 4;
-  const int m = t.m0 + row;
-  double v[4];
+
+  // phase 1: contraction chunks, round-robin over the waves, one chunk ahead
+  typename Cfg::Acc acc;
+  Cfg::zero(acc);
+  const int nw = t.nchunk < kW ? t.nchunk : kW;   // waves that get work
+  if (wave < t.nchunk) {
+    // two register buffers, used alternately: load chunk g + kW while chunk g
+    // is on the matrix cores
+    typename Cfg::Regs ra, rb;
+    auto fetch = [&](typename Cfg::Regs& R, int g) {
+      const int si = seg_of_chunk(segs, t, g);
+      const SegDesc sg = segs[t.seg0 + si];
+      Cfg::load(R, sg, t, g - sg.ch0, si, sh, dense, psi, lane);
+    };
+    int g = wave;
+    fetch(ra, g);
+    for (;;) {
+      const int g2 = g + kW;
+      if (g2 < t.nchunk) fetch(rb, g2);
+      Cfg::mma(acc, ra);
+      if (g2 >= t.nchunk) break;
+      const int g3 = g2 + kW;
+      if (g3 < t.nchunk) fetch(ra, g3);
+      Cfg::mma(acc, rb);
+      if (g3 >= t.nchunk) break;
+      g = g3;
+    }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = row * kTile + c4 + q;
-    v[q] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    for (int r = 0; r < Cfg::kRegs; ++r) {
+      int row, col;
+      Cfg::coords(lane, r, row, col);
+      red[wave][row * kTile + col] = Cfg::value(acc, r);
+    }
   }
-  for (int s = 0; s < t.nseg; ++s) {
-    const SegDesc sg = segs[t.seg0 + s];
-    if (sg.kind != SEG_GG) continue;
+  __syncthreads();
+
+  // phase 2: fixed-order sum, elementwise terms, y
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] += gg_term(sg, t, m, t.n0 + c4 + q, gsrc, gscale, psi);
-  }
-  if (m < t.a) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int n = t.n0 + c4 + q;
-      if (n < t.b) {
-        const int64_t idx = t.y_off + (int64_t)m * t.b + n;
-        y[idx] = beta == 0.0 ? alpha * v[q] : alpha * v[q] + beta * y[idx];
-      }
+  for (int e = 0; e < kPer; ++e) {
+    const int el = threadIdx.x + e * kT;
+    const int m = t.m0 + el / kTile, n = t.n0 + el % kTile;
+    double v = 0.0;
+    for (int w = 0; w < nw; ++w) v += (double)red[w][el];
+    v += gg[e];
+    for (int q = kMaxGG; q < ngg; ++q) v += gg_term(segs[t.seg0 + t.ngemm + q], t, m, n, gsrc, gscale, psi);
+    if (m < t.a && n < t.b) {
+      const int64_t idx = t.y_off + (int64_t)m * t.b + n;
+      y[idx] = beta == 0.0 ? alpha * v : alpha * v + beta * y[idx];
     }
   }
 }
@@ -382,17 +609,17 @@ __global__ __launch_bounds__(256) void plain_segment(SegDesc sg, TileDesc t,
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_hpsi(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,
-                       const void* dense, const int32_t* gsrc, const double* gscale,
-                       const double* psi, double* y, double alpha, double beta,
-                       hipStream_t stream) {
-  if (ntiles <= 0) return hipSuccess;
+hipError_t launch_hpsi(int prec, int nslots, const int32_t* order, const TileDesc* tiles,
+                       const SegDesc* segs, const void* dense, const int32_t* gsrc,
+                       const double* gscale, const double* psi, double* y, double alpha,
+                       double beta, hipStream_t stream) {
+  if (nslots <= 0) return hipSuccess;
   if (prec == kPrecF32) {
-    hipLaunchKernelGGL(hpsi_grouped<CfgF32>, dim3(ntiles), dim3(256), 0, stream, tiles, segs,
-                       (const float*)dense, gsrc, gscale, psi, y, alpha, beta);
+    hipLaunchKernelGGL(hpsi_grouped<F32Tile>, dim3(nslots), dim3(F32Tile::kWaves * 64), 0, stream,
+                       order, tiles, segs, (const float*)dense, gsrc, gscale, psi, y, alpha, beta);
   } else {
-    hipLaunchKernelGGL(hpsi_grouped<CfgF64>, dim3(ntiles), dim3(256), 0, stream, tiles, segs,
-                       (const double*)dense, gsrc, gscale, psi, y, alpha, beta);
+    hipLaunchKernelGGL(hpsi_grouped<F64Tile>, dim3(nslots), dim3(F64Tile::kWaves * 64), 0, stream,
+                       order, tiles, segs, (const double*)dense, gsrc, gscale, psi, y, alpha, beta);
   }
   return hipGetLastError();
 }

@@ -13,14 +13,17 @@ namespace dmrg {
 constexpr int kPrecF64 = 0;
 constexpr int kPrecF32 = 1;
 constexpr int kPrecBF16X3 = 2;
+constexpr int kMaxSegPerBlock = 32;
 
 // y = alpha * H psi + beta * y with the grouped kernel; `dense` holds the
 // operator pool in the kernel's precision (double for F64, float for F32,
 // interleaved bf16 hi/lo pairs for BF16X3).
-hipError_t launch_hpsi(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,
-                       const void* dense, const int32_t* gsrc, const double* gscale,
-                       const double* psi, double* y, double alpha, double beta,
-                       hipStream_t stream);
+// nslots workgroups; slot b takes tile order[b] (-1: idle); order == nullptr
+// means slot b takes tile b.  Every target block may have at most 32 segments.
+hipError_t launch_hpsi(int prec, int nslots, const int32_t* order, const TileDesc* tiles,
+                       const SegDesc* segs, const void* dense, const int32_t* gsrc,
+                       const double* gscale, const double* psi, double* y, double alpha,
+                       double beta, hipStream_t stream);
 
 // partial[tile * stride + s] = < G tile, segment s of the tile with c = 1 >
 hipError_t launch_term_dots(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,
@@ -55,6 +58,17 @@ hipError_t launch_combine(double* out, const double* V, int64_t ldv, int nv, con
 // dst = src * (1 / sqrt(*nrm2))   (the norm read on the device)
 hipError_t launch_normalise(double* dst, const double* src, const double* nrm2, int64_t n,
                             hipStream_t stream);
+
+// One fused CGS2 step of the Lanczos recursion against the nv basis vectors
+// V_0..V_{nv-1} (V_{nv-1} the current one): h1 = V^T w; w -= V h1;
+// h2 = V^T w; w -= V h2; ab[0] = h1[nv-1] + h2[nv-1] (alpha),
+// ab[1] = ||w|| (beta); vnext = w / beta (if vnext is not null).
+// partial needs nv * lz_blocks(n) doubles; counter one zeroed unsigned int
+// (left zeroed on return).
+int lz_blocks(int64_t n);
+hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
+                          double* h1, double* h2, double* partial, unsigned int* counter,
+                          double* ab, double* vnext, hipStream_t stream);
 
 // Record alpha_j = h1[j] + h2[j] and beta_j = sqrt(nrm2) into ab[2*it], ab[2*it+1].
 hipError_t launch_record(const double* h1, const double* h2, int j, const double* nrm2,

@@ -256,28 +256,45 @@ dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_targe
       plan.segs.push_back(sg);
     }
     plan.pair_nseg[p] = (int32_t)plan.segs.size() - plan.pair_seg0[p];
+    // matrix-core segments first, elementwise ones after (stable)
+    std::stable_partition(plan.segs.begin() + plan.pair_seg0[p], plan.segs.end(),
+                          [](const SegDesc& sg) { return sg.kind != SEG_GG; });
+    if (plan.pair_nseg[p] > 32) {
+      std::ostringstream os;
+      os << "target block " << p << " receives " << plan.pair_nseg[p]
+         << " terms; the fused kernel takes at most 32 per block";
+      err = os.str();
+      return DMRG_E_UNSUPPORTED;
+    }
   }
 
-  // tiles, most expensive first (list scheduling in dispatch order)
-  std::vector<std::pair<int64_t, int32_t>> order;
+  // tiles; each block's segments know where their chunks start
+  std::vector<int64_t> pair_cost(npairs, 0), tile_cost;
+  std::vector<int32_t> tile_pair;
   for (int32_t p = 0; p < npairs; ++p) {
     const int32_t a = plan.dS[plan.pair_s[p]], b = plan.dE[plan.pair_e[p]];
     int64_t cost = 0, kpad = 0;
+    int32_t nch = 0, ngemm = 0;
     for (int32_t s = 0; s < plan.pair_nseg[p]; ++s) {
-      const SegDesc& sg = plan.segs[plan.pair_seg0[p] + s];
+      SegDesc& sg = plan.segs[plan.pair_seg0[p] + s];
       const double c2 = 2.0 * a * b;
+      sg.ch0 = nch;
       if (sg.kind == SEG_GG) {
         cost += 2;
         plan.flops_alg += c2;
       } else {
-        const int64_t kp = (sg.K + kChunk - 1) / kChunk * kChunk;
-        kpad += kp;
-        cost += kp / kChunk * 4;
+        const int32_t c = (sg.K + kChunk - 1) / kChunk;
+        nch += c;
+        ++ngemm;
+        kpad += (int64_t)c * kChunk;
+        cost += 4 * c;
         plan.flops_alg += c2 * sg.K;
         const int32_t gathered = sg.kind == SEG_KN ? (sg.gB >= 0) : (sg.gA >= 0);
         if (gathered) plan.flops_alg += 2.0 * sg.K * (sg.kind == SEG_KN ? b : a);
       }
     }
+    // a tile's time is set by the chunks each of the workgroup's waves takes
+    const int64_t tcost = 8 + cost;
     for (int32_t m0 = 0; m0 < a; m0 += kTile)
       for (int32_t n0 = 0; n0 < b; n0 += kTile) {
         TileDesc t{};
@@ -288,20 +305,46 @@ dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_targe
         t.n0 = n0;
         t.seg0 = plan.pair_seg0[p];
         t.nseg = plan.pair_nseg[p];
-        order.push_back({cost, (int32_t)plan.tiles.size()});
+        t.nchunk = nch;
+        t.ngemm = ngemm;
         plan.tiles.push_back(t);
+        tile_cost.push_back(tcost);
+        tile_pair.push_back(p);
+        pair_cost[p] += tcost;
         plan.flops_exec += 2.0 * kTile * kTile * (double)kpad;
         plan.gemm_elems += kpad;
       }
   }
-  std::stable_sort(order.begin(), order.end(),
-                   [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
-                     return x.first > y.first;
-                   });
-  std::vector<TileDesc> sorted;
-  sorted.reserve(plan.tiles.size());
-  for (auto& o : order) sorted.push_back(plan.tiles[o.second]);
-  plan.tiles.swap(sorted);
+  // XCD-aware order: whole blocks go to one XCD (its L2 then holds the
+  // block's operators and psi), blocks spread over the XCDs by LPT on their
+  // cost, and inside an XCD tiles run most expensive first.  Slot b of the
+  // launch runs on XCD b % kXcds and takes the (b / kXcds)-th tile of it.
+  {
+    std::vector<int32_t> pidx(npairs);
+    for (int32_t p = 0; p < npairs; ++p) pidx[p] = p;
+    std::stable_sort(pidx.begin(), pidx.end(),
+                     [&](int32_t x, int32_t y) { return pair_cost[x] > pair_cost[y]; });
+    std::vector<int64_t> load(kXcds, 0);
+    std::vector<int32_t> xcd_of(npairs, 0);
+    for (int32_t p : pidx) {
+      int best = 0;
+      for (int x = 1; x < kXcds; ++x)
+        if (load[x] < load[best]) best = x;
+      xcd_of[p] = best;
+      load[best] += pair_cost[p];
+    }
+    std::vector<std::vector<int32_t>> lists(kXcds);
+    std::vector<int32_t> tidx(plan.tiles.size());
+    for (size_t t = 0; t < tidx.size(); ++t) tidx[t] = (int32_t)t;
+    std::stable_sort(tidx.begin(), tidx.end(),
+                     [&](int32_t x, int32_t y) { return tile_cost[x] > tile_cost[y]; });
+    for (int32_t t : tidx) lists[xcd_of[tile_pair[t]]].push_back(t);
+    size_t rows = 0;
+    for (auto& l : lists) rows = std::max(rows, l.size());
+    plan.order.assign(rows * kXcds, -1);
+    for (int x = 0; x < kXcds; ++x)
+      for (size_t r = 0; r < lists[x].size(); ++r) plan.order[r * kXcds + x] = lists[x][r];
+  }
   plan.bytes_dense = 8.0 * plan.dense.size();
   return DMRG_OK;
 }

@@ -37,6 +37,7 @@ struct SegDesc {
   int32_t gA;         // gather pool offset for output rows (-1: identity)
   int32_t gB;         // gather pool offset for output columns (-1: identity)
   int32_t term;       // term index k
+  int32_t ch0;        // index of this segment's first chunk in its block's chunk sequence
 };
 
 // One 32 x 32 output tile of one target block.
@@ -45,7 +46,11 @@ struct TileDesc {
   int32_t a, b;       // output block rows, columns
   int32_t m0, n0;     // tile origin inside the block
   int32_t seg0, nseg; // the block's segments
+  int32_t nchunk;     // contraction chunks over all of the block's matrix-core segments
+  int32_t ngemm;      // segments [seg0, seg0 + ngemm) are matrix-core ones, the rest elementwise
 };
+
+constexpr int kXcds = 8;     // MI355X: 8 XCDs; workgroup b runs on XCD b % 8
 
 constexpr int kTile = 32;    // output tile edge
 constexpr int kChunk = 16;   // contraction chunk
@@ -66,6 +71,7 @@ struct Plan {
   std::vector<SegDesc> segs;      // grouped by output pair
   std::vector<int32_t> pair_seg0, pair_nseg;
   std::vector<TileDesc> tiles;    // sorted by decreasing cost
+  std::vector<int32_t> order;     // workgroup slot -> tile (-1: idle), XCD-aware
   // staged operator data (FP64; converted at upload)
   std::vector<double> dense;      // dense pool
   std::vector<int32_t> gsrc;      // gather pool: source index (-1: zero row)

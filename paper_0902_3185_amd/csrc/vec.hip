@@ -132,6 +132,141 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused CGS2 passes for one Lanczos step.  Each kernel walks the Krylov basis
+// once; every block writes its partial sums, and the last block to finish
+// (counted with one device-scope atomic) adds them up in a fixed order and
+// resets the counter, so results are repeatable and no extra launch is needed.
+// ---------------------------------------------------------------------------
+constexpr int kLzThreads = 256;
+constexpr int kLzPer = 8;                       // elements per thread
+constexpr int kLzSpan = kLzThreads * kLzPer;    // elements per block
+
+int lz_blocks(int64_t n) { return (int)((n + kLzSpan - 1) / kLzSpan); }
+
+// Returns true in every thread of the block that finished last.
+__device__ inline bool last_block_done(unsigned int* counter) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int done = atomicAdd(counter, 1u);
+    last = done == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+// out[j] = sum_b partial[j * nblk + b] (b ascending), by the whole block.
+__device__ inline void reduce_partials(const double* partial, int nblk, int nv, double* out,
+                                       double* sh) {
+  for (int j = 0; j < nv; ++j) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kLzThreads) s += partial[(int64_t)j * nblk + b];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[j] = s;
+  }
+}
+
+// Mode 0: h1 = V^T w.
+// Mode 1: w -= V h1, then h2 = V^T w.
+// Mode 2: w -= V h2, then nrm = ||w||^2 and ab[0..1] = (h1[j] + h2[j], sqrt(nrm)).
+template <int kMode>
+__global__ __launch_bounds__(kLzThreads) void lz_pass(double* __restrict__ w,
+                                                      const double* __restrict__ V, int64_t ldv,
+                                                      int nv, int64_t n, double* __restrict__ h1,
+                                                      double* __restrict__ h2,
+                                                      double* __restrict__ partial,
+                                                      unsigned int* __restrict__ counter,
+                                                      double* __restrict__ ab) {
+  __shared__ double sh[4];
+  const int nblk = gridDim.x;
+  const int64_t base = (int64_t)blockIdx.x * kLzSpan + threadIdx.x;
+  double x[kLzPer];
+#pragma unroll
+  for (int q = 0; q < kLzPer; ++q) {
+    const int64_t i = base + (int64_t)q * kLzThreads;
+    x[q] = i < n ? w[i] : 0.0;
+  }
+  if (kMode >= 1) {
+    const double* h = kMode == 1 ? h1 : h2;
+    for (int j = 0; j < nv; ++j) {
+      const double hj = h[j];
+      const double* Vj = V + (int64_t)j * ldv;
+#pragma unroll
+      for (int q = 0; q < kLzPer; ++q) {
+        const int64_t i = base + (int64_t)q * kLzThreads;
+        if (i < n) x[q] -= hj * Vj[i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kLzPer; ++q) {
+      const int64_t i = base + (int64_t)q * kLzThreads;
+      if (i < n) w[i] = x[q];
+    }
+  }
+  if (kMode <= 1) {
+    for (int j = 0; j < nv; ++j) {
+      const double* Vj = V + (int64_t)j * ldv;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kLzPer; ++q) {
+        const int64_t i = base + (int64_t)q * kLzThreads;
+        if (i < n) s += Vj[i] * x[q];
+      }
+      s = block_sum(s, sh);
+      if (threadIdx.x == 0) partial[(int64_t)j * nblk + blockIdx.x] = s;
+    }
+  } else {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kLzPer; ++q) s += x[q] * x[q];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+  if (!last_block_done(counter)) return;
+  if (kMode == 2) {
+    __shared__ double nrm;
+    reduce_partials(partial, nblk, 1, &nrm, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      ab[0] = h1[nv - 1] + h2[nv - 1];
+      ab[1] = sqrt(nrm > 0.0 ? nrm : 0.0);
+    }
+  } else {
+    reduce_partials(partial, nblk, nv, kMode == 0 ? h1 : h2, sh);
+  }
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
+}
+
+// v_next = w / ab[1]
+__global__ __launch_bounds__(kThreads) void lz_normalise(double* __restrict__ v,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ ab,
+                                                         int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const double b = ab[1];
+  const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  if (i < n) v[i] = w[i] * inv;
+}
+
+hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
+                          double* h1, double* h2, double* partial, unsigned int* counter,
+                          double* ab, double* vnext, hipStream_t stream) {
+  const int nblk = lz_blocks(n);
+  hipLaunchKernelGGL(lz_pass<0>, dim3(nblk), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1, h2,
+                     partial, counter, ab);
+  hipLaunchKernelGGL(lz_pass<1>, dim3(nblk), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1, h2,
+                     partial, counter, ab);
+  hipLaunchKernelGGL(lz_pass<2>, dim3(nblk), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1, h2,
+                     partial, counter, ab);
+  if (vnext)
+    hipLaunchKernelGGL(lz_normalise, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       stream, vnext, w, ab, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_multi_dot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
                             double* partial, double* h, hipStream_t stream) {
   if (nv <= 0) return hipSuccess;
