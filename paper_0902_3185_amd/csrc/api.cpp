@@ -172,7 +172,11 @@ dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
   return DMRG_OK;
 }
 
-int kernel_prec(dmrg_prec p) { return p == DMRG_FP32 ? kPrecF32 : kPrecF64; }
+int kernel_prec(dmrg_prec p) {
+  return p == DMRG_FP32 ? kPrecF32 : (p == DMRG_BF16X3 ? kPrecBF16X3 : kPrecF64);
+}
+
+bool uses32(dmrg_prec p) { return p == DMRG_FP32 || p == DMRG_BF16X3; }
 
 hipError_t take_event(dmrg_ctx c, hipEvent_t* e) {
   if (!c->spare.empty()) {
@@ -211,9 +215,8 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
                          st.gscale.as<double>(), psi, y, alpha, beta, s));
     return DMRG_OK;
   }
-  if (prec == DMRG_BF16X3) return fail(DMRG_E_UNSUPPORTED, "BF16x3 product not built in this library");
   const void* dense = st.dense64.p;
-  if (prec == DMRG_FP32) {
+  if (uses32(prec)) {
     if (!st.has32) return fail(DMRG_E_ARG, "FP32 operators not staged (use dmrg_sb_set_prec)");
     dense = st.dense32.p;
   }
@@ -347,7 +350,6 @@ dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_
                                   dmrg_prec prec, dmrg_sb* out) {
   if (out == nullptr) return fail(DMRG_E_ARG, "null output pointer");
   if (prec < DMRG_FP64 || prec > DMRG_FP64_PLAIN) return fail(DMRG_E_ARG, "unknown precision");
-  if (prec == DMRG_BF16X3) return fail(DMRG_E_UNSUPPORTED, "BF16x3 product not built in this library");
   auto sb = std::make_unique<dmrg_sb_s>();
   std::string err;
   dmrg_status st = build_plan(S, E, q_target, nterms, terms, false, sb->fwd.plan, err);
@@ -372,7 +374,7 @@ dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_
   if (ctx) {
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(DMRG_E_DEVICE, "hipSetDevice failed");
-    if ((st = stage(ctx, sb->fwd, prec == DMRG_FP32)) != DMRG_OK) return st;
+    if ((st = stage(ctx, sb->fwd, uses32(prec))) != DMRG_OK) return st;
   }
   *out = sb.release();
   return DMRG_OK;
@@ -405,7 +407,7 @@ dmrg_status dmrg_sb_stats(dmrg_sb sb, double* flops_alg, double* flops_exec, dou
                           int32_t* ntiles) {
   if (!sb) return fail(DMRG_E_ARG, "null superblock");
   const Plan& p = sb->fwd.plan;
-  const int elem = sb->prec == DMRG_FP32 ? 4 : 8;
+  const int elem = uses32(sb->prec) ? 4 : 8;
   if (flops_alg) *flops_alg = p.flops_alg;
   if (flops_exec) *flops_exec = p.flops_exec;
   if (bytes_alg) *bytes_alg = plan_bytes_alg(p, elem);
@@ -434,8 +436,7 @@ dmrg_status dmrg_sb_set_coeffs(dmrg_sb sb, const double* c_h) {
 dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec) {
   if (!sb) return fail(DMRG_E_ARG, "null superblock");
   if (prec < DMRG_FP64 || prec > DMRG_FP64_PLAIN) return fail(DMRG_E_ARG, "unknown precision");
-  if (prec == DMRG_BF16X3) return fail(DMRG_E_UNSUPPORTED, "BF16x3 product not built in this library");
-  if (prec == DMRG_FP32 && sb->ctx && !sb->fwd.has32) {
+  if (uses32(prec) && sb->ctx && !sb->fwd.has32) {
     DeviceGuard g(sb->ctx->device);
     std::vector<float> f(sb->fwd.plan.dense.size());
     for (size_t i = 0; i < f.size(); ++i) f[i] = (float)sb->fwd.plan.dense[i];
@@ -477,7 +478,7 @@ dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d
       sb->adj = std::move(adj);
     }
     dmrg_prec p = sb->prec;
-    if (p == DMRG_FP32 && !sb->adj->has32) p = DMRG_FP64;
+    if (uses32(p) && !sb->adj->has32) p = DMRG_FP64;
     if ((st = run_product(sb, *sb->adj, p, g_d, gpsi_d, 1.0, 0.0)) != DMRG_OK) return st;
   }
   if (gc_h) {
@@ -486,7 +487,7 @@ dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d
     const int stride = std::max(1, f.max_nseg);
     DevBuf part;
     HIP_TRY(part.ensure((size_t)nt * stride * sizeof(double)));
-    const bool use32 = sb->prec == DMRG_FP32 && f.has32;
+    const bool use32 = uses32(sb->prec) && f.has32;
     HIP_TRY(launch_term_dots(use32 ? kPrecF32 : kPrecF64, nt, f.tiles.as<TileDesc>(),
                              f.segs.as<SegDesc>(), use32 ? f.dense32.p : f.dense64.p,
                              f.gsrc.as<int32_t>(), f.gscale.as<double>(), psi_d, g_d,

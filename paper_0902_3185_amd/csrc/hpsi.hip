@@ -16,6 +16,7 @@ namespace dmrg {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------------------
 // Per-precision contraction of one segment's chunks into a wave's 32x32 tile.
@@ -405,6 +406,88 @@ struct F64Tile {
   }
 };
 
+// BF16 hi/lo split on the matrix cores: v_mfma_f32_32x32x16_bf16, A[i][k]
+// from lane i + 32*(k/8), element k%8 (B likewise with column j); D as in the
+// FP32 32x32 layout.  Every FP32 operand x is split into hi = bf16(x) and
+// lo = bf16(x - hi); a product is hi*hi + hi*lo + lo*hi (the lo*lo term and
+// the rounding of lo leave a relative error of about 2^-16), accumulated in
+// FP32.  The operators are read from the FP32 pool and split on load.
+struct BF16Tile {
+  using op_t = float;
+  using red_t = float;
+  static constexpr int kWaves = 16;
+  struct Acc {
+    f32x16 d;
+  };
+  struct Regs {
+    bf16x8 ah, al, bh, bl;
+  };
+  __device__ static void zero(Acc& a) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a.d[r] = 0.f;
+  }
+  __device__ static void split(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const __bf16 h = (__bf16)x[j];
+      hi[j] = h;
+      lo[j] = (__bf16)(x[j] - (float)h);
+    }
+  }
+  __device__ static void load(Regs& R, const SegDesc& sg, const TileDesc& t, int ch, int si,
+                              const TileShared& sh, const op_t* dense, const double* psi,
+                              int lane) {
+    const int i = lane & 31, kh = lane >> 5;
+    const double* P = psi + sg.psi_off;
+    const int64_t ldp = sg.psi_ld;
+    const int32_t src = sh.gsrc[si][i];
+    const float scl = sh.gscl[si][i];
+    const int k0 = ch * kChunk + 8 * kh;
+    float a[8], b[8];
+    if (sg.kind == SEG_KN) {
+      const op_t* At = dense + sg.op_off;
+      const int64_t lda = sg.op_ld;
+      const int m = t.m0 + i;
+      const bool mok = m < t.a;
+      const bool nok = src >= 0;
+      const float cs = (float)sg.c;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + j;
+        const bool kok = k < sg.K;
+        a[j] = (mok && kok) ? cs * At[k * lda + m] : 0.f;
+        b[j] = (nok && kok) ? scl * (float)P[k * ldp + src] : 0.f;
+      }
+    } else {
+      const bool mok = src >= 0;
+      const double* Arow = P + (int64_t)(mok ? src : 0) * ldp;
+      const int n = t.n0 + i;
+      const bool nok = n < t.b;
+      const op_t* Brow = dense + sg.op_off + (int64_t)(nok ? n : 0) * sg.op_ld;
+      const float ca = (float)sg.c * scl;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const bool kok = k0 + j < sg.K;
+        a[j] = (mok && kok) ? ca * (float)Arow[k0 + j] : 0.f;
+        b[j] = (nok && kok) ? Brow[k0 + j] : 0.f;
+      }
+    }
+    split(a, R.ah, R.al);
+    split(b, R.bh, R.bl);
+  }
+  __device__ static void mma(Acc& acc, const Regs& R) {
+    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.ah, R.bh, acc.d, 0, 0, 0);
+    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.ah, R.bl, acc.d, 0, 0, 0);
+    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.al, R.bh, acc.d, 0, 0, 0);
+  }
+  static constexpr int kRegs = 16;
+  __device__ static float value(const Acc& a, int r) { return a.d[r]; }
+  __device__ static void coords(int lane, int r, int& row, int& col) {
+    row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    col = lane & 31;
+  }
+};
+
 // Matrix-core segment holding global chunk g of the tile.
 __device__ inline int seg_of_chunk(const SegDesc* segs, const TileDesc& t, int g) {
   int found = 0;
@@ -617,6 +700,10 @@ hipError_t launch_hpsi(int prec, int nslots, const int32_t* order, const TileDes
   if (prec == kPrecF32) {
     hipLaunchKernelGGL(hpsi_grouped<F32Tile>, dim3(nslots), dim3(F32Tile::kWaves * 64), 0, stream,
                        order, tiles, segs, (const float*)dense, gsrc, gscale, psi, y, alpha, beta);
+  } else if (prec == kPrecBF16X3) {
+    hipLaunchKernelGGL(hpsi_grouped<BF16Tile>, dim3(nslots), dim3(BF16Tile::kWaves * 64), 0,
+                       stream, order, tiles, segs, (const float*)dense, gsrc, gscale, psi, y, alpha,
+                       beta);
   } else {
     hipLaunchKernelGGL(hpsi_grouped<F64Tile>, dim3(nslots), dim3(F64Tile::kWaves * 64), 0, stream,
                        order, tiles, segs, (const double*)dense, gsrc, gscale, psi, y, alpha, beta);

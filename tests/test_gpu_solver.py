@@ -42,7 +42,7 @@ def _oracle_ground(desc, seed):
     return E, psi
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp64_plain"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp64_plain"])
 @pytest.mark.parametrize("name,m", [("heisenberg_L16_m32", None), ("hubbard_L64_U4_m512", 64),
                                     ("j1j2_L64_m256", 48)])
 def test_lanczos_energy(ctx, name, m, prec):
