@@ -230,6 +230,31 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
 dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int32_t m,
                               int32_t no_split, dmrg_trunc* out);
 
+/* One block of a basis change (Eq. (4) with (w)^-1 read as W^T, a truncated W
+ * having orthonormal columns):  out = Wr^T O Wc, where
+ *   O    rows x cols, row-major, at O_d + o_off
+ *   Wr   rows x kr,   row-major, at W_d + wr_off  (kept eigenvectors of the row sector)
+ *   Wc   cols x kc,   row-major, at W_d + wc_off  (kept eigenvectors of the column sector)
+ *   out  kr x kc,     row-major, at out_d + out_off                           */
+typedef struct {
+  int64_t o_off;
+  int32_t rows, cols;
+  int64_t wr_off;
+  int32_t kr;
+  int64_t wc_off;
+  int32_t kc;
+  int64_t out_off;
+} dmrg_tblock;
+
+/* Change the basis of block operators and truncate them (Sec. 1: H_S' and
+ * the other operators in the kept density-matrix eigenvectors; Eq. (4)),
+ * all blocks in two FP64 matrix-core launches (U = O^T Wr, out = U^T Wc).
+ * O_d, W_d, out_d are device FP64 buffers owned by the caller; blocks[] is
+ * host memory.  Asynchronous on the context's stream.  DMRG_E_ARG on a
+ * negative size or null pointer.                                             */
+dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock* blocks,
+                                  const double* O_d, const double* W_d, double* out_d);
+
 /* ---------------------------------------------------------------------- */
 /* Host utilities (no device needed): the FP64 eigen-solvers the library   */
 /* uses for the Lanczos tridiagonal matrix and the density-matrix blocks.  */

@@ -116,3 +116,9 @@ def truncate(sb, psi, side, m, no_split=False):
                 lam_sec=np.array([entries[k][3] for k in kept]),
                 W=W, straddle=straddle,
                 all_lam=np.array([e[0] for e in entries]))
+
+
+def transform_block(O, Wr, Wc):
+    """One block of the basis change, Eq. (4) with (w)^-1 read as W^T:
+    O_new = Wr^T O Wc, Wr / Wc the kept eigenvectors of the row / column sector."""
+    return Wr.T @ O @ Wc

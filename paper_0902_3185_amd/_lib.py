@@ -39,6 +39,12 @@ class dmrg_term(C.Structure):
                 ("group", C.c_int32)]
 
 
+class dmrg_tblock(C.Structure):
+    _fields_ = [("o_off", C.c_int64), ("rows", C.c_int32), ("cols", C.c_int32),
+                ("wr_off", C.c_int64), ("kr", C.c_int32), ("wc_off", C.c_int64), ("kc", C.c_int32),
+                ("out_off", C.c_int64)]
+
+
 class dmrg_trunc(C.Structure):
     _fields_ = [("trunc_err", C.c_double), ("kept", C.c_int32), ("straddle", C.c_int32),
                 ("lambda_", C.POINTER(C.c_double)), ("lambda_sec", C.POINTER(C.c_int32)),
@@ -70,6 +76,7 @@ _SIGS = {
     "dmrg_lanczos_ground": (C.c_int, [_P, _P, C.c_int32, C.c_double, _D, _P,
                                       C.POINTER(C.c_int32), _D]),
     "dmrg_rho_truncate": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(dmrg_trunc)]),
+    "dmrg_transform_blocks": (C.c_int, [_P, C.c_int32, C.POINTER(dmrg_tblock), _P, _P, _P]),
     "dmrg_host_sym_eigen": (C.c_int, [C.c_int32, _D, _D]),
     "dmrg_host_tridiag_lowest": (C.c_int, [C.c_int32, _D, _D, _D, _D]),
 }

@@ -98,6 +98,7 @@ struct OpCopy {
 struct dmrg_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  DevBuf tr_tiles, tr_segs, tr_tmp;   // basis-change scratch
   // optional per-launch timing of the product kernels (HIP events on `stream`)
   bool timing = false;
   struct Mark {
@@ -819,6 +820,87 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   out->nsec = nsec;
   out->kept_per_sec = sb->tr_kps.data();
   out->W = sb->tr_Wp.data();
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock* blocks,
+                                  const double* O_d, const double* W_d, double* out_d) {
+  if (!ctx) return fail(DMRG_E_ARG, "null context");
+  if (nblk < 0 || (nblk > 0 && (!blocks || !O_d || !W_d || !out_d))) return fail(DMRG_E_ARG, "bad argument");
+  if (nblk == 0) return DMRG_OK;
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = ctx->stream;
+  // stage 1: U_b = O_b^T Wr_b (cols x kr) in scratch; stage 2: out_b = U_b^T Wc_b
+  std::vector<TileDesc> tiles1, tiles2;
+  std::vector<SegDesc> segs;
+  std::vector<int64_t> uoff(nblk);
+  int64_t utot = 0;
+  for (int32_t b = 0; b < nblk; ++b) {
+    const dmrg_tblock& B = blocks[b];
+    if (B.rows < 0 || B.cols < 0 || B.kr < 0 || B.kc < 0) return fail(DMRG_E_ARG, "negative block size");
+    uoff[b] = utot;
+    utot += (int64_t)B.cols * B.kr;
+  }
+  for (int32_t b = 0; b < nblk; ++b) {
+    const dmrg_tblock& B = blocks[b];
+    if (B.rows == 0 || B.cols == 0 || B.kr == 0 || B.kc == 0) continue;
+    for (int stage = 0; stage < 2; ++stage) {
+      SegDesc sg{};
+      sg.kind = SEG_KN;
+      sg.c = 1.0;
+      sg.gA = -1;
+      sg.gB = -1;
+      sg.ch0 = 0;
+      TileDesc t{};
+      if (stage == 0) {   // U[m][n] = sum_k O[k][m] Wr[k][n]
+        sg.K = B.rows;
+        sg.op_off = B.o_off;
+        sg.op_ld = B.cols;
+        sg.psi_off = B.wr_off;
+        sg.psi_ld = B.kr;
+        sg.psi_rows = B.rows;
+        t.y_off = uoff[b];
+        t.a = B.cols;
+        t.b = B.kr;
+      } else {            // out[m][n] = sum_k U[k][m] Wc[k][n]
+        sg.K = B.cols;
+        sg.op_off = uoff[b];
+        sg.op_ld = B.kr;
+        sg.psi_off = B.wc_off;
+        sg.psi_ld = B.kc;
+        sg.psi_rows = B.cols;
+        t.y_off = B.out_off;
+        t.a = B.kr;
+        t.b = B.kc;
+      }
+      t.seg0 = (int32_t)segs.size();
+      t.nseg = 1;
+      t.ngemm = 1;
+      t.nchunk = (sg.K + kChunk - 1) / kChunk;
+      segs.push_back(sg);
+      std::vector<TileDesc>& tl = stage == 0 ? tiles1 : tiles2;
+      for (int32_t m0 = 0; m0 < t.a; m0 += kTile)
+        for (int32_t n0 = 0; n0 < t.b; n0 += kTile) {
+          TileDesc tt = t;
+          tt.m0 = m0;
+          tt.n0 = n0;
+          tl.push_back(tt);
+        }
+    }
+  }
+  const size_t n1 = tiles1.size(), n2 = tiles2.size();
+  std::vector<TileDesc> all(tiles1);
+  all.insert(all.end(), tiles2.begin(), tiles2.end());
+  dmrg_status st;
+  if ((st = upload(ctx->tr_tiles, all.data(), all.size() * sizeof(TileDesc), s)) != DMRG_OK) return st;
+  if ((st = upload(ctx->tr_segs, segs.data(), segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return st;
+  HIP_TRY(ctx->tr_tmp.ensure((size_t)std::max<int64_t>(utot, 1) * sizeof(double)));
+  const TileDesc* dt = ctx->tr_tiles.as<TileDesc>();
+  HIP_TRY(launch_hpsi(kPrecF64, (int)n1, nullptr, dt, ctx->tr_segs.as<SegDesc>(), O_d, nullptr,
+                      nullptr, W_d, ctx->tr_tmp.as<double>(), 1.0, 0.0, s));
+  HIP_TRY(launch_hpsi(kPrecF64, (int)n2, nullptr, dt + n1, ctx->tr_segs.as<SegDesc>(),
+                      ctx->tr_tmp.as<double>(), nullptr, nullptr, W_d, out_d, 1.0, 0.0, s));
+  HIP_TRY(hipStreamSynchronize(s));   // the host tile lists die here
   return DMRG_OK;
 }
 

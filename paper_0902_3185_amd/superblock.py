@@ -52,6 +52,21 @@ class Context:
         check(lib().dmrg_ctx_timing(self.handle, PREC[prec], C.byref(ms), C.byref(n), int(bool(reset))))
         return ms.value, n.value
 
+    def transform_blocks(self, blocks, O, W, out):
+        """dmrg_transform_blocks: out_b = Wr_b^T O_b Wc_b for every block.
+
+        ``blocks`` is a list of dicts with o_off, rows, cols, wr_off, kr,
+        wc_off, kc, out_off (element offsets into the float64 CUDA tensors
+        O, W, out)."""
+        n = len(blocks)
+        arr = (_lib.dmrg_tblock * max(1, n))()
+        for i, b in enumerate(blocks):
+            arr[i] = _lib.dmrg_tblock(int(b["o_off"]), int(b["rows"]), int(b["cols"]),
+                                      int(b["wr_off"]), int(b["kr"]), int(b["wc_off"]),
+                                      int(b["kc"]), int(b["out_off"]))
+        check(lib().dmrg_transform_blocks(self.handle, n, arr, _ptr(O), _ptr(W), _ptr(out)))
+        return out
+
     def close(self):
         if getattr(self, "handle", None) and _lib.alive():
             lib().dmrg_ctx_destroy(self.handle)

@@ -210,3 +210,30 @@ def test_tie_break_and_no_split():
     assert tr["kept"] == 4 and abs(tr["eps"]) < 1e-15
     tr = OR.truncate(sb, psi, 0, 1, no_split=True)
     assert tr["kept"] == 2 and abs(tr["eps"] - 0.4) < 1e-14
+
+
+def test_basis_change_block_identities():
+    """Eq. (4) and the remark after it: for a square orthogonal W the change
+    of basis is a similarity (spectra kept, products commute with it); for a
+    truncated W, (W^T A W)(W^T B W) != W^T (A B) W while W^T W = 1."""
+    rng = np.random.default_rng(3)
+    n, k = 12, 5
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    B = rng.standard_normal((n, n))
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    At = OR.transform_block(A, Q, Q)
+    assert np.allclose(np.linalg.eigvalsh(At), np.linalg.eigvalsh(A))
+    assert np.allclose(OR.transform_block(A, Q, Q) @ OR.transform_block(B, Q, Q),
+                       OR.transform_block(A @ B, Q, Q))
+    W = Q[:, :k]
+    assert np.allclose(W.T @ W, np.eye(k))
+    lhs = OR.transform_block(A, W, W) @ OR.transform_block(B, W, W)
+    assert not np.allclose(lhs, OR.transform_block(A @ B, W, W))
+    # entry by entry
+    Wr, Wc = Q[:, :k], Q[:, 2:2 + 3]
+    T = OR.transform_block(B, Wr, Wc)
+    for i in range(k):
+        for j in range(3):
+            assert abs(T[i, j] - sum(Wr[a, i] * B[a, b] * Wc[b, j]
+                                     for a in range(n) for b in range(n))) < 1e-12
