@@ -1,0 +1,453 @@
+"""Whole-run DMRG on top of libdmrg: the infinite loop of the paper's
+Sec. 3.1 (Fig. 2) and the finite sweeps of Sec. 1.
+
+Host bookkeeping (the paper's ``grow`` / ``setToProduct``, Sec. 3.3) keeps
+block operators block-sparse by effective quantum number (Sec. 3.2): a grown
+block S' = S (x) x is a list of "runs" -- one per (S sector, site state) with
+q_S + q_x fixed -- and every product operator A (x) a is assembled from
+A's sector blocks scaled by a's entries, run by run.  Everything on the
+superblock goes through the library: the product, the Lanczos ground state
+(FP64, or FP32 products with FP64 cycles), the density-matrix truncation,
+and the change of basis of the block Hamiltonian and carried operators
+(Eq. (4)) on the GPU.
+
+Readings (shared with the oracle, stated in the repository's design notes):
+the infinite-phase superblock of n sites is the open n-site system; right
+blocks label sites by distance from the right end; a finite sweep goes
+p = L/2 -> L-2 (truncate S'), L-2 -> 2 (truncate E'), 2 -> L/2; fermion
+signs by Jordan-Wigner order with the left part's parity on bond terms.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Models (Sec. 4.1) and geometries (Sec. 4.2)
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class SiteModel:
+    """One-site basis and operators of a model, states in increasing q."""
+    name: str
+    qsite: object            # function Q -> effective q of each state
+    parity: np.ndarray       # +1 / -1 fermion parity per state (all +1 for spins)
+    onsite: np.ndarray       # d x d one-site Hamiltonian
+    ops: dict                # carried one-site operators, name -> d x d
+    bond: list               # [(factor, left, left_T, right, right_T, fmode)]
+    bonds: object            # L -> [(i, j, value, group)]
+    target: object           # n -> (N_up, N_down)
+    fermionic: bool = False
+
+    @property
+    def d(self):
+        return self.onsite.shape[0]
+
+
+def heisenberg(bonds):
+    """Spin-1/2 sum J S_i.S_j; states (down, up), q = N_up."""
+    sz = np.diag([-0.5, 0.5])
+    spl = np.array([[0.0, 0.0], [1.0, 0.0]])      # S+|down> = |up>
+    return SiteModel(
+        name="heisenberg", qsite=lambda Q: np.array([0, 1]), parity=np.ones(2),
+        onsite=np.zeros((2, 2)), ops={"Sz": sz, "Sp": spl},
+        bond=[(1.0, "Sz", False, "Sz", False, ""), (0.5, "Sp", False, "Sp", True, ""),
+              (0.5, "Sp", True, "Sp", False, "")],
+        bonds=bonds, target=lambda n: (n // 2, 0))
+
+
+def hubbard(U, t=1.0):
+    """Hubbard t (c^dag c + h.c.) + U n_up n_dn; states (e, up, down, updown)
+    with q = N_up + Q N_down, |updown> = c^dag_up c^dag_down |e>."""
+    cu = np.zeros((4, 4))
+    cd = np.zeros((4, 4))
+    cu[0, 1] = cu[2, 3] = 1.0
+    cd[0, 2] = 1.0
+    cd[1, 3] = -1.0
+    nu, nd = cu.T @ cu, cd.T @ cd
+    bond = []
+    for s in ("cu", "cd"):
+        bond.append((1.0, s, True, s, False, "OF"))
+        bond.append((1.0, s, False, s, True, "FO"))
+    return SiteModel(
+        name="hubbard", qsite=lambda Q: np.array([0, 1, Q, Q + 1]),
+        parity=np.array([1.0, -1.0, -1.0, 1.0]), onsite=U * (nu @ nd),
+        ops={"cu": cu, "cd": cd}, bond=bond,
+        bonds=lambda L: [(i, i + 1, float(t), 0) for i in range(L - 1)],
+        target=lambda n: (n // 2, n // 2), fermionic=True)
+
+
+def chain(J=1.0):
+    return lambda L: [(i, i + 1, float(J), 0) for i in range(L - 1)]
+
+
+def j1j2(J1, J2):
+    return lambda L: sorted([(i, i + 1, float(J1), 0) for i in range(L - 1)]
+                            + [(i, i + 2, float(J2), 1) for i in range(L - 2)])
+
+
+def ladder(j_leg=1.0, j_rung=1.0):
+    """Two legs, sites numbered rung by rung (site = 2x + y); rungs group 0, legs 1."""
+    def f(L):
+        W = L // 2
+        b = [(2 * x, 2 * x + 1, float(j_rung), 0) for x in range(W)]
+        b += [(2 * x + y, 2 * x + 2 + y, float(j_leg), 1) for x in range(W - 1) for y in range(2)]
+        return sorted(b)
+    return f
+
+
+# ---------------------------------------------------------------------------
+# Block-sparse operators
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class Basis:
+    q: np.ndarray            # sector q, strictly increasing
+    dim: np.ndarray          # sector sizes
+
+
+@dataclass
+class Op:
+    delta: int
+    blocks: dict             # (row sector, col sector) -> dense block
+
+    def transpose(self):
+        return Op(-self.delta, {(c, r): b.T.copy() for (r, c), b in self.blocks.items()})
+
+    def scaled(self, rows=None, cols=None):
+        """Multiply block (r, c) by rows[r] * cols[c] (per-sector scalars)."""
+        out = {}
+        for (r, c), b in self.blocks.items():
+            f = (1.0 if rows is None else rows[r]) * (1.0 if cols is None else cols[c])
+            out[(r, c)] = f * b
+        return Op(self.delta, out)
+
+
+def add_into(acc, op, c=1.0):
+    for k, b in op.blocks.items():
+        if k in acc:
+            acc[k] = acc[k] + c * b
+        else:
+            acc[k] = c * b
+
+
+@dataclass
+class Block:
+    labels: list
+    basis: Basis
+    H: dict                  # group -> {(r, r): block}
+    ops: dict = field(default_factory=dict)   # (label, name) -> Op
+
+
+def site_block(model, label, Q):
+    q = model.qsite(Q)
+    order = np.argsort(q, kind="stable")
+    qs = q[order]
+    if len(np.unique(qs)) != len(qs):
+        raise ValueError("one-site states must have distinct quantum numbers")
+    basis = Basis(qs.astype(np.int64), np.ones(len(qs), dtype=np.int64))
+    H = {-1: {(i, i): model.onsite[order][:, order][i:i + 1, i:i + 1].copy()
+              for i in range(len(qs)) if model.onsite[order[i], order[i]] != 0.0}}
+    ops = {}
+    for name, o in model.ops.items():
+        oo = o[np.ix_(order, order)]
+        blocks = {(i, j): oo[i:i + 1, j:j + 1].copy() for i in range(len(qs)) for j in range(len(qs))
+                  if oo[i, j] != 0.0}
+        deltas = {int(qs[i] - qs[j]) for (i, j) in blocks}
+        ops[(label, name)] = Op(deltas.pop() if deltas else 0, blocks)
+    return Block([label], basis, H, ops)
+
+
+def sector_parity(basis, Q, fermionic):
+    if not fermionic:
+        return np.ones(len(basis.q))
+    n = basis.q % Q + basis.q // Q
+    return np.where(n % 2 == 0, 1.0, -1.0)
+
+
+class Product:
+    """The basis of L (x) R, reordered by q: per product sector, its runs
+    (left sector, right sector, offset) in product order."""
+
+    def __init__(self, left: Basis, right: Basis, left_major=True):
+        self.left, self.right = left, right
+        runs = {}
+        for a in range(len(left.q)):
+            for b in range(len(right.q)):
+                runs.setdefault(int(left.q[a] + right.q[b]), []).append((a, b))
+        qs = sorted(runs)
+        self.basis = Basis(np.array(qs, dtype=np.int64), np.zeros(len(qs), dtype=np.int64))
+        self.runs = []
+        for s, qq in enumerate(qs):
+            # product order: left index major (left_major) -- runs of one
+            # sector in left-sector order; each run is dim(a) * dim(b) states
+            rr = sorted(runs[qq]) if left_major else sorted(runs[qq], key=lambda t: (t[1], t[0]))
+            off = 0
+            lst = []
+            for (a, b) in rr:
+                lst.append((a, b, off))
+                off += int(left.dim[a] * right.dim[b])
+            self.runs.append(lst)
+            self.basis.dim[s] = off
+        self.index = {qq: s for s, qq in enumerate(qs)}
+
+    def kron(self, A, a):
+        """(A (x) a) on the product basis; A on the left part, a on the right
+        (None: identity).  Both Op, or None."""
+        L, R = self.left, self.right
+        dA = 0 if A is None else A.delta
+        da = 0 if a is None else a.delta
+        Ab = None if A is None else A.blocks
+        ab = None if a is None else a.blocks
+        out = {}
+        for s_out, runs_out in enumerate(self.runs):
+            q_in = int(self.basis.q[s_out]) - dA - da
+            s_in = self.index.get(q_in)
+            if s_in is None:
+                continue
+            blk = None
+            for (a1, b1, o1) in runs_out:
+                for (a2, b2, o2) in self.runs[s_in]:
+                    if Ab is None:
+                        if a1 != a2:
+                            continue
+                        Lb = None
+                    else:
+                        Lb = Ab.get((a1, a2))
+                        if Lb is None:
+                            continue
+                    if ab is None:
+                        if b1 != b2:
+                            continue
+                        Rb = None
+                    else:
+                        Rb = ab.get((b1, b2))
+                        if Rb is None:
+                            continue
+                    if Lb is None:
+                        Lb = np.eye(int(L.dim[a1]))
+                    if Rb is None:
+                        Rb = np.eye(int(R.dim[b1]))
+                    sub = np.kron(Lb, Rb)
+                    if blk is None:
+                        blk = np.zeros((int(self.basis.dim[s_out]), int(self.basis.dim[s_in])))
+                    blk[o1:o1 + sub.shape[0], o2:o2 + sub.shape[1]] += sub
+            if blk is not None and np.any(blk != 0.0):
+                out[(s_out, s_in)] = blk
+        return Op(dA + da, out)
+
+
+def _op(block, label, name, transpose):
+    o = block.ops[(label, name)]
+    return o.transpose() if transpose else o
+
+
+def _bond_terms(model, left, right, label_l, label_r, value, Q):
+    """[(c, A, B)] of one bond between a left and a right part."""
+    Fl = sector_parity(left.basis, Q, model.fermionic)
+    out = []
+    for (f, ln, lt, rn, rt, fm) in model.bond:
+        A = _op(left, label_l, ln, lt)
+        if fm == "OF":
+            A = A.scaled(cols=Fl)
+        elif fm == "FO":
+            A = A.scaled(rows=Fl)
+        out.append((value * f, A, _op(right, label_r, rn, rt)))
+    return out
+
+
+def grow_right(S, model, Q, bonds, keep):
+    """S' = S (x) x (Fig. 2(a))."""
+    x = max(S.labels) + 1
+    site = site_block(model, x, Q)
+    P = Product(S.basis, site.basis, left_major=True)
+    H = {}
+    for g, blocks in S.H.items():
+        H.setdefault(g, {})
+        add_into(H[g], P.kron(Op(0, blocks), None))
+    for g, blocks in site.H.items():
+        H.setdefault(g, {})
+        add_into(H[g], P.kron(None, Op(0, blocks)))
+    for (i, j, v, g) in bonds:
+        if j == x and i in S.labels:
+            H.setdefault(g, {})
+            for (c, A, B) in _bond_terms(model, S, site, i, x, v, Q):
+                add_into(H[g], P.kron(A, B), c)
+    FS = Op(0, {(r, r): np.diag(np.full(int(S.basis.dim[r]), f))
+                for r, f in enumerate(sector_parity(S.basis, Q, model.fermionic))})
+    ops = {}
+    for (lab, name), o in S.ops.items():
+        if lab > x - keep:
+            ops[(lab, name)] = P.kron(o, None)
+    for (lab, name), o in site.ops.items():
+        ops[(lab, name)] = P.kron(FS if model.fermionic else None, o)
+    return Block(S.labels + [x], P.basis, H, ops)
+
+
+def grow_left(E, model, Q, n, bonds, keep):
+    """E' = y (x) E (Fig. 2(b)); labels are distances from the right end."""
+    r = max(E.labels) + 1
+    site = site_block(model, r, Q)
+    P = Product(site.basis, E.basis, left_major=True)
+    H = {}
+    for g, blocks in site.H.items():
+        H.setdefault(g, {})
+        add_into(H[g], P.kron(Op(0, blocks), None))
+    for g, blocks in E.H.items():
+        H.setdefault(g, {})
+        add_into(H[g], P.kron(None, Op(0, blocks)))
+    py = n - 1 - r
+    for (i, j, v, g) in bonds:
+        if i == py and (n - 1 - j) in E.labels:
+            H.setdefault(g, {})
+            for (c, A, B) in _bond_terms(model, site, E, r, n - 1 - j, v, Q):
+                add_into(H[g], P.kron(A, B), c)
+    Fy = Op(0, {(k, k): np.full((1, 1), f)
+                for k, f in enumerate(sector_parity(site.basis, Q, model.fermionic))})
+    ops = {}
+    for (lab, name), o in site.ops.items():
+        ops[(lab, name)] = P.kron(o, None)
+    for (lab, name), o in E.ops.items():
+        if lab > r - keep:
+            ops[(lab, name)] = P.kron(Fy if model.fermionic else None, o)
+    return Block(E.labels + [r], P.basis, H, ops)
+
+
+def _as_desc_op(op):
+    return None if op is None else dict(delta=int(op.delta),
+                                         blocks=[(r, c, b) for (r, c), b in sorted(op.blocks.items())])
+
+
+def superblock(Sp, Ep, model, Q, n, bonds, q_target):
+    """Superblock description (terms H_S'(x)I, I(x)H_E' per group, bonds across)."""
+    terms = []
+    for g in sorted(Sp.H):
+        if Sp.H[g]:
+            terms.append(dict(c=1.0, A=_as_desc_op(Op(0, Sp.H[g])), B=None, group=g))
+    for g in sorted(Ep.H):
+        if Ep.H[g]:
+            terms.append(dict(c=1.0, A=None, B=_as_desc_op(Op(0, Ep.H[g])), group=g))
+    for (i, j, v, g) in bonds:
+        if i in Sp.labels and (n - 1 - j) in Ep.labels:
+            for (c, A, B) in _bond_terms(model, Sp, Ep, i, n - 1 - j, v, Q):
+                terms.append(dict(c=c, A=_as_desc_op(A), B=_as_desc_op(B), group=g))
+    return dict(S=dict(q=Sp.basis.q, dim=Sp.basis.dim), E=dict(q=Ep.basis.q, dim=Ep.basis.dim),
+                q_target=int(q_target), terms=terms)
+
+
+def change_basis(ctx, block, tr):
+    """Truncate a grown block with the kept eigenvectors (Eq. (4)), on the GPU."""
+    import torch
+    W = tr["W"]
+    keep_secs = sorted(W)
+    new_index = {s: k for k, s in enumerate(keep_secs)}
+    basis = Basis(np.array([block.basis.q[s] for s in keep_secs], dtype=np.int64),
+                  np.array([W[s].shape[1] for s in keep_secs], dtype=np.int64))
+    # every operator block whose row and column sectors survive
+    items = []
+    for g, blocks in block.H.items():
+        for (r, c), b in blocks.items():
+            items.append((("H", g), (r, c), b))
+    for key, op in block.ops.items():
+        for (r, c), b in op.blocks.items():
+            items.append((("O", key), (r, c), b))
+    items = [it for it in items if it[1][0] in W and it[1][1] in W]
+    Wflat, woff = [], {}
+    off = 0
+    for s in keep_secs:
+        woff[s] = off
+        Wflat.append(W[s].reshape(-1))
+        off += W[s].size
+    Oflat, tbl = [], []
+    o_off = out_off = 0
+    for (_, (r, c), b) in items:
+        tbl.append(dict(o_off=o_off, rows=b.shape[0], cols=b.shape[1], wr_off=woff[r],
+                        kr=W[r].shape[1], wc_off=woff[c], kc=W[c].shape[1], out_off=out_off))
+        Oflat.append(b.reshape(-1))
+        o_off += b.size
+        out_off += W[r].shape[1] * W[c].shape[1]
+    new = Block(list(block.labels), basis, {g: {} for g in block.H},
+                {k: Op(op.delta, {}) for k, op in block.ops.items()})
+    if not items:
+        return new
+    dO = torch.tensor(np.concatenate(Oflat), dtype=torch.float64, device="cuda")
+    dW = torch.tensor(np.concatenate(Wflat), dtype=torch.float64, device="cuda")
+    out = torch.empty(out_off, dtype=torch.float64, device="cuda")
+    ctx.transform_blocks(tbl, dO, dW, out)
+    res = out.cpu().numpy()
+    for (kind, (r, c), _), t in zip(items, tbl):
+        blk = res[t["out_off"]:t["out_off"] + t["kr"] * t["kc"]].reshape(t["kr"], t["kc"])
+        key = (new_index[r], new_index[c])
+        if kind[0] == "H":
+            new.H[kind[1]][key] = blk.copy()
+        else:
+            new.ops[kind[1]].blocks[key] = blk.copy()
+    return new
+
+
+def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=2000,
+        no_split=True, keep_range=None, on_step=None):
+    """Infinite phase to L sites, then ``sweeps`` finite sweeps (Secs. 1, 3.1).
+
+    ``init(D, step)`` gives the Lanczos start vector of each step (numpy).
+    Returns a list of per-step records.
+    """
+    import torch
+
+    from .superblock import Context, Superblock
+    if ctx is None:
+        ctx = Context(0)
+    Q = L + 1
+    if keep_range is None:
+        keep_range = max(j - i for (i, j, _v, _g) in model.bonds(L))
+    left = {1: site_block(model, 0, Q)}
+    right = {1: site_block(model, 0, Q)}
+    log = []
+    step = [0]
+
+    def solve(Sp, Ep, n, sides, phase, p):
+        bonds = model.bonds(n)
+        nu, nd = model.target(n)
+        desc = superblock(Sp, Ep, model, Q, n, bonds, nu + Q * nd)
+        sb = Superblock(desc, prec=prec, ctx=ctx)
+        psi0 = torch.tensor(init(sb.D, step[0]), dtype=torch.float64, device="cuda")
+        r = sb.lanczos(psi0, max_iter=max_iter, tol=tol)
+        rec = dict(phase=phase, n=n, p=p, energy=r["energy"], iters=r["iters"],
+                   resid=r["resid"], D=sb.D, dimS=int(np.sum(Sp.basis.dim)),
+                   dimE=int(np.sum(Ep.basis.dim)), step=step[0])
+        out = {}
+        for side in sides:
+            tr = sb.rho_truncate(r["psi"], side, m, no_split=no_split)
+            rec["eps%d" % side] = tr["eps"]
+            rec["straddle%d" % side] = tr["straddle"]
+            out[side] = change_basis(ctx, Sp if side == 0 else Ep, tr)
+        if on_step is not None:
+            on_step(rec, desc, r)
+        log.append(rec)
+        sb.close()
+        step[0] += 1
+        return out
+
+    for n in range(4, L + 1, 2):
+        h = n // 2
+        bonds = model.bonds(n)
+        Sp = grow_right(left[h - 1], model, Q, bonds, keep_range)
+        Ep = grow_left(right[h - 1], model, Q, n, bonds, keep_range)
+        out = solve(Sp, Ep, n, (0, 1), "infinite", h)
+        left[h], right[h] = out[0], out[1]
+    bonds = model.bonds(L)
+    for _ in range(sweeps):
+        path = ([(p, 0) for p in range(L // 2, L - 1)] + [(p, 1) for p in range(L - 2, 1, -1)]
+                + [(p, 0) for p in range(2, L // 2 + 1)])
+        for (p, side) in path:
+            Sp = grow_right(left[p - 1], model, Q, bonds, keep_range)
+            Ep = grow_left(right[L - p - 1], model, Q, L, bonds, keep_range)
+            out = solve(Sp, Ep, L, (side,), "finite", p)
+            if side == 0:
+                left[p] = out[0]
+            else:
+                right[L - p] = out[1]
+    return log
