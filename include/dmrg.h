@@ -232,10 +232,13 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
 
 /* One block of a basis change (Eq. (4) with (w)^-1 read as W^T, a truncated W
  * having orthonormal columns):  out = Wr^T O Wc, where
- *   O    rows x cols, row-major, at O_d + o_off
+ *   O    rows x cols, row stride o_ld (0: cols), at O_d + o_off
  *   Wr   rows x kr,   row-major, at W_d + wr_off  (kept eigenvectors of the row sector)
  *   Wc   cols x kc,   row-major, at W_d + wc_off  (kept eigenvectors of the column sector)
- *   out  kr x kc,     row-major, at out_d + out_off                           */
+ *   out  kr x kc,     row stride out_ld (0: kc), at out_d + out_off
+ * (The strides let O be a column slice of a larger block and out a slice of
+ * a psi block, as the wave-function transformation between DMRG steps
+ * needs.)                                                                    */
 typedef struct {
   int64_t o_off;
   int32_t rows, cols;
@@ -244,6 +247,7 @@ typedef struct {
   int64_t wc_off;
   int32_t kc;
   int64_t out_off;
+  int32_t o_ld, out_ld;
 } dmrg_tblock;
 
 /* Change the basis of block operators and truncate them (Sec. 1: H_S' and

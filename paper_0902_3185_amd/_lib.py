@@ -42,7 +42,7 @@ class dmrg_term(C.Structure):
 class dmrg_tblock(C.Structure):
     _fields_ = [("o_off", C.c_int64), ("rows", C.c_int32), ("cols", C.c_int32),
                 ("wr_off", C.c_int64), ("kr", C.c_int32), ("wc_off", C.c_int64), ("kc", C.c_int32),
-                ("out_off", C.c_int64)]
+                ("out_off", C.c_int64), ("o_ld", C.c_int32), ("out_ld", C.c_int32)]
 
 
 class dmrg_trunc(C.Structure):

@@ -167,6 +167,7 @@ dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
     t.y_off = p.pair_off[q];
     t.a = p.dS[p.pair_s[q]];
     t.b = p.dE[p.pair_e[q]];
+    t.ldy = t.b;
     for (int32_t k = 0; k < p.pair_nseg[q]; ++k) st.plain.push_back({p.segs[p.pair_seg0[q] + k], t});
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -683,6 +684,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
         t.nseg = 1;
         t.nchunk = (sg.K + kChunk - 1) / kChunk;
         t.ngemm = 1;
+        t.ldy = n;
         tiles.push_back(t);
       }
     total += (int64_t)n * n;
@@ -838,6 +840,8 @@ dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock*
   for (int32_t b = 0; b < nblk; ++b) {
     const dmrg_tblock& B = blocks[b];
     if (B.rows < 0 || B.cols < 0 || B.kr < 0 || B.kc < 0) return fail(DMRG_E_ARG, "negative block size");
+    if ((B.o_ld > 0 && B.o_ld < B.cols) || (B.out_ld > 0 && B.out_ld < B.kc))
+      return fail(DMRG_E_ARG, "leading dimension smaller than the block width");
     uoff[b] = utot;
     utot += (int64_t)B.cols * B.kr;
   }
@@ -855,13 +859,14 @@ dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock*
       if (stage == 0) {   // U[m][n] = sum_k O[k][m] Wr[k][n]
         sg.K = B.rows;
         sg.op_off = B.o_off;
-        sg.op_ld = B.cols;
+        sg.op_ld = B.o_ld > 0 ? B.o_ld : B.cols;
         sg.psi_off = B.wr_off;
         sg.psi_ld = B.kr;
         sg.psi_rows = B.rows;
         t.y_off = uoff[b];
         t.a = B.cols;
         t.b = B.kr;
+        t.ldy = B.kr;
       } else {            // out[m][n] = sum_k U[k][m] Wc[k][n]
         sg.K = B.cols;
         sg.op_off = uoff[b];
@@ -872,6 +877,7 @@ dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock*
         t.y_off = B.out_off;
         t.a = B.kr;
         t.b = B.kc;
+        t.ldy = B.out_ld > 0 ? B.out_ld : B.kc;
       }
       t.seg0 = (int32_t)segs.size();
       t.nseg = 1;

@@ -578,7 +578,7 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_grouped(
     v += gg[e];
     for (int q = kMaxGG; q < ngg; ++q) v += gg_term(segs[t.seg0 + t.ngemm + q], t, m, n, gsrc, gscale, psi);
     if (m < t.a && n < t.b) {
-      const int64_t idx = t.y_off + (int64_t)m * t.b + n;
+      const int64_t idx = t.y_off + (int64_t)m * t.ldy + n;
       y[idx] = beta == 0.0 ? alpha * v : alpha * v + beta * y[idx];
     }
   }

@@ -307,6 +307,7 @@ dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_targe
         t.nseg = plan.pair_nseg[p];
         t.nchunk = nch;
         t.ngemm = ngemm;
+        t.ldy = b;
         plan.tiles.push_back(t);
         tile_cost.push_back(tcost);
         tile_pair.push_back(p);

@@ -48,6 +48,8 @@ struct TileDesc {
   int32_t seg0, nseg; // the block's segments
   int32_t nchunk;     // contraction chunks over all of the block's matrix-core segments
   int32_t ngemm;      // segments [seg0, seg0 + ngemm) are matrix-core ones, the rest elementwise
+  int32_t ldy;        // row stride of the output block (b for psi blocks)
+  int32_t pad;
 };
 
 constexpr int kXcds = 8;     // MI355X: 8 XCDs; workgroup b runs on XCD b % 8

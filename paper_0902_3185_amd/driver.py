@@ -23,6 +23,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+DEVICE = "cuda"   # where the driver keeps psi and staging buffers
+
 # ---------------------------------------------------------------------------
 # Models (Sec. 4.1) and geometries (Sec. 4.2)
 # ---------------------------------------------------------------------------
@@ -140,6 +142,10 @@ class Block:
     basis: Basis
     H: dict                  # group -> {(r, r): block}
     ops: dict = field(default_factory=dict)   # (label, name) -> Op
+    # how a truncated block came about: the grown product it was cut from and,
+    # per kept sector k, (product sector, kept eigenvectors dim x kept)
+    origin: object = None
+    product: object = None   # for a grown block: its Product structure
 
 
 def site_block(model, label, Q):
@@ -284,7 +290,7 @@ def grow_right(S, model, Q, bonds, keep):
             ops[(lab, name)] = P.kron(o, None)
     for (lab, name), o in site.ops.items():
         ops[(lab, name)] = P.kron(FS if model.fermionic else None, o)
-    return Block(S.labels + [x], P.basis, H, ops)
+    return Block(S.labels + [x], P.basis, H, ops, product=P)
 
 
 def grow_left(E, model, Q, n, bonds, keep):
@@ -313,7 +319,7 @@ def grow_left(E, model, Q, n, bonds, keep):
     for (lab, name), o in E.ops.items():
         if lab > r - keep:
             ops[(lab, name)] = P.kron(Fy if model.fermionic else None, o)
-    return Block(E.labels + [r], P.basis, H, ops)
+    return Block(E.labels + [r], P.basis, H, ops, product=P)
 
 
 def _as_desc_op(op):
@@ -338,7 +344,7 @@ def superblock(Sp, Ep, model, Q, n, bonds, q_target):
                 q_target=int(q_target), terms=terms)
 
 
-def change_basis(ctx, block, tr):
+def change_basis(ctx, block, tr, product=None):
     """Truncate a grown block with the kept eigenvectors (Eq. (4)), on the GPU."""
     import torch
     W = tr["W"]
@@ -370,12 +376,13 @@ def change_basis(ctx, block, tr):
         o_off += b.size
         out_off += W[r].shape[1] * W[c].shape[1]
     new = Block(list(block.labels), basis, {g: {} for g in block.H},
-                {k: Op(op.delta, {}) for k, op in block.ops.items()})
+                {k: Op(op.delta, {}) for k, op in block.ops.items()},
+                origin=(product, [(s, W[s]) for s in keep_secs]))
     if not items:
         return new
-    dO = torch.tensor(np.concatenate(Oflat), dtype=torch.float64, device="cuda")
-    dW = torch.tensor(np.concatenate(Wflat), dtype=torch.float64, device="cuda")
-    out = torch.empty(out_off, dtype=torch.float64, device="cuda")
+    dO = torch.tensor(np.concatenate(Oflat), dtype=torch.float64, device=DEVICE)
+    dW = torch.tensor(np.concatenate(Wflat), dtype=torch.float64, device=DEVICE)
+    out = torch.empty(out_off, dtype=torch.float64, device=DEVICE)
     ctx.transform_blocks(tbl, dO, dW, out)
     res = out.cpu().numpy()
     for (kind, (r, c), _), t in zip(items, tbl):
@@ -388,11 +395,125 @@ def change_basis(ctx, block, tr):
     return new
 
 
+# ---------------------------------------------------------------------------
+# Wave-function transformation between finite-sweep steps (the paper's
+# conclusions, after White 1996): the previous ground state, written in the
+# next superblock's basis, starts the next Lanczos run.  Each piece is
+# Wr^T (slice of Psi) Wc, so the whole map is one dmrg_transform_blocks call.
+# ---------------------------------------------------------------------------
+
+
+def _pairs(sb):
+    dS, dE = sb._dims
+    return {(int(i), int(j)): (int(o), int(dS[i]), int(dE[j]))
+            for i, j, o in zip(sb.s_sec, sb.e_sec, sb.offsets)}
+
+
+def _runs_of(product, sector):
+    return product.runs[sector]
+
+
+def wf_left_to_right(ctx, old_sb, psi_old, PS_old, PE_old, W_L, left_new, right_old, new_sb,
+                     PS_new, PE_new):
+    """psi at split p -> start vector at split p+1.
+
+    W_L: the kept eigenvectors of S'(p) (sector -> a x k), left_new = S'(p)
+    truncated; right_old = R_{L-p-1}, whose origin expands it into
+    site_{p+1} (x) R_{L-p-2} = E'(p+1)."""
+    import torch
+    old = _pairs(old_sb)
+    new = _pairs(new_sb)
+    keep_L = {s: k for k, (s, _w) in enumerate(left_new.origin[1])}
+    R_prod, R_kept = right_old.origin
+    Wbuf, tbl = [], []
+    woff = [0]
+
+    def put(a):
+        Wbuf.append(np.ascontiguousarray(a).reshape(-1))
+        o = woff[0]
+        woff[0] += a.size
+        return o
+
+    wl_off = {s: put(W_L[s]) for s in W_L}
+    wr_off = {k: put(Wk.T) for k, (_s, Wk) in enumerate(R_kept)}   # dim_rho x dim_rho'
+    for (i, j), (o_ij, a, b) in old.items():
+        if i not in W_L:
+            continue
+        li = keep_L[i]
+        k_i = W_L[i].shape[1]
+        for (x, rho, coff) in _runs_of(PE_old, j):
+            sec_p, Wr = R_kept[rho]              # E'(p+1) sector and its kept vectors
+            dim_rho = Wr.shape[1]
+            q_new_S = int(PS_new.left.q[li] + PS_new.right.q[x])
+            sig = PS_new.index.get(q_new_S)
+            if sig is None:
+                continue
+            roff = next(o for (aa, bb, o) in PS_new.runs[sig] if aa == li and bb == x)
+            if (sig, sec_p) not in new:
+                continue
+            n_off, _na, nb = new[(sig, sec_p)]
+            tbl.append(dict(o_off=o_ij + coff, rows=a, cols=dim_rho, o_ld=b, wr_off=wl_off[i],
+                            kr=k_i, wc_off=wr_off[rho], kc=Wr.shape[0],
+                            out_off=n_off + roff * nb, out_ld=nb))
+    out = torch.zeros(new_sb.D, dtype=torch.float64, device=DEVICE)
+    if tbl:
+        dW = torch.tensor(np.concatenate(Wbuf), dtype=torch.float64, device=DEVICE)
+        ctx.transform_blocks(tbl, psi_old, dW, out)
+    return out
+
+
+def wf_right_to_left(ctx, old_sb, psi_old, PS_old, PE_old, W_E, right_new, left_old, new_sb,
+                     PS_new, PE_new):
+    """psi at split p -> start vector at split p-1 (the mirror image)."""
+    import torch
+    old = _pairs(old_sb)
+    new = _pairs(new_sb)
+    keep_E = {s: k for k, (s, _w) in enumerate(right_new.origin[1])}
+    L_prod, L_kept = left_old.origin
+    Wbuf, tbl = [], []
+    woff = [0]
+
+    def put(a):
+        Wbuf.append(np.ascontiguousarray(a).reshape(-1))
+        o = woff[0]
+        woff[0] += a.size
+        return o
+
+    we_off = {s: put(W_E[s]) for s in W_E}
+    wl_off = {k: put(Wk.T) for k, (_s, Wk) in enumerate(L_kept)}   # dim_a x dim_a'
+    for (i, j), (o_ij, a, b) in old.items():
+        if j not in W_E:
+            continue
+        rj = keep_E[j]
+        k_j = W_E[j].shape[1]
+        for (lam, x, roff) in _runs_of(PS_old, i):
+            sec_p, Wl = L_kept[lam]               # S'(p-1) sector and its kept vectors
+            dim_a = Wl.shape[1]
+            q_new_E = int(PE_new.left.q[x] + PE_new.right.q[rj])
+            tau = PE_new.index.get(q_new_E)
+            if tau is None:
+                continue
+            coff = next(o for (aa, bb, o) in PE_new.runs[tau] if aa == x and bb == rj)
+            if (sec_p, tau) not in new:
+                continue
+            n_off, _na, nb = new[(sec_p, tau)]
+            tbl.append(dict(o_off=o_ij + roff * b, rows=dim_a, cols=b, o_ld=b, wr_off=wl_off[lam],
+                            kr=Wl.shape[0], wc_off=we_off[j], kc=k_j,
+                            out_off=n_off + coff, out_ld=nb))
+    out = torch.zeros(new_sb.D, dtype=torch.float64, device=DEVICE)
+    if tbl:
+        dW = torch.tensor(np.concatenate(Wbuf), dtype=torch.float64, device=DEVICE)
+        ctx.transform_blocks(tbl, psi_old, dW, out)
+    return out
+
+
 def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=2000,
-        no_split=True, keep_range=None, on_step=None):
+        no_split=True, keep_range=None, on_step=None, wavefunction=True):
     """Infinite phase to L sites, then ``sweeps`` finite sweeps (Secs. 1, 3.1).
 
-    ``init(D, step)`` gives the Lanczos start vector of each step (numpy).
+    ``init(D, step)`` gives the Lanczos start vector of each infinite-phase
+    step (numpy); finite-sweep steps start from the previous ground state
+    carried to the new basis when ``wavefunction`` is set (else ``init``).
     Returns a list of per-step records.
     """
     import torch
@@ -407,28 +528,36 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
     right = {1: site_block(model, 0, Q)}
     log = []
     step = [0]
+    prev = {}
 
-    def solve(Sp, Ep, n, sides, phase, p):
+    def solve(Sp, Ep, n, sides, phase, p, start=None):
         bonds = model.bonds(n)
         nu, nd = model.target(n)
         desc = superblock(Sp, Ep, model, Q, n, bonds, nu + Q * nd)
         sb = Superblock(desc, prec=prec, ctx=ctx)
-        psi0 = torch.tensor(init(sb.D, step[0]), dtype=torch.float64, device="cuda")
+        psi0 = start(sb) if start is not None else None
+        if psi0 is None or float(torch.linalg.vector_norm(psi0)) == 0.0:
+            psi0 = torch.tensor(init(sb.D, step[0]), dtype=torch.float64, device=DEVICE)
         r = sb.lanczos(psi0, max_iter=max_iter, tol=tol)
         rec = dict(phase=phase, n=n, p=p, energy=r["energy"], iters=r["iters"],
                    resid=r["resid"], D=sb.D, dimS=int(np.sum(Sp.basis.dim)),
                    dimE=int(np.sum(Ep.basis.dim)), step=step[0])
-        out = {}
+        out, trs = {}, {}
         for side in sides:
             tr = sb.rho_truncate(r["psi"], side, m, no_split=no_split)
             rec["eps%d" % side] = tr["eps"]
             rec["straddle%d" % side] = tr["straddle"]
-            out[side] = change_basis(ctx, Sp if side == 0 else Ep, tr)
+            blk = Sp if side == 0 else Ep
+            out[side] = change_basis(ctx, blk, tr, product=blk.product)
+            trs[side] = tr
         if on_step is not None:
             on_step(rec, desc, r)
         log.append(rec)
         sb.close()
         step[0] += 1
+        prev.clear()
+        prev.update(sb=sb, psi=r["psi"], Sp=Sp, Ep=Ep, p=p, sides=sides, trs=trs, out=out,
+                    phase=phase)
         return out
 
     for n in range(4, L + 1, 2):
@@ -445,7 +574,23 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
         for (p, side) in path:
             Sp = grow_right(left[p - 1], model, Q, bonds, keep_range)
             Ep = grow_left(right[L - p - 1], model, Q, L, bonds, keep_range)
-            out = solve(Sp, Ep, L, (side,), "finite", p)
+            start = None
+            if wavefunction and prev:
+                pv = dict(prev)
+                same = pv["p"] == p and (pv["phase"] == "finite" or p == L // 2)
+                if same:
+                    start = lambda sb, pv=pv: pv["psi"] if sb.D == pv["sb"].D else None
+                elif pv["p"] + 1 == p and 0 in pv["sides"]:
+                    start = lambda sb, pv=pv, Sp=Sp, Ep=Ep: wf_left_to_right(
+                        ctx, pv["sb"], pv["psi"], pv["Sp"].product, pv["Ep"].product,
+                        pv["trs"][0]["W"], pv["out"][0], right[L - pv["p"] - 1], sb,
+                        Sp.product, Ep.product)
+                elif pv["p"] - 1 == p and 1 in pv["sides"]:
+                    start = lambda sb, pv=pv, Sp=Sp, Ep=Ep: wf_right_to_left(
+                        ctx, pv["sb"], pv["psi"], pv["Sp"].product, pv["Ep"].product,
+                        pv["trs"][1]["W"], pv["out"][1], left[pv["p"] - 1], sb,
+                        Sp.product, Ep.product)
+            out = solve(Sp, Ep, L, (side,), "finite", p, start=start)
             if side == 0:
                 left[p] = out[0]
             else:

@@ -63,7 +63,8 @@ class Context:
         for i, b in enumerate(blocks):
             arr[i] = _lib.dmrg_tblock(int(b["o_off"]), int(b["rows"]), int(b["cols"]),
                                       int(b["wr_off"]), int(b["kr"]), int(b["wc_off"]),
-                                      int(b["kc"]), int(b["out_off"]))
+                                      int(b["kc"]), int(b["out_off"]), int(b.get("o_ld", 0)),
+                                      int(b.get("out_ld", 0)))
         check(lib().dmrg_transform_blocks(self.handle, n, arr, _ptr(O), _ptr(W), _ptr(out)))
         return out
 

@@ -61,3 +61,18 @@ def test_hubbard_u4_and_ladder_exact(ctx):
     assert abs(log[-1]["energy"] - M.hubbard_ed(8, M.chain_bonds(8), 4.0)[0]) < 1e-9
     log = DR.run(DR.heisenberg(DR.ladder(1.0, 1.0)), 8, 64, 1, _init, ctx=ctx, prec="fp32", tol=1e-9)
     assert abs(log[-1]["energy"] - M.heisenberg_ed(8, M.ladder_bonds(4))[0]) < 1e-9
+
+
+def test_wavefunction_transformation_saves_products(ctx):
+    """Carrying psi between finite-sweep steps (on the GPU) leaves the energies
+    unchanged and cuts the number of products."""
+    from paper_0902_3185_amd import driver as DR
+    L = 16
+    a = DR.run(DR.heisenberg(DR.chain(1.0)), L, 32, 1, _init, ctx=ctx, prec="fp32", tol=1e-9)
+    b = DR.run(DR.heisenberg(DR.chain(1.0)), L, 32, 1, _init, ctx=ctx, prec="fp32", tol=1e-9,
+               wavefunction=False)
+    for x, y in zip(a, b):
+        assert abs(x["energy"] - y["energy"]) <= 1e-9 * L
+    fa = sum(r["iters"] for r in a if r["phase"] == "finite")
+    fb = sum(r["iters"] for r in b if r["phase"] == "finite")
+    assert fa < 0.6 * fb, (fa, fb)
