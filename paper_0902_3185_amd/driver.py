@@ -507,8 +507,48 @@ def wf_right_to_left(ctx, old_sb, psi_old, PS_old, PE_old, W_E, right_new, left_
     return out
 
 
+# ---------------------------------------------------------------------------
+# Reflection symmetry in the infinite phase (the paper's conclusions: a factor
+# of 2 in that phase).  When the n-site system is its own mirror image, the
+# environment block of size h is the system block of size h read from the
+# other end: same basis, same matrices, labels now distances from the right
+# end.  Only S' is diagonalised and truncated.  Spin models only: for
+# fermions the mirrored Jordan-Wigner strings would need a parity dressing.
+# ---------------------------------------------------------------------------
+
+
+def mirror_symmetric(model, n):
+    b = {(i, j, v, g) for (i, j, v, g) in model.bonds(n)}
+    m = {(n - 1 - j, n - 1 - i, v, g) for (i, j, v, g) in b}
+    return not model.fermionic and b == m
+
+
+def mirrored(block):
+    """The right block equal to a left block read from the other end.
+
+    Its origin is re-expressed in the site (x) block product order of a grown
+    right block, so the wave-function transformation can expand it."""
+    origin = None
+    if block.origin is not None and block.origin[0] is not None:
+        Pl, kept = block.origin          # Pl = Product(left block, site)
+        Pr = Product(Pl.right, Pl.left, left_major=True)   # site (x) block
+        new_kept = []
+        for (sec, W) in kept:
+            q = int(Pl.basis.q[sec])
+            sec_r = Pr.index[q]
+            rows = np.empty(W.shape[0], dtype=np.int64)
+            where = {(a, b): o for (a, b, o) in Pl.runs[sec]}
+            for (x, a, o_r) in Pr.runs[sec_r]:
+                o_l = where[(a, x)]
+                n_run = int(Pl.left.dim[a] * Pl.right.dim[x])
+                rows[o_r:o_r + n_run] = np.arange(o_l, o_l + n_run)
+            new_kept.append((sec_r, W[rows, :]))
+        origin = (Pr, new_kept)
+    return Block(list(block.labels), block.basis, block.H, dict(block.ops), origin=origin)
+
+
 def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=2000,
-        no_split=True, keep_range=None, on_step=None, wavefunction=True):
+        no_split=True, keep_range=None, on_step=None, wavefunction=True, reflect=False):
     """Infinite phase to L sites, then ``sweeps`` finite sweeps (Secs. 1, 3.1).
 
     ``init(D, step)`` gives the Lanczos start vector of each infinite-phase
@@ -565,8 +605,12 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
         bonds = model.bonds(n)
         Sp = grow_right(left[h - 1], model, Q, bonds, keep_range)
         Ep = grow_left(right[h - 1], model, Q, n, bonds, keep_range)
-        out = solve(Sp, Ep, n, (0, 1), "infinite", h)
-        left[h], right[h] = out[0], out[1]
+        if reflect and mirror_symmetric(model, n):
+            out = solve(Sp, Ep, n, (0,), "infinite", h)
+            left[h], right[h] = out[0], mirrored(out[0])
+        else:
+            out = solve(Sp, Ep, n, (0, 1), "infinite", h)
+            left[h], right[h] = out[0], out[1]
     bonds = model.bonds(L)
     for _ in range(sweeps):
         path = ([(p, 0) for p in range(L // 2, L - 1)] + [(p, 1) for p in range(L - 2, 1, -1)]

@@ -106,3 +106,24 @@ def test_transformation_off_gives_same_energies(fake):
                wavefunction=False)
     for x, y in zip(a, b):
         assert abs(x["energy"] - y["energy"]) < 1e-9 * L
+
+
+@pytest.mark.parametrize("bonds", ["chain", "j1j2", "ladder"])
+def test_reflection_in_infinite_phase(fake, bonds):
+    """Environment = mirrored system block: same energies, half the truncations."""
+    DR = fake
+    L = 12
+    bf = {"chain": DR.chain(1.0), "j1j2": DR.j1j2(1.0, 0.4), "ladder": DR.ladder(1.0, 0.7)}[bonds]
+    a = DR.run(DR.heisenberg(bf), L, 16, 1, _init, ctx=FakeContext(), tol=1e-12, reflect=True)
+    b = DR.run(DR.heisenberg(bf), L, 16, 1, _init, ctx=FakeContext(), tol=1e-12, reflect=False)
+    for x, y in zip(a, b):
+        assert abs(x["energy"] - y["energy"]) < 1e-9 * L, (x, y)
+    assert all("eps1" not in r for r in a if r["phase"] == "infinite")
+    n_inf = sum(1 for r in a if r["phase"] == "infinite")
+    assert min(STARTS[n_inf:len(a)]) > 0.99   # run a's finite steps only
+
+
+def test_reflection_skips_fermions(fake):
+    DR = fake
+    assert not DR.mirror_symmetric(DR.hubbard(1.0), 8)
+    assert DR.mirror_symmetric(DR.heisenberg(DR.ladder()), 8)

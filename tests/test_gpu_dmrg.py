@@ -76,3 +76,12 @@ def test_wavefunction_transformation_saves_products(ctx):
     fa = sum(r["iters"] for r in a if r["phase"] == "finite")
     fb = sum(r["iters"] for r in b if r["phase"] == "finite")
     assert fa < 0.6 * fb, (fa, fb)
+
+
+def test_reflection_on_gpu(ctx):
+    from paper_0902_3185_amd import driver as DR
+    L = 16
+    a = DR.run(DR.heisenberg(DR.chain(1.0)), L, 32, 1, _init, ctx=ctx, prec="fp32", tol=1e-9,
+               reflect=True)
+    ref = OD.run(M.heisenberg_model(M.chain_bonds), L, 32, 1, _init, tol=1e-10)
+    assert abs(a[-1]["energy"] - ref[-1]["energy"]) <= 1e-9 * L
