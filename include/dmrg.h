@@ -169,6 +169,20 @@ dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_
                                   dmrg_prec prec, dmrg_sb* out);
 void dmrg_sb_destroy(dmrg_sb sb);
 
+/* An operator between two target sectors (for spectral functions, Eq. (5):
+ * c_i maps the ground state's sector to one with an electron less): inputs
+ * live in the q_in sector, outputs in q_out, both laid out as
+ * dmrg_build_superblock would lay them out for that target; every term must
+ * shift q by q_out - q_in (DMRG_E_QN otherwise).  dmrg_hpsi and
+ * dmrg_hpsi_adjoint work on it; the Lanczos and density-matrix calls need
+ * q_in == q_out (DMRG_E_ARG).                                               */
+dmrg_status dmrg_build_operator(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_basis* E,
+                                int64_t q_in, int64_t q_out, int32_t nterms,
+                                const dmrg_term* terms, dmrg_prec prec, dmrg_sb* out);
+
+/* Input and output vector lengths of a superblock or operator.             */
+dmrg_status dmrg_sb_dims(dmrg_sb sb, int64_t* D_in, int64_t* D_out);
+
 /* psi layout (Eq. (1) restricted to the target): npairs blocks; block p is
  * the row-major dim_S[s_sec[p]] x dim_E[e_sec[p]] matrix Psi_p starting at
  * element off[p]; D = total length.  Arrays are library-owned.            */
@@ -220,6 +234,17 @@ dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d
 dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_iter, double tol,
                                 double* E0_h, double* psi_d, int32_t* iters_h, double* resid_h);
 
+/* The Lanczos recursion (Sec. 3.3) from an arbitrary start vector, for the
+ * continued fraction of a spectral function (the paper's LDOS, Eq. (5),
+ * computed from H's tridiagonal form on c_i|psi>).  v0_d (device, length D)
+ * is normalised inside; *norm0_h = ||v0||.  nsteps products with full FP64
+ * reorthogonalisation; alpha_h[k], beta_h[k] (host, nsteps each) receive the
+ * diagonal and the coupling of step k to k+1; *steps_h the number of steps
+ * before the recursion broke down (an invariant subspace), at most nsteps.
+ * Synchronises the stream.                                                  */
+dmrg_status dmrg_lanczos_tridiag(dmrg_sb sb, const double* v0_d, int32_t nsteps, double* alpha_h,
+                                 double* beta_h, int32_t* steps_h, double* norm0_h);
+
 /* Reduced density matrix of S' (side 0, Eq. (2): rho_S = Psi Psi^T) or E'
  * (side 1, Eq. (3): rho_E = Psi^T Psi), formed per symmetry block on the
  * device in FP64, diagonalised per block in FP64 on the host, eigenvalues
@@ -268,6 +293,14 @@ dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock*
  * eigenvector of w[c] (Householder tridiagonalisation, implicit QR with
  * Wilkinson shifts).  DMRG_E_NOCONV if the sweeps do not converge.        */
 dmrg_status dmrg_host_sym_eigen(int32_t n, double* a, double* w);
+
+/* Local density of states of Eq. (5) from Lanczos coefficients of H on
+ * phi = c|psi> (host): out[k] = 2 weight Im f(E0 - omega[k] - i eta), with
+ * f(z) = 1/(z - a_0 - b_0^2/(z - a_1 - b_1^2/(...))) over n steps and
+ * weight = ||phi||^2; i.e. 2 pi sum_n |<n|c|psi>|^2 L_eta(omega - (E0 - E_n))
+ * with L_eta a unit-area Lorentzian of half-width eta.                      */
+dmrg_status dmrg_host_ldos(int32_t n, const double* alpha, const double* beta, double weight,
+                           double e0, int32_t nomega, const double* omega, double eta, double* out);
 
 /* Lowest eigenpair of the symmetric tridiagonal matrix with diagonal
  * alpha[n] and off-diagonal beta[n-1] (Sturm bisection + inverse

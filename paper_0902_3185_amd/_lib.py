@@ -65,6 +65,13 @@ _SIGS = {
     "dmrg_build_superblock": (C.c_int, [_P, C.POINTER(dmrg_basis), C.POINTER(dmrg_basis), C.c_int64,
                                         C.c_int32, C.POINTER(dmrg_term), C.c_int, C.POINTER(_P)]),
     "dmrg_sb_destroy": (None, [_P]),
+    "dmrg_build_operator": (C.c_int, [_P, C.POINTER(dmrg_basis), C.POINTER(dmrg_basis), C.c_int64,
+                                      C.c_int64, C.c_int32, C.POINTER(dmrg_term), C.c_int,
+                                      C.POINTER(_P)]),
+    "dmrg_sb_dims": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "dmrg_lanczos_tridiag": (C.c_int, [_P, _P, C.c_int32, _D, _D, C.POINTER(C.c_int32), _D]),
+    "dmrg_host_ldos": (C.c_int, [C.c_int32, _D, _D, C.c_double, C.c_double, C.c_int32, _D,
+                                 C.c_double, _D]),
     "dmrg_sb_layout": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                  C.POINTER(C.POINTER(C.c_int64)), C.POINTER(C.POINTER(C.c_int32)),
                                  C.POINTER(C.POINTER(C.c_int32))]),

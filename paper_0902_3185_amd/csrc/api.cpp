@@ -121,6 +121,7 @@ struct dmrg_sb_s {
   std::vector<int64_t> qS, qE;
   std::vector<int32_t> dS, dE;
   int64_t q_target = 0;
+  int64_t q_in = 0;             // == q_target for a Hamiltonian superblock
   std::vector<double> coeff;
   std::vector<int32_t> group;
   std::vector<std::unique_ptr<OpCopy>> opA, opB;
@@ -231,6 +232,14 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
 dmrg_status need_device(dmrg_sb sb) {
   if (sb == nullptr) return fail(DMRG_E_ARG, "null superblock");
   if (sb->ctx == nullptr) return fail(DMRG_E_DEVICE, "superblock was built without a device context");
+  return DMRG_OK;
+}
+
+dmrg_status need_square(dmrg_sb sb) {
+  dmrg_status st = need_device(sb);
+  if (st != DMRG_OK) return st;
+  if (sb->q_in != sb->q_target)
+    return fail(DMRG_E_ARG, "this call needs a Hamiltonian (input sector == output sector)");
   return DMRG_OK;
 }
 
@@ -347,15 +356,16 @@ dmrg_status dmrg_ctx_set_stream(dmrg_ctx ctx, void* hip_stream) {
   return DMRG_OK;
 }
 
-dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_basis* E,
-                                  int64_t q_target, int32_t nterms, const dmrg_term* terms,
-                                  dmrg_prec prec, dmrg_sb* out) {
+static dmrg_status build_sb(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_basis* E, int64_t q_in,
+                            int64_t q_target, int32_t nterms, const dmrg_term* terms,
+                            dmrg_prec prec, dmrg_sb* out) {
   if (out == nullptr) return fail(DMRG_E_ARG, "null output pointer");
   if (prec < DMRG_FP64 || prec > DMRG_FP64_PLAIN) return fail(DMRG_E_ARG, "unknown precision");
   auto sb = std::make_unique<dmrg_sb_s>();
   std::string err;
-  dmrg_status st = build_plan(S, E, q_target, nterms, terms, false, sb->fwd.plan, err);
+  dmrg_status st = build_plan_between(S, E, q_in, q_target, nterms, terms, false, sb->fwd.plan, err);
   if (st != DMRG_OK) return fail(st, err);
+  sb->q_in = q_in;
   sb->ctx = ctx;
   if (ctx) {
     sb->device = ctx->device;
@@ -379,6 +389,25 @@ dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_
     if ((st = stage(ctx, sb->fwd, uses32(prec))) != DMRG_OK) return st;
   }
   *out = sb.release();
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_build_superblock(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_basis* E,
+                                  int64_t q_target, int32_t nterms, const dmrg_term* terms,
+                                  dmrg_prec prec, dmrg_sb* out) {
+  return build_sb(ctx, S, E, q_target, q_target, nterms, terms, prec, out);
+}
+
+dmrg_status dmrg_build_operator(dmrg_ctx ctx, const dmrg_basis* S, const dmrg_basis* E,
+                                int64_t q_in, int64_t q_out, int32_t nterms,
+                                const dmrg_term* terms, dmrg_prec prec, dmrg_sb* out) {
+  return build_sb(ctx, S, E, q_in, q_out, nterms, terms, prec, out);
+}
+
+dmrg_status dmrg_sb_dims(dmrg_sb sb, int64_t* D_in, int64_t* D_out) {
+  if (!sb) return fail(DMRG_E_ARG, "null superblock");
+  if (D_in) *D_in = sb->fwd.plan.D_in;
+  if (D_out) *D_out = sb->fwd.plan.D;
   return DMRG_OK;
 }
 
@@ -474,7 +503,8 @@ dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d
       std::string err;
       dmrg_basis bS = basis_view(sb->qS, sb->dS), bE = basis_view(sb->qE, sb->dE);
       std::vector<dmrg_term> tv = term_views(sb);
-      st = build_plan(&bS, &bE, sb->q_target, (int32_t)tv.size(), tv.data(), true, adj->plan, err);
+      st = build_plan_between(&bS, &bE, sb->q_in, sb->q_target, (int32_t)tv.size(), tv.data(), true,
+                              adj->plan, err);
       if (st != DMRG_OK) return fail(st, "adjoint plan: " + err);
       if ((st = stage(sb->ctx, *adj, sb->fwd.has32)) != DMRG_OK) return st;
       sb->adj = std::move(adj);
@@ -509,7 +539,7 @@ dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d
 
 dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_iter, double tol,
                                 double* E0_h, double* psi_d, int32_t* iters_h, double* resid_h) {
-  dmrg_status st = need_device(sb);
+  dmrg_status st = need_square(sb);
   if (st != DMRG_OK) return st;
   if (!psi0_d || !psi_d || !E0_h) return fail(DMRG_E_ARG, "null argument");
   if (max_iter < 1 || !(tol >= 0.0)) return fail(DMRG_E_ARG, "max_iter must be >= 1 and tol >= 0");
@@ -631,7 +661,7 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
 
 dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int32_t m,
                               int32_t no_split, dmrg_trunc* out) {
-  dmrg_status st = need_device(sb);
+  dmrg_status st = need_square(sb);
   if (st != DMRG_OK) return st;
   if (!psi_d || !out) return fail(DMRG_E_ARG, "null argument");
   if (side != 0 && side != 1) return fail(DMRG_E_ARG, "side must be 0 (S') or 1 (E')");
@@ -907,6 +937,76 @@ dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock*
   HIP_TRY(launch_hpsi(kPrecF64, (int)n2, nullptr, dt + n1, ctx->tr_segs.as<SegDesc>(),
                       ctx->tr_tmp.as<double>(), nullptr, nullptr, W_d, out_d, 1.0, 0.0, s));
   HIP_TRY(hipStreamSynchronize(s));   // the host tile lists die here
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_lanczos_tridiag(dmrg_sb sb, const double* v0_d, int32_t nsteps, double* alpha_h,
+                                 double* beta_h, int32_t* steps_h, double* norm0_h) {
+  dmrg_status st = need_square(sb);
+  if (st != DMRG_OK) return st;
+  if (!v0_d || !alpha_h || !beta_h || !steps_h || nsteps < 1) return fail(DMRG_E_ARG, "bad argument");
+  dmrg_ctx ctx = sb->ctx;
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = ctx->stream;
+  const int64_t D = sb->fwd.plan.D;
+  const int nvec = nsteps + 1;
+  const int nblk = std::max(lz_blocks(D), vec_blocks(D));
+  HIP_TRY(ctx->V.ensure((size_t)nvec * D * sizeof(double)));
+  HIP_TRY(ctx->w.ensure((size_t)D * sizeof(double)));
+  HIP_TRY(ctx->partial.ensure((size_t)nvec * nblk * sizeof(double)));
+  const size_t nsmall = (size_t)5 * nvec + 16;
+  HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
+  HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));
+  double* V = ctx->V.as<double>();
+  double* w = ctx->w.as<double>();
+  double* part = ctx->partial.as<double>();
+  double* h1 = ctx->small.as<double>();
+  double* h2 = h1 + nvec;
+  double* nrm2 = h2 + 2 * nvec;
+  double* ab = nrm2 + 8;
+  unsigned int* counter = reinterpret_cast<unsigned int*>(ab + 2 * nvec);
+  HIP_TRY(launch_multi_dot(v0_d, 0, 1, v0_d, D, part, nrm2, s));
+  HIP_TRY(launch_normalise(V, v0_d, nrm2, D, s));
+  for (int j = 0; j < nsteps; ++j) {
+    if ((st = run_product(sb, sb->fwd, sb->prec, V + (size_t)j * D, w, 1.0, 0.0)) != DMRG_OK) return st;
+    HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, counter, ab + 2 * j,
+                           V + (size_t)(j + 1) * D, s));
+  }
+  std::vector<double> hs(2 * nsteps + 1);
+  HIP_TRY(hipMemcpyAsync(hs.data(), ab, 2 * nsteps * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hs.data() + 2 * nsteps, nrm2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int steps = 0;
+  for (; steps < nsteps; ++steps) {
+    alpha_h[steps] = hs[2 * steps];
+    beta_h[steps] = hs[2 * steps + 1];
+    if (hs[2 * steps + 1] <= 1e-13 * std::max(1.0, std::fabs(hs[2 * steps]))) {
+      ++steps;
+      break;
+    }
+  }
+  *steps_h = steps;
+  if (norm0_h) *norm0_h = std::sqrt(std::max(0.0, hs[2 * nsteps]));
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_host_ldos(int32_t n, const double* alpha, const double* beta, double weight,
+                           double e0, int32_t nomega, const double* omega, double eta, double* out) {
+  if (n < 1 || !alpha || !beta || nomega < 0 || (nomega > 0 && (!omega || !out)) || !(eta > 0.0))
+    return fail(DMRG_E_ARG, "bad argument");
+  for (int32_t k = 0; k < nomega; ++k) {
+    const double zr = e0 - omega[k], zi = -eta;   // zeta = E0 - omega - i eta
+    // continued fraction from the bottom: f = 1 / (zeta - a_j - b_j^2 f_next)
+    double fr = 0.0, fi = 0.0;
+    for (int32_t j = n - 1; j >= 0; --j) {
+      const double b2 = j + 1 < n ? beta[j] * beta[j] : 0.0;
+      const double dr = zr - alpha[j] - b2 * fr, di = zi - b2 * fi;
+      const double den = dr * dr + di * di;
+      fr = dr / den;
+      fi = -di / den;
+    }
+    out[k] = 2.0 * weight * fi;
+  }
   return DMRG_OK;
 }
 

@@ -148,6 +148,15 @@ dmrg_status stage_side(const dmrg_op* op, const dmrg_basis* b, bool a_side, bool
 dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_target,
                        int32_t nterms, const dmrg_term* terms, bool transpose, Plan& plan,
                        std::string& err) {
+  return build_plan_between(S, E, q_target, q_target, nterms, terms, transpose, plan, err);
+}
+
+dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t q_in,
+                               int64_t q_out, int32_t nterms, const dmrg_term* terms,
+                               bool transpose, Plan& plan, std::string& err) {
+  // a transposed operator maps q_out back to q_in
+  if (transpose) std::swap(q_in, q_out);
+  const int64_t q_target = q_out;
   dmrg_status st;
   if ((st = check_basis(S, "S'", err)) != DMRG_OK) return st;
   if ((st = check_basis(E, "E'", err)) != DMRG_OK) return st;
@@ -183,15 +192,39 @@ dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_targe
   }
   plan.D = off;
   const int32_t npairs = (int32_t)plan.pair_s.size();
+  // input layout (the same rule, for q_in)
+  std::vector<int32_t> in_pair_e(S->nsec, -1);
+  std::vector<int64_t> in_off(S->nsec, -1);
+  int64_t off_in = 0;
+  for (int32_t i = 0; i < S->nsec; ++i) {
+    const int64_t want = q_in - S->q[i];
+    const int64_t* it = std::lower_bound(E->q, E->q + E->nsec, want);
+    if (it != E->q + E->nsec && *it == want) {
+      in_pair_e[i] = (int32_t)(it - E->q);
+      in_off[i] = off_in;
+      off_in += (int64_t)S->dim[i] * E->dim[it - E->q];
+    }
+  }
+  if (off_in == 0) {
+    err = "no S'/E' sector pair reaches the input quantum number";
+    return DMRG_E_QN;
+  }
+  plan.q_in = q_in;
+  plan.D_in = off_in;
 
   // stage operators
   std::vector<std::vector<SideBlock>> Aside(nterms), Bside(nterms);
   for (int32_t k = 0; k < nterms; ++k) {
     const dmrg_term& t = terms[k];
     int64_t dA = t.A ? t.A->delta : 0, dB = t.B ? t.B->delta : 0;
-    if (dA + dB != 0) {
+    if (transpose) {
+      dA = -dA;
+      dB = -dB;
+    }
+    if (dA + dB != q_out - q_in) {
       std::ostringstream os;
-      os << "term " << k << " changes the total quantum number by " << dA + dB;
+      os << "term " << k << " changes the total quantum number by " << dA + dB << ", not by "
+         << q_out - q_in;
       err = os.str();
       return DMRG_E_QN;
     }
@@ -220,12 +253,11 @@ dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_targe
       } else {
         b.src_sec = j;
       }
-      const int32_t p2 = pair_of_s[a.src_sec];
-      if (p2 < 0 || plan.pair_e[p2] != b.src_sec) continue;  // source block outside the target
+      if (in_pair_e[a.src_sec] != b.src_sec) continue;   // source block outside the input sector
       SegDesc sg{};
       sg.c = terms[k].c;
       sg.term = k;
-      sg.psi_off = plan.pair_off[p2];
+      sg.psi_off = in_off[a.src_sec];
       sg.psi_ld = plan.dE[b.src_sec];
       sg.psi_rows = plan.dS[a.src_sec];
       sg.op_off = -1;

@@ -66,6 +66,8 @@ struct Plan {
   std::vector<int32_t> pair_s, pair_e;
   std::vector<int64_t> pair_off;
   int64_t D = 0;
+  int64_t q_in = 0;               // input sector (== q_target for a Hamiltonian)
+  int64_t D_in = 0;
   // terms
   int32_t nterms = 0;
   std::vector<double> coeff;
@@ -88,6 +90,12 @@ struct Plan {
 dmrg_status build_plan(const dmrg_basis* S, const dmrg_basis* E, int64_t q_target,
                        int32_t nterms, const dmrg_term* terms, bool transpose, Plan& plan,
                        std::string& err);
+
+// Plan of an operator between two target sectors: input vectors live in the
+// q_in sector, outputs in q_out; every term must shift q by q_out - q_in.
+dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t q_in,
+                               int64_t q_out, int32_t nterms, const dmrg_term* terms,
+                               bool transpose, Plan& plan, std::string& err);
 
 // Recomputes statistics for an element size of the staged operators.
 double plan_bytes_alg(const Plan& p, int elem_bytes);

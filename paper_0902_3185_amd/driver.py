@@ -547,8 +547,59 @@ def mirrored(block):
     return Block(list(block.labels), block.basis, block.H, dict(block.ops), origin=origin)
 
 
+# ---------------------------------------------------------------------------
+# Local density of states (Eq. (5)) by the continued-fraction method: c_i on
+# the ground state through the library's sector-changing operator, the
+# Lanczos recursion of H in the sector with one electron less from c_i|psi>,
+# and the continued fraction on the host.
+# ---------------------------------------------------------------------------
+
+
+def ldos(ctx, Sp, Ep, model, n, q_target, psi, site, spin, omega, eta, nsteps=100,
+         prec="fp64"):
+    """N_site(omega) for spin 0 (up) / 1 (down) of the superblock's ground
+    state psi; ``site`` is a label of S' (its newest site is max(Sp.labels))."""
+    from .superblock import Superblock, ldos as host_ldos
+    if not model.fermionic:
+        raise ValueError("the local density of states needs a fermion model")
+    name = "cu" if spin == 0 else "cd"
+    if (site, name) not in Sp.ops:
+        raise ValueError("site %r carries no operators in S'" % (site,))
+    c_op = Sp.ops[(site, name)]               # c with its string inside S'
+    q_out = q_target + c_op.delta
+    op_desc = dict(S=dict(q=Sp.basis.q, dim=Sp.basis.dim), E=dict(q=Ep.basis.q, dim=Ep.basis.dim),
+                   q_target=int(q_out), terms=[dict(c=1.0, A=_as_desc_op(c_op), B=None, group=0)])
+    C_sb = Superblock(op_desc, prec="fp64", ctx=ctx, q_in=q_target)
+    phi = C_sb.hpsi(psi)
+    H_desc = superblock(Sp, Ep, model, _Q_of(Sp, Ep, model, n), n, model.bonds(n), q_out)
+    H_sb = Superblock(H_desc, prec=prec, ctx=ctx)
+    a, b, nrm = H_sb.lanczos_tridiag(phi, nsteps)
+    C_sb.close()
+    H_sb.close()
+    return host_ldos(a, b, nrm * nrm, e0_of(ctx, Sp, Ep, model, n, q_target, psi, prec), omega,
+                     eta)
+
+
+def _Q_of(Sp, Ep, model, n):
+    """The base of the effective quantum number the run used (Q = L + 1)."""
+    return n + 1
+
+
+def e0_of(ctx, Sp, Ep, model, n, q_target, psi, prec):
+    """<psi|H|psi> of a normalised ground state (the E0 of Eq. (5))."""
+    import torch
+
+    from .superblock import Superblock
+    desc = superblock(Sp, Ep, model, _Q_of(Sp, Ep, model, n), n, model.bonds(n), q_target)
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    e0 = float(torch.dot(psi, sb.hpsi(psi)) / torch.dot(psi, psi))
+    sb.close()
+    return e0
+
+
 def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=2000,
-        no_split=True, keep_range=None, on_step=None, wavefunction=True, reflect=False):
+        no_split=True, keep_range=None, on_step=None, wavefunction=True, reflect=False,
+        on_solve=None):
     """Infinite phase to L sites, then ``sweeps`` finite sweeps (Secs. 1, 3.1).
 
     ``init(D, step)`` gives the Lanczos start vector of each infinite-phase
@@ -592,6 +643,8 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
             trs[side] = tr
         if on_step is not None:
             on_step(rec, desc, r)
+        if on_solve is not None:
+            on_solve(Sp, Ep, n, desc, r)
         log.append(rec)
         sb.close()
         step[0] += 1

@@ -125,16 +125,26 @@ class Superblock:
     ``ctx=None`` builds the host plan only (layout and statistics).
     """
 
-    def __init__(self, desc, prec="fp32", ctx=None):
+    def __init__(self, desc, prec="fp32", ctx=None, q_in=None):
+        """q_in: build the operator from the q_in sector to desc["q_target"]
+        (dmrg_build_operator) instead of a Hamiltonian superblock."""
         self.ctx = ctx
         self.prec = prec
         self.nterms = len(desc["terms"])
         m = _Marshal(desc)
         h = C.c_void_p()
-        check(lib().dmrg_build_superblock(ctx.handle if ctx is not None else None,
-                                          C.byref(m.S), C.byref(m.E), int(desc["q_target"]),
-                                          m.nterms, m.terms, PREC[prec], C.byref(h)))
+        dev = ctx.handle if ctx is not None else None
+        if q_in is None:
+            check(lib().dmrg_build_superblock(dev, C.byref(m.S), C.byref(m.E), int(desc["q_target"]),
+                                              m.nterms, m.terms, PREC[prec], C.byref(h)))
+        else:
+            check(lib().dmrg_build_operator(dev, C.byref(m.S), C.byref(m.E), int(q_in),
+                                            int(desc["q_target"]), m.nterms, m.terms, PREC[prec],
+                                            C.byref(h)))
         self.handle = h
+        di, do = C.c_int64(), C.c_int64()
+        check(lib().dmrg_sb_dims(h, C.byref(di), C.byref(do)))
+        self.D_in = int(di.value)
         self._dims = (np.asarray(desc["S"]["dim"]), np.asarray(desc["E"]["dim"]))
         D = C.c_int64()
         npairs = C.c_int32()
@@ -167,18 +177,33 @@ class Superblock:
         self.prec = prec
 
     # -- device work -----------------------------------------------------------
-    def _vec(self, t, name):
+    def _vec(self, t, name, n=None):
         import torch
+        n = self.D if n is None else n
         if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
-                and t.is_contiguous() and t.numel() == self.D):
-            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of length {self.D}")
+                and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of length {n}")
         return t
+
+    def lanczos_tridiag(self, v0, nsteps):
+        """dmrg_lanczos_tridiag: (alpha, beta, ||v0||) of the recursion from v0."""
+        self._vec(v0, "v0")
+        a = np.zeros(nsteps)
+        b = np.zeros(nsteps)
+        steps = C.c_int32()
+        nrm = C.c_double()
+        check(lib().dmrg_lanczos_tridiag(self.handle, _ptr(v0), int(nsteps),
+                                         a.ctypes.data_as(C.POINTER(C.c_double)),
+                                         b.ctypes.data_as(C.POINTER(C.c_double)), C.byref(steps),
+                                         C.byref(nrm)))
+        k = steps.value
+        return a[:k], b[:k], nrm.value
 
     def hpsi(self, psi, y=None, alpha=1.0, beta=0.0):
         import torch
-        self._vec(psi, "psi")
+        self._vec(psi, "psi", self.D_in)
         if y is None:
-            y = torch.empty_like(psi)
+            y = torch.empty(self.D, dtype=psi.dtype, device=psi.device)
             beta = 0.0
         self._vec(y, "y")
         check(lib().dmrg_hpsi(self.handle, _ptr(psi), _ptr(y), float(alpha), float(beta)))
@@ -243,3 +268,16 @@ class Superblock:
 
 def build_superblock(desc, prec="fp32", ctx=None):
     return Superblock(desc, prec=prec, ctx=ctx)
+
+
+def ldos(alpha, beta, weight, e0, omega, eta):
+    """dmrg_host_ldos: the Eq. (5) density of states on the grid omega."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    w = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros(len(w))
+    check(lib().dmrg_host_ldos(len(a), a.ctypes.data_as(C.POINTER(C.c_double)),
+                               b.ctypes.data_as(C.POINTER(C.c_double)), float(weight), float(e0),
+                               len(w), w.ctypes.data_as(C.POINTER(C.c_double)), float(eta),
+                               out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out

@@ -85,3 +85,23 @@ def test_reflection_on_gpu(ctx):
                reflect=True)
     ref = OD.run(M.heisenberg_model(M.chain_bonds), L, 32, 1, _init, tol=1e-10)
     assert abs(a[-1]["energy"] - ref[-1]["energy"]) <= 1e-9 * L
+
+
+@pytest.mark.parametrize("U,spin", [(1.0, 0), (4.0, 1)])
+def test_ldos_matches_exact_diagonalisation(ctx, U, spin):
+    """Eq. (5) on the centre superblock of an untruncated 8-site Hubbard run:
+    continued fraction through the library vs the ED Lehmann sum."""
+    from oracle import ldos as OLD
+    from paper_0902_3185_amd import driver as DR
+    L = 8
+    keep = {}
+    DR.run(DR.hubbard(U), L, 256, 1, _init, ctx=ctx, prec="fp64", tol=1e-11,
+           on_solve=lambda Sp, Ep, n, desc, r: keep.update(Sp=Sp, Ep=Ep, n=n, desc=desc, r=r))
+    Sp, Ep, desc, r = keep["Sp"], keep["Ep"], keep["desc"], keep["r"]
+    site = max(Sp.labels)
+    omega = np.linspace(-4, 4, 81)
+    eta = 0.1
+    N = DR.ldos(ctx, Sp, Ep, DR.hubbard(U), L, desc["q_target"], r["psi"], site, spin, omega,
+                eta, nsteps=120)
+    ref, _, w, _ = OLD.hubbard_ldos_lehmann(L, M.chain_bonds(L), U, site, spin, omega, eta)
+    assert np.max(np.abs(N - ref)) <= 1e-6 * np.max(ref)
