@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cmath>
 #include <thread>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <sstream>
@@ -22,6 +23,17 @@ using namespace dmrg;
 namespace {
 
 thread_local std::string g_err;
+
+// Host threads for the per-sector eigen-solves: OMP_NUM_THREADS when set
+// (the machine's share for this process), else the hardware count; at most 32.
+int host_threads() {
+  int n = (int)std::max(1u, std::thread::hardware_concurrency());
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(e);
+    if (v > 0) n = std::min(n, v);
+  }
+  return std::max(1, std::min(n, 32));
+}
 
 dmrg_status fail(dmrg_status st, const std::string& msg) {
   g_err = msg;
@@ -745,6 +757,8 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   for (int i = 0; i < nsec; ++i) work[i] = i;
   std::stable_sort(work.begin(), work.end(), [&](int x, int y) { return ds[x] > ds[y]; });
   std::atomic<int> next(0), bad(0);
+  const int hw = host_threads();
+  const int inner = std::max(1, hw / 2);   // threads inside one large sector's solve
   auto solve = [&]() {
     for (;;) {
       const int w = next.fetch_add(1);
@@ -759,7 +773,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
           const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
           A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
         }
-      if (!sym_eigen(n, A.data(), wv.data())) {
+      if (!sym_eigen(n, A.data(), wv.data(), n >= 128 ? inner : 1)) {
         bad.fetch_add(1);
         continue;
       }
@@ -775,8 +789,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     }
   };
   {
-    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-    const int nthr = std::min({hw, nsec, 32});
+    const int nthr = std::min(hw, nsec);
     std::vector<std::thread> pool;
     for (int t = 1; t < nthr; ++t) pool.emplace_back(solve);
     solve();

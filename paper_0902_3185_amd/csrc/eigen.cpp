@@ -6,13 +6,17 @@
 // * the per-sector density-matrix blocks (Eqs. (2)-(3)): all eigenpairs by
 //   Householder reduction to tridiagonal form followed by implicitly shifted
 //   QR sweeps with Wilkinson shifts (Golub & Van Loan, Matrix Computations,
-//   Sec. 8.3), accumulating the transformations.
+//   Sec. 8.3).  The QR sweeps run on the tridiagonal alone and record their
+//   rotations; applying those rotations and the Householder reflectors to
+//   the eigenvector matrix, the O(n^3) part, is split over host threads.
 #include "eigen.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <limits>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 namespace dmrg {
@@ -118,15 +122,42 @@ void tridiag_lowest(int n, const double* a, const double* b, double* theta, doub
   for (int i = 0; i < n; ++i) u[i] = sgn * x[i];
 }
 
-bool sym_eigen(int n, double* A, double* w) {
+namespace {
+
+// Run body(t) for t in [0, nthreads) on that many threads (the caller's
+// thread takes t = 0).
+template <class F>
+void parallel(int nthreads, F body) {
+  if (nthreads <= 1) {
+    body(0);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(nthreads - 1);
+  for (int t = 1; t < nthreads; ++t) th.emplace_back(body, t);
+  body(0);
+  for (auto& x : th) x.join();
+}
+
+// sqrt(x^2 + z^2) without the cost of std::hypot where the squares can
+// neither overflow nor lose precision to underflow.
+inline double safe_hypot(double x, double z) {
+  const double m = std::max(std::fabs(x), std::fabs(z));
+  if (m > 1e-150 && m < 1e150) return std::sqrt(x * x + z * z);
+  return std::hypot(x, z);
+}
+
+
+}  // namespace
+
+bool sym_eigen(int n, double* A, double* w, int nthreads) {
   if (n <= 0) return true;
-  // QT holds the accumulated orthogonal transformation transposed: row j of
-  // QT is column j of Q, so both the reflector and the rotation updates walk
-  // contiguous memory.
-  std::vector<double> QT((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) QT[(size_t)i * n + i] = 1.0;
-  std::vector<double> v(n), p(n), ww(n), sr(n);
-  // Householder reduction: column k below the subdiagonal is annihilated.
+  nthreads = std::max(1, std::min(nthreads, (n + 31) / 32));
+  // 1. Householder reduction to tridiagonal form on the lower triangle.
+  //    Reflector k is H_k = I - beta_k v_k v_k^T with v_k[0..k] = 0; its
+  //    nonzero part v_k[k+1..n) is kept in R[k][k+1..n).
+  std::vector<double> R((size_t)n * n, 0.0), betas(n, 0.0);
+  std::vector<double> v(n), p(n);
   for (int k = 0; k + 2 < n; ++k) {
     double sigma = 0.0;
     for (int i = k + 2; i < n; ++i) sigma += A[(size_t)i * n + k] * A[(size_t)i * n + k];
@@ -134,47 +165,53 @@ bool sym_eigen(int n, double* A, double* w) {
     const double x0 = A[(size_t)(k + 1) * n + k];
     const double norm = std::sqrt(x0 * x0 + sigma);
     const double alpha = x0 <= 0.0 ? norm : -norm;
-    std::fill(v.begin(), v.end(), 0.0);
     v[k + 1] = x0 - alpha;
     for (int i = k + 2; i < n; ++i) v[i] = A[(size_t)i * n + k];
-    const double vtv = v[k + 1] * v[k + 1] + sigma;
-    const double beta = 2.0 / vtv;
-    // p = beta * A v on the trailing block
+    const double beta = 2.0 / (v[k + 1] * v[k + 1] + sigma);
+    // p = beta * A v over the trailing block, reading the lower triangle
+    // only: row i contributes A[i][j] v[j] to p[i] and A[i][j] v[i] to p[j]
+    // for j < i, both along contiguous memory.
+    for (int i = k + 1; i < n; ++i) p[i] = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      const double* ai = &A[(size_t)i * n];
+      const double vi = v[i];
+      double s = 0.0;
+      for (int j = k + 1; j < i; ++j) {
+        s += ai[j] * v[j];
+        p[j] += ai[j] * vi;
+      }
+      p[i] += s + ai[i] * vi;
+    }
     double vtp = 0.0;
     for (int i = k + 1; i < n; ++i) {
-      double s = 0.0;
-      for (int j = k + 1; j < n; ++j) s += A[(size_t)i * n + j] * v[j];
-      p[i] = beta * s;
+      p[i] *= beta;
       vtp += v[i] * p[i];
     }
     const double K = 0.5 * beta * vtp;
-    for (int i = k + 1; i < n; ++i) ww[i] = p[i] - K * v[i];
-    for (int i = k + 1; i < n; ++i)
-      for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= v[i] * ww[j] + ww[i] * v[j];
+    for (int i = k + 1; i < n; ++i) p[i] -= K * v[i];   // p becomes w
+    for (int i = k + 1; i < n; ++i) {
+      double* ai = &A[(size_t)i * n];
+      const double vi = v[i], wi = p[i];
+      for (int j = k + 1; j <= i; ++j) ai[j] -= vi * p[j] + wi * v[j];
+    }
     A[(size_t)(k + 1) * n + k] = alpha;
-    A[(size_t)k * n + (k + 1)] = alpha;
-    for (int i = k + 2; i < n; ++i) {
-      A[(size_t)i * n + k] = 0.0;
-      A[(size_t)k * n + i] = 0.0;
-    }
-    // Q <- Q H: s_r = beta * sum_j Q[r][j] v[j]; Q[r][j] -= s_r v[j]
-    std::fill(sr.begin(), sr.end(), 0.0);
-    for (int j = k + 1; j < n; ++j) {
-      const double vj = v[j];
-      const double* q = &QT[(size_t)j * n];
-      for (int r = 0; r < n; ++r) sr[r] += q[r] * vj;
-    }
-    for (int r = 0; r < n; ++r) sr[r] *= beta;
-    for (int j = k + 1; j < n; ++j) {
-      const double vj = v[j];
-      double* q = &QT[(size_t)j * n];
-      for (int r = 0; r < n; ++r) q[r] -= sr[r] * vj;
-    }
+    for (int i = k + 2; i < n; ++i) A[(size_t)i * n + k] = 0.0;
+    betas[k] = beta;
+    std::copy(v.begin() + k + 1, v.end(), R.begin() + (size_t)k * n + k + 1);
   }
   std::vector<double> d(n), e(n, 0.0);
   for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
   for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];
-  // Implicit symmetric QR with Wilkinson shifts; Q accumulates the rotations.
+
+  // 2. Implicit symmetric QR with Wilkinson shifts on (d, e).  Each rotation
+  //    acts on rows k and k+1 of Z^T (columns of the tridiagonal's
+  //    eigenvector matrix Z); it is recorded as (k, c, s) and applied in
+  //    step 3.
+  std::vector<int32_t> rk;
+  std::vector<double> rc, rs;
+  rk.reserve((size_t)4 * n * n / 2 + 16);
+  rc.reserve(rk.capacity());
+  rs.reserve(rk.capacity());
   const double eps = std::numeric_limits<double>::epsilon();
   int hi = n - 1;
   long iters = 0;
@@ -199,7 +236,7 @@ bool sym_eigen(int n, double* A, double* w) {
         x = e[k - 1];
         z = bulge;
       }
-      const double r = std::hypot(x, z);
+      const double r = safe_hypot(x, z);
       double c = 1.0, s = 0.0;
       if (r != 0.0) {
         c = x / r;
@@ -217,22 +254,66 @@ bool sym_eigen(int n, double* A, double* w) {
         bulge = -s * e[k + 1];
         e[k + 1] = c * e[k + 1];
       }
-      double* qk = &QT[(size_t)k * n];
-      double* qk1 = &QT[(size_t)(k + 1) * n];
-      for (int row = 0; row < n; ++row) {
-        const double zk = qk[row], zk1 = qk1[row];
-        qk[row] = c * zk - s * zk1;
-        qk1[row] = s * zk + c * zk1;
-      }
+      rk.push_back(k);
+      rc.push_back(c);
+      rs.push_back(s);
     }
   }
+
+  // 3. Z^T = (rotations) applied to the identity; the columns r of Z^T are
+  //    independent, so threads take disjoint column ranges and every element
+  //    sees the same operations in the same order for any thread count.
+  // 4. Eigenvectors V = H_0 H_1 ... H_{n-3} Z: column c of Z (row c of Z^T)
+  //    gets the reflectors applied last to first; columns are independent.
+  // Rows of Z^T start on 64-byte boundaries with a stride of whole cache
+  // lines, so the column ranges of different threads share no line.
+  const int ld = (n + 7) / 8 * 8;
+  std::vector<double> zbuf((size_t)n * ld + 8, 0.0);
+  double* ZT = zbuf.data() + ((8 - (reinterpret_cast<uintptr_t>(zbuf.data()) / 8) % 8) % 8);
+  for (int i = 0; i < n; ++i) ZT[(size_t)i * ld + i] = 1.0;
+  const size_t nrot = rk.size();
+  // One thread sweeps the whole width; several threads take one-line strips
+  // round robin (strip i to thread i mod nthreads), which keeps each
+  // thread's strip in its first-level cache while the rotation list streams.
+  const int width = nthreads == 1 ? ld : 8;
+  const int nstrip = ld / width;
+  parallel(nthreads, [&](int t) {
+    for (int st = t; st < nstrip; st += nthreads) {
+      const int c0 = st * width, c1 = std::min(n, c0 + width);
+      for (size_t q = 0; q < nrot; ++q) {
+        const double c = rc[q], s = rs[q];
+        double* zk = &ZT[(size_t)rk[q] * ld];
+        double* zk1 = zk + ld;
+        for (int r = c0; r < c1; ++r) {
+          const double a = zk[r], b = zk1[r];
+          zk[r] = c * a - s * b;
+          zk1[r] = s * a + c * b;
+        }
+      }
+    }
+  });
+  parallel(nthreads, [&](int t) {
+    const int per = (n + nthreads - 1) / nthreads;
+    const int r0 = std::min(n, t * per), r1 = std::min(n, (t + 1) * per);
+    for (int row = r0; row < r1; ++row) {
+      double* z = &ZT[(size_t)row * ld];
+      for (int k = n - 3; k >= 0; --k) {
+        if (betas[k] == 0.0) continue;
+        const double* vk = &R[(size_t)k * n];
+        double s = 0.0;
+        for (int i = k + 1; i < n; ++i) s += vk[i] * z[i];
+        s *= betas[k];
+        for (int i = k + 1; i < n; ++i) z[i] -= s * vk[i];
+      }
+    }
+  });
   // sort ascending; eigenvectors as columns of A
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
   for (int c = 0; c < n; ++c) {
     w[c] = d[idx[c]];
-    const double* q = &QT[(size_t)idx[c] * n];
+    const double* q = &ZT[(size_t)idx[c] * ld];
     for (int r = 0; r < n; ++r) A[(size_t)r * n + c] = q[r];
   }
   return true;

@@ -11,6 +11,8 @@ void tridiag_lowest(int n, const double* a, const double* b, double* theta, doub
 // All eigenpairs of the dense symmetric n x n row-major matrix A: on return
 // w holds the eigenvalues in ascending order and column c of A the
 // eigenvector of w[c].  Returns false if the QR sweeps did not converge.
-bool sym_eigen(int n, double* A, double* w);
+// nthreads host threads share the eigenvector work (capped at one per 32
+// rows); the result is bit-identical for every thread count.
+bool sym_eigen(int n, double* A, double* w, int nthreads = 1);
 
 }  // namespace dmrg
