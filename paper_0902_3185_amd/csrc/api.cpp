@@ -564,14 +564,14 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   const int per_cycle = reduced ? 100 : std::min<int>(max_iter, 400);
   const int nvec = per_cycle + 1;
   constexpr int kCheck = 4;
-  const int nblk = std::max(lz_blocks(D), vec_blocks(D));
+  const size_t npart = std::max(lz_partial_size(D, nvec), (size_t)vec_blocks(D));
   HIP_TRY(ctx->V.ensure((size_t)nvec * D * sizeof(double)));
   HIP_TRY(ctx->w.ensure((size_t)D * sizeof(double)));
-  HIP_TRY(ctx->partial.ensure((size_t)nvec * nblk * sizeof(double)));
-  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec], counter
-  const size_t nsmall = (size_t)5 * nvec + 16;
+  HIP_TRY(ctx->partial.ensure(npart * sizeof(double)));
+  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec]
+  const size_t nsmall = (size_t)5 * nvec + 8;
   HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
-  HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));   // counter starts at 0
+  HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));
   if (ctx->host_small_n < nsmall) {
     if (ctx->host_small) (void)hipHostFree(ctx->host_small);
     ctx->host_small = nullptr;
@@ -586,7 +586,6 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   double* ud = h2 + nvec;
   double* nrm2 = ud + nvec;
   double* ab = nrm2 + 8;
-  unsigned int* counter = reinterpret_cast<unsigned int*>(ab + 2 * nvec);
   double* hs = ctx->host_small;
 
   // v0 = psi0 / |psi0|
@@ -606,7 +605,7 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
       if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
       ++total;
-      HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, counter, ab + 2 * j,
+      HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
                              j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, s));
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
@@ -963,11 +962,12 @@ dmrg_status dmrg_lanczos_tridiag(dmrg_sb sb, const double* v0_d, int32_t nsteps,
   hipStream_t s = ctx->stream;
   const int64_t D = sb->fwd.plan.D;
   const int nvec = nsteps + 1;
-  const int nblk = std::max(lz_blocks(D), vec_blocks(D));
+  const size_t npart = std::max(lz_partial_size(D, nvec), (size_t)vec_blocks(D));
   HIP_TRY(ctx->V.ensure((size_t)nvec * D * sizeof(double)));
   HIP_TRY(ctx->w.ensure((size_t)D * sizeof(double)));
-  HIP_TRY(ctx->partial.ensure((size_t)nvec * nblk * sizeof(double)));
-  const size_t nsmall = (size_t)5 * nvec + 16;
+  HIP_TRY(ctx->partial.ensure(npart * sizeof(double)));
+  // small: h1[nvec], h2[nvec], (unused)[nvec], nrm2[8], ab[2*nvec]
+  const size_t nsmall = (size_t)5 * nvec + 8;
   HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
   HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));
   double* V = ctx->V.as<double>();
@@ -977,12 +977,11 @@ dmrg_status dmrg_lanczos_tridiag(dmrg_sb sb, const double* v0_d, int32_t nsteps,
   double* h2 = h1 + nvec;
   double* nrm2 = h2 + 2 * nvec;
   double* ab = nrm2 + 8;
-  unsigned int* counter = reinterpret_cast<unsigned int*>(ab + 2 * nvec);
   HIP_TRY(launch_multi_dot(v0_d, 0, 1, v0_d, D, part, nrm2, s));
   HIP_TRY(launch_normalise(V, v0_d, nrm2, D, s));
   for (int j = 0; j < nsteps; ++j) {
     if ((st = run_product(sb, sb->fwd, sb->prec, V + (size_t)j * D, w, 1.0, 0.0)) != DMRG_OK) return st;
-    HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, counter, ab + 2 * j,
+    HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
                            V + (size_t)(j + 1) * D, s));
   }
   std::vector<double> hs(2 * nsteps + 1);

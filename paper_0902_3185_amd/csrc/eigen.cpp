@@ -213,17 +213,31 @@ bool sym_eigen(int n, double* A, double* w, int nthreads) {
   rc.reserve(rk.capacity());
   rs.reserve(rk.capacity());
   const double eps = std::numeric_limits<double>::epsilon();
+  // An off-diagonal entry is dropped once it is below eps relative to its
+  // two diagonal neighbours or below eps * ||T|| (the normwise backward
+  // error the Householder reduction already commits); the second test keeps
+  // rank-deficient blocks, whose null space is pure rounding noise, from
+  // iterating on that noise.
+  double anorm = 0.0;
+  for (int i = 0; i < n; ++i)
+    anorm = std::max(anorm, std::fabs(d[i]) + (i > 0 ? std::fabs(e[i - 1]) : 0.0) +
+                                (i + 1 < n ? std::fabs(e[i]) : 0.0));
+  const double small = eps * anorm;
+  auto negligible = [&](int k) {
+    const double a = std::fabs(e[k]);
+    return a == 0.0 || a <= small || a <= eps * (std::fabs(d[k]) + std::fabs(d[k + 1]));
+  };
   int hi = n - 1;
   long iters = 0;
   const long cap = 60L * n + 100;
   while (hi > 0) {
-    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi])) || e[hi - 1] == 0.0) {
+    if (negligible(hi - 1)) {
       e[hi - 1] = 0.0;
       --hi;
       continue;
     }
     int lo = hi - 1;
-    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    while (lo > 0 && !negligible(lo - 1)) --lo;
     if (lo > 0) e[lo - 1] = 0.0;
     if (++iters > cap) return false;
     const double aa = d[hi - 1], bb = e[hi - 1], cc = d[hi];

@@ -3,6 +3,8 @@
 // Reductions go through fixed-shape partial sums, so results are repeatable.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace dmrg {
@@ -133,137 +135,206 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 }
 
 // ---------------------------------------------------------------------------
-// Fused CGS2 passes for one Lanczos step.  Each kernel walks the Krylov basis
-// once; every block writes its partial sums, and the last block to finish
-// (counted with one device-scope atomic) adds them up in a fixed order and
-// resets the counter, so results are repeatable and no extra launch is needed.
+// One CGS2 step of the Lanczos recursion in bandwidth-shaped launches:
+//   dot     partial sums of V^T w   grid (element chunks) x (groups of kDotG vectors)
+//   reduce  h1 = sum of the partials, one wave per basis vector
+//   axpy    w -= V h1               grid (element chunks), all basis vectors per thread
+//   dot, reduce  h2 = V^T w
+//   axpy    w -= V h2 and partial sums of ||w||^2
+//   finish  (alpha, beta) and v_next = w / beta
+// Partial sums are added in a fixed order by the next launch, so results are
+// repeatable; the kernel boundary makes them visible across the chip without
+// any cache maintenance inside the kernels.
 // ---------------------------------------------------------------------------
 constexpr int kLzThreads = 256;
-constexpr int kLzPer = 8;                       // elements per thread
-constexpr int kLzSpan = kLzThreads * kLzPer;    // elements per block
+constexpr int kDotPer = 4;                       // elements per thread (dot)
+constexpr int kDotSpan = kLzThreads * kDotPer;   // elements per block (dot)
+constexpr int kDotG = 8;                         // basis vectors per block (dot)
+constexpr int kAxPer = 2;                        // elements per thread (axpy)
+constexpr int kAxSpan = kLzThreads * kAxPer;     // elements per block (axpy)
 
-int lz_blocks(int64_t n) { return (int)((n + kLzSpan - 1) / kLzSpan); }
+int dot_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kDotSpan - 1) / kDotSpan); }
+int axpy_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kAxSpan - 1) / kAxSpan); }
 
-// Returns true in every thread of the block that finished last.
-__device__ inline bool last_block_done(unsigned int* counter) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int done = atomicAdd(counter, 1u);
-    last = done == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
+size_t lz_partial_size(int64_t n, int nv) {
+  return std::max((size_t)nv * dot_blocks(n), (size_t)axpy_blocks(n));
 }
 
-// out[j] = sum_b partial[j * nblk + b] (b ascending), by the whole block.
-__device__ inline void reduce_partials(const double* partial, int nblk, int nv, double* out,
-                                       double* sh) {
-  for (int j = 0; j < nv; ++j) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kLzThreads) s += partial[(int64_t)j * nblk + b];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) out[j] = s;
-  }
-}
-
-// Mode 0: h1 = V^T w.
-// Mode 1: w -= V h1, then h2 = V^T w.
-// Mode 2: w -= V h2, then nrm = ||w||^2 and ab[0..1] = (h1[j] + h2[j], sqrt(nrm)).
-template <int kMode>
-__global__ __launch_bounds__(kLzThreads) void lz_pass(double* __restrict__ w,
-                                                      const double* __restrict__ V, int64_t ldv,
-                                                      int nv, int64_t n, double* __restrict__ h1,
-                                                      double* __restrict__ h2,
-                                                      double* __restrict__ partial,
-                                                      unsigned int* __restrict__ counter,
-                                                      double* __restrict__ ab) {
-  __shared__ double sh[4];
-  const int nblk = gridDim.x;
-  const int64_t base = (int64_t)blockIdx.x * kLzSpan + threadIdx.x;
-  double x[kLzPer];
+__device__ inline double wave_sum(double v) {
 #pragma unroll
-  for (int q = 0; q < kLzPer; ++q) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of row[0..cnt) by one wave: lane l adds l, l+64, ... in order, then a
+// fixed butterfly.  Every lane returns the total.
+__device__ inline double wave_row_sum(const double* row, int cnt) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int b = lane; b < cnt; b += 64) s += row[b];
+  return wave_sum(s);
+}
+
+// partial[(g0 + g) * gridDim.x + blockIdx.x] = block part of <V_{g0+g}, w>,
+// g < kDotG; blockIdx.y selects g0.
+__global__ __launch_bounds__(kLzThreads) void lz_dot(const double* __restrict__ V, int64_t ldv,
+                                                     int nv, const double* __restrict__ w,
+                                                     int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[kLzThreads / 64][kDotG];
+  const int nbx = gridDim.x;
+  const int g0 = blockIdx.y * kDotG;
+  const int ng = min(kDotG, nv - g0);
+  const int64_t start = (int64_t)blockIdx.x * kDotSpan;
+  const int64_t base = start + threadIdx.x;
+  const bool full = start + kDotSpan <= n;
+  double x[kDotPer];
+  double s[kDotG];
+#pragma unroll
+  for (int q = 0; q < kDotPer; ++q) {
     const int64_t i = base + (int64_t)q * kLzThreads;
-    x[q] = i < n ? w[i] : 0.0;
+    x[q] = (full || i < n) ? w[i] : 0.0;
   }
-  if (kMode >= 1) {
-    const double* h = kMode == 1 ? h1 : h2;
-    for (int j = 0; j < nv; ++j) {
-      const double hj = h[j];
-      const double* Vj = V + (int64_t)j * ldv;
+  if (ng == kDotG && full) {
 #pragma unroll
-      for (int q = 0; q < kLzPer; ++q) {
-        const int64_t i = base + (int64_t)q * kLzThreads;
-        if (i < n) x[q] -= hj * Vj[i];
-      }
-    }
+    for (int g = 0; g < kDotG; ++g) {
+      const double* Vg = V + (int64_t)(g0 + g) * ldv + base;
+      double a = 0.0;
 #pragma unroll
-    for (int q = 0; q < kLzPer; ++q) {
-      const int64_t i = base + (int64_t)q * kLzThreads;
-      if (i < n) w[i] = x[q];
-    }
-  }
-  if (kMode <= 1) {
-    for (int j = 0; j < nv; ++j) {
-      const double* Vj = V + (int64_t)j * ldv;
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < kLzPer; ++q) {
-        const int64_t i = base + (int64_t)q * kLzThreads;
-        if (i < n) s += Vj[i] * x[q];
-      }
-      s = block_sum(s, sh);
-      if (threadIdx.x == 0) partial[(int64_t)j * nblk + blockIdx.x] = s;
+      for (int q = 0; q < kDotPer; ++q) a += Vg[(int64_t)q * kLzThreads] * x[q];
+      s[g] = a;
     }
   } else {
-    double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < kLzPer; ++q) s += x[q] * x[q];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  }
-  if (!last_block_done(counter)) return;
-  if (kMode == 2) {
-    __shared__ double nrm;
-    reduce_partials(partial, nblk, 1, &nrm, sh);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      ab[0] = h1[nv - 1] + h2[nv - 1];
-      ab[1] = sqrt(nrm > 0.0 ? nrm : 0.0);
+    for (int g = 0; g < kDotG; ++g) {
+      double a = 0.0;
+      if (g < ng) {
+        const double* Vg = V + (int64_t)(g0 + g) * ldv;
+#pragma unroll
+        for (int q = 0; q < kDotPer; ++q) {
+          const int64_t i = base + (int64_t)q * kLzThreads;
+          if (i < n) a += Vg[i] * x[q];
+        }
+      }
+      s[g] = a;
     }
-  } else {
-    reduce_partials(partial, nblk, nv, kMode == 0 ? h1 : h2, sh);
   }
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int g = 0; g < kDotG; ++g) {
+    const double t = wave_sum(s[g]);
+    if (lane == 0) sh[wave][g] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < ng) {
+    const int g = threadIdx.x;
+    partial[(int64_t)(g0 + g) * nbx + blockIdx.x] = ((sh[0][g] + sh[1][g]) + sh[2][g]) + sh[3][g];
+  }
 }
 
-// v_next = w / ab[1]
-__global__ __launch_bounds__(kThreads) void lz_normalise(double* __restrict__ v,
-                                                         const double* __restrict__ w,
-                                                         const double* __restrict__ ab,
-                                                         int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const double b = ab[1];
+// h[i] = sum_b partial[i * nbx + b]: one 64-thread block per basis vector.
+__global__ __launch_bounds__(64) void lz_reduce(const double* __restrict__ partial, int nbx,
+                                                double* __restrict__ h) {
+  const double t = wave_row_sum(partial + (int64_t)blockIdx.x * nbx, nbx);
+  if (threadIdx.x == 0) h[blockIdx.x] = t;
+}
+
+// w -= sum_{i<nv} h[i] V_i.  With kNorm, also partial[blockIdx.x] = the
+// block's part of ||w||^2.
+template <bool kNorm>
+__global__ __launch_bounds__(kLzThreads) void lz_axpy(double* __restrict__ w,
+                                                      const double* __restrict__ V, int64_t ldv,
+                                                      int nv, int64_t n,
+                                                      const double* __restrict__ h,
+                                                      double* __restrict__ partial) {
+  const int64_t start = (int64_t)blockIdx.x * kAxSpan;
+  const int64_t base = start + threadIdx.x;
+  const bool full = start + kAxSpan <= n;
+  double x[kAxPer];
+#pragma unroll
+  for (int q = 0; q < kAxPer; ++q) {
+    const int64_t i = base + (int64_t)q * kLzThreads;
+    x[q] = (full || i < n) ? w[i] : 0.0;
+  }
+  if (full) {
+    const double* Vb = V + base;
+#pragma unroll 8
+    for (int i = 0; i < nv; ++i) {
+      const double hi = h[i];
+      const double* Vi = Vb + (int64_t)i * ldv;
+#pragma unroll
+      for (int q = 0; q < kAxPer; ++q) x[q] -= hi * Vi[(int64_t)q * kLzThreads];
+    }
+  } else {
+    for (int i = 0; i < nv; ++i) {
+      const double hi = h[i];
+      const double* Vi = V + (int64_t)i * ldv;
+#pragma unroll
+      for (int q = 0; q < kAxPer; ++q) {
+        const int64_t e = base + (int64_t)q * kLzThreads;
+        if (e < n) x[q] -= hi * Vi[e];
+      }
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kAxPer; ++q) {
+    const int64_t e = base + (int64_t)q * kLzThreads;
+    if (full || e < n) {
+      w[e] = x[q];
+      s += x[q] * x[q];
+    }
+  }
+  if (!kNorm) return;
+  __shared__ double sh[kLzThreads / 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  s = wave_sum(s);
+  if (lane == 0) sh[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// beta = sqrt(sum of partial[0..np)) (every block adds the same partials in
+// the same order); block 0 writes ab[0] = h1[j] + h2[j] and ab[1] = beta;
+// v_next = w / beta where v_next is given.
+__global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ partial, int np,
+                                                      const double* __restrict__ h1,
+                                                      const double* __restrict__ h2, int j,
+                                                      double* __restrict__ ab, int64_t n) {
+  __shared__ double beta;
+  if (threadIdx.x < 64) {
+    const double nrm = wave_row_sum(partial, np);
+    if (threadIdx.x == 0) beta = sqrt(nrm > 0.0 ? nrm : 0.0);
+  }
+  __syncthreads();
+  const double b = beta;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ab[0] = h1[j] + h2[j];
+    ab[1] = b;
+  }
+  if (!v) return;
   const double inv = b > 0.0 ? 1.0 / b : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i < n) v[i] = w[i] * inv;
 }
 
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
-                          double* h1, double* h2, double* partial, unsigned int* counter,
-                          double* ab, double* vnext, hipStream_t stream) {
-  const int nblk = lz_blocks(n);
-  hipLaunchKernelGGL(lz_pass<0>, dim3(nblk), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1, h2,
-                     partial, counter, ab);
-  hipLaunchKernelGGL(lz_pass<1>, dim3(nblk), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1, h2,
-                     partial, counter, ab);
-  hipLaunchKernelGGL(lz_pass<2>, dim3(nblk), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1, h2,
-                     partial, counter, ab);
-  if (vnext)
-    hipLaunchKernelGGL(lz_normalise, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                       stream, vnext, w, ab, n);
+                          double* h1, double* h2, double* partial, double* ab, double* vnext,
+                          hipStream_t stream) {
+  const dim3 gd(dot_blocks(n), (nv + kDotG - 1) / kDotG);
+  const int na = axpy_blocks(n);
+  hipLaunchKernelGGL(lz_dot, gd, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, (int)gd.x, h1);
+  hipLaunchKernelGGL(lz_axpy<false>, dim3(na), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
+                     partial);
+  hipLaunchKernelGGL(lz_dot, gd, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, (int)gd.x, h2);
+  hipLaunchKernelGGL(lz_axpy<true>, dim3(na), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h2,
+                     partial);
+  const unsigned nfin = vnext ? (unsigned)((n + kThreads - 1) / kThreads) : 1u;
+  hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, na, h1, h2,
+                     nv - 1, ab, n);
   return hipGetLastError();
 }
 

@@ -136,6 +136,24 @@ def test_host_sym_eigen_matches_numpy():
         assert np.allclose(A @ V, V * w[None, :], atol=1e-12 * scale * n)
 
 
+def test_host_sym_eigen_rank_deficient_density_matrices():
+    """rho = Psi Psi^T of rank r < n (the untruncated small blocks of a run),
+    with its null space at rounding level: all eigenpairs, no stall."""
+    rng = np.random.default_rng(7)
+    for n, r in ((64, 20), (150, 30), (256, 64), (97, 1)):
+        X = rng.standard_normal((n, r)) * np.exp(-0.4 * np.arange(r))[None, :]
+        A = X @ X.T
+        A /= np.trace(A)
+        a = np.ascontiguousarray(A.copy())
+        w = np.zeros(n)
+        _lib.check(_lib.lib().dmrg_host_sym_eigen(n, a.ctypes.data_as(C.POINTER(C.c_double)),
+                                                  w.ctypes.data_as(C.POINTER(C.c_double))))
+        wr = np.linalg.eigvalsh(A)
+        assert np.allclose(w, wr, atol=1e-14 * n)
+        assert np.allclose(a.T @ a, np.eye(n), atol=1e-12 * n)
+        assert np.allclose(A @ a, a * w[None, :], atol=1e-14 * n)
+
+
 def test_host_tridiag_lowest():
     rng = np.random.default_rng(1)
     for n in (1, 2, 5, 40, 300):
