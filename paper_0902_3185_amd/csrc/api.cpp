@@ -90,7 +90,10 @@ struct DeviceGuard {
 // A plan and its device copy.
 struct Staged {
   Plan plan;
-  DevBuf order, tiles, segs, gsrc, gscale, dense64, dense32;
+  DevBuf tiles, segs, gsrc, gscale, dense64, dense32;
+  DevBuf images;            // one tile image per workgroup slot of the fused kernel
+  int32_t img_stride = 0;   // words per image
+  int32_t nslots = 0;
   bool has32 = false;
   int max_nseg = 0;
   std::vector<std::pair<SegDesc, TileDesc>> plain;  // one entry per (block, term)
@@ -110,7 +113,7 @@ struct OpCopy {
 struct dmrg_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
-  DevBuf tr_tiles, tr_segs, tr_tmp;   // basis-change scratch
+  DevBuf tr_images, tr_tmp;   // basis-change scratch
   // optional per-launch timing of the product kernels (HIP events on `stream`)
   bool timing = false;
   struct Mark {
@@ -140,7 +143,7 @@ struct dmrg_sb_s {
   Staged fwd;
   std::unique_ptr<Staged> adj;
   // density-matrix scratch and results
-  DevBuf rho_tiles, rho_segs, rho_out;
+  DevBuf rho_images, rho_out;
   std::vector<double> tr_lambda;
   std::vector<int32_t> tr_sec, tr_kps;
   std::vector<std::vector<double>> tr_W;
@@ -155,11 +158,25 @@ dmrg_status upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s) {
   return DMRG_OK;
 }
 
+// Tile images of a staged plan (again after a coefficient change).
+dmrg_status stage_images(Staged& st, hipStream_t s) {
+  std::vector<uint32_t> img;
+  std::string err;
+  if (!build_images(st.plan.tiles, st.plan.segs, st.plan.order, st.plan.gsrc, st.plan.gscale, img,
+                    st.img_stride, err))
+    return fail(DMRG_E_UNSUPPORTED, err);
+  st.nslots = (int32_t)st.plan.order.size();
+  dmrg_status r = upload(st.images, img.data(), img.size() * sizeof(uint32_t), s);
+  if (r != DMRG_OK) return r;
+  HIP_TRY(hipStreamSynchronize(s));   // the host image vector dies here
+  return DMRG_OK;
+}
+
 dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
   const Plan& p = st.plan;
   hipStream_t s = ctx->stream;
   dmrg_status r;
-  if ((r = upload(st.order, p.order.data(), p.order.size() * sizeof(int32_t), s)) != DMRG_OK) return r;
+  if ((r = stage_images(st, s)) != DMRG_OK) return r;
   if ((r = upload(st.tiles, p.tiles.data(), p.tiles.size() * sizeof(TileDesc), s)) != DMRG_OK) return r;
   if ((r = upload(st.segs, p.segs.data(), p.segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return r;
   if ((r = upload(st.gsrc, p.gsrc.data(), p.gsrc.size() * sizeof(int32_t), s)) != DMRG_OK) return r;
@@ -235,9 +252,8 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
     if (!st.has32) return fail(DMRG_E_ARG, "FP32 operators not staged (use dmrg_sb_set_prec)");
     dense = st.dense32.p;
   }
-  HIP_TRY(launch_hpsi(kernel_prec(prec), (int)p.order.size(), st.order.as<int32_t>(),
-                      st.tiles.as<TileDesc>(), st.segs.as<SegDesc>(), dense, st.gsrc.as<int32_t>(),
-                      st.gscale.as<double>(), psi, y, alpha, beta, s));
+  HIP_TRY(launch_hpsi(kernel_prec(prec), st.nslots, st.images.as<uint32_t>(), st.img_stride, dense,
+                      psi, y, alpha, beta, s));
   return DMRG_OK;
 }
 
@@ -470,7 +486,8 @@ dmrg_status dmrg_sb_set_coeffs(dmrg_sb sb, const double* c_h) {
       DeviceGuard g(sb->ctx->device);
       HIP_TRY(hipMemcpyAsync(st->segs.p, st->plan.segs.data(), st->plan.segs.size() * sizeof(SegDesc),
                              hipMemcpyHostToDevice, sb->ctx->stream));
-      HIP_TRY(hipStreamSynchronize(sb->ctx->stream));
+      dmrg_status r = stage_images(*st, sb->ctx->stream);
+      if (r != DMRG_OK) return r;
     }
   }
   return DMRG_OK;
@@ -730,11 +747,15 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
       }
     total += (int64_t)n * n;
   }
-  if ((st = upload(sb->rho_tiles, tiles.data(), tiles.size() * sizeof(TileDesc), s)) != DMRG_OK) return st;
-  if ((st = upload(sb->rho_segs, segs.data(), segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return st;
+  std::vector<uint32_t> img;
+  int32_t stride = 0;
+  {
+    std::string err;
+    if (!build_images(tiles, segs, {}, {}, {}, img, stride, err)) return fail(DMRG_E_UNSUPPORTED, err);
+  }
+  if ((st = upload(sb->rho_images, img.data(), img.size() * sizeof(uint32_t), s)) != DMRG_OK) return st;
   HIP_TRY(sb->rho_out.ensure((size_t)std::max<int64_t>(total, 1) * sizeof(double)));
-  HIP_TRY(launch_hpsi(kPrecF64, (int)tiles.size(), nullptr, sb->rho_tiles.as<TileDesc>(),
-                      sb->rho_segs.as<SegDesc>(), psi_d, nullptr, nullptr, psi_d,
+  HIP_TRY(launch_hpsi(kPrecF64, (int)tiles.size(), sb->rho_images.as<uint32_t>(), stride, psi_d, psi_d,
                       sb->rho_out.as<double>(), 1.0, 0.0, s));
   std::vector<double> rho((size_t)total);
   HIP_TRY(hipMemcpyAsync(rho.data(), sb->rho_out.p, rho.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -756,6 +777,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   for (int i = 0; i < nsec; ++i) work[i] = i;
   std::stable_sort(work.begin(), work.end(), [&](int x, int y) { return ds[x] > ds[y]; });
   std::atomic<int> next(0), bad(0);
+  std::string bad_what;
   const int hw = host_threads();
   const int inner = std::max(1, hw / 2);   // threads inside one large sector's solve
   auto solve = [&]() {
@@ -773,7 +795,19 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
           A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
         }
       if (!sym_eigen(n, A.data(), wv.data(), n >= 128 ? inner : 1)) {
-        bad.fetch_add(1);
+        if (bad.fetch_add(1) == 0) {
+          int nonfinite = 0;
+          double amax = 0.0;
+          for (int64_t x = 0; x < (int64_t)n * n; ++x) {
+            const double v = rho_off[sec] >= 0 ? rho[rho_off[sec] + x] : 0.0;
+            if (!std::isfinite(v)) ++nonfinite;
+            else amax = std::max(amax, std::fabs(v));
+          }
+          std::ostringstream os;
+          os << "sector " << sec << " (dimension " << n << ", " << nonfinite
+             << " non-finite entries, max |rho| " << amax << ")";
+          bad_what = os.str();
+        }
         continue;
       }
       // decreasing order within the sector
@@ -794,7 +828,8 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     solve();
     for (auto& th : pool) th.join();
   }
-  if (bad.load() > 0) return fail(DMRG_E_NOCONV, "density-matrix eigen-solve did not converge");
+  if (bad.load() > 0)
+    return fail(DMRG_E_NOCONV, "density-matrix eigen-solve did not converge in " + bad_what);
   for (int sec = 0; sec < nsec; ++sec)
     for (int c = 0; c < ds[sec]; ++c) {
       const double raw = vals[sec][c];
@@ -937,17 +972,23 @@ dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock*
     }
   }
   const size_t n1 = tiles1.size(), n2 = tiles2.size();
-  std::vector<TileDesc> all(tiles1);
-  all.insert(all.end(), tiles2.begin(), tiles2.end());
+  std::vector<uint32_t> img1, img2;
+  int32_t stride1 = 0, stride2 = 0;
+  {
+    std::string err;
+    if (!build_images(tiles1, segs, {}, {}, {}, img1, stride1, err) ||
+        !build_images(tiles2, segs, {}, {}, {}, img2, stride2, err))
+      return fail(DMRG_E_UNSUPPORTED, err);
+  }
+  const size_t w1 = img1.size();
+  img1.insert(img1.end(), img2.begin(), img2.end());
   dmrg_status st;
-  if ((st = upload(ctx->tr_tiles, all.data(), all.size() * sizeof(TileDesc), s)) != DMRG_OK) return st;
-  if ((st = upload(ctx->tr_segs, segs.data(), segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return st;
+  if ((st = upload(ctx->tr_images, img1.data(), img1.size() * sizeof(uint32_t), s)) != DMRG_OK) return st;
   HIP_TRY(ctx->tr_tmp.ensure((size_t)std::max<int64_t>(utot, 1) * sizeof(double)));
-  const TileDesc* dt = ctx->tr_tiles.as<TileDesc>();
-  HIP_TRY(launch_hpsi(kPrecF64, (int)n1, nullptr, dt, ctx->tr_segs.as<SegDesc>(), O_d, nullptr,
-                      nullptr, W_d, ctx->tr_tmp.as<double>(), 1.0, 0.0, s));
-  HIP_TRY(launch_hpsi(kPrecF64, (int)n2, nullptr, dt + n1, ctx->tr_segs.as<SegDesc>(),
-                      ctx->tr_tmp.as<double>(), nullptr, nullptr, W_d, out_d, 1.0, 0.0, s));
+  const uint32_t* di = ctx->tr_images.as<uint32_t>();
+  HIP_TRY(launch_hpsi(kPrecF64, (int)n1, di, stride1, O_d, W_d, ctx->tr_tmp.as<double>(), 1.0, 0.0, s));
+  HIP_TRY(launch_hpsi(kPrecF64, (int)n2, di + w1, stride2, ctx->tr_tmp.as<double>(), W_d, out_d, 1.0,
+                      0.0, s));
   HIP_TRY(hipStreamSynchronize(s));   // the host tile lists die here
   return DMRG_OK;
 }

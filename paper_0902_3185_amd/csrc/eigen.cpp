@@ -159,14 +159,23 @@ bool sym_eigen(int n, double* A, double* w, int nthreads) {
   std::vector<double> R((size_t)n * n, 0.0), betas(n, 0.0);
   std::vector<double> v(n), p(n);
   for (int k = 0; k + 2 < n; ++k) {
+    // The column is scaled by its largest entry first: the reflector does
+    // not change, and its norm neither underflows nor overflows (the
+    // trailing columns of a low-rank density matrix decay towards the
+    // underflow threshold).
+    double scale = 0.0;
+    for (int i = k + 1; i < n; ++i) scale = std::max(scale, std::fabs(A[(size_t)i * n + k]));
+    if (scale == 0.0) continue;
     double sigma = 0.0;
-    for (int i = k + 2; i < n; ++i) sigma += A[(size_t)i * n + k] * A[(size_t)i * n + k];
+    for (int i = k + 2; i < n; ++i) {
+      v[i] = A[(size_t)i * n + k] / scale;
+      sigma += v[i] * v[i];
+    }
     if (sigma == 0.0) continue;
-    const double x0 = A[(size_t)(k + 1) * n + k];
+    const double x0 = A[(size_t)(k + 1) * n + k] / scale;
     const double norm = std::sqrt(x0 * x0 + sigma);
     const double alpha = x0 <= 0.0 ? norm : -norm;
     v[k + 1] = x0 - alpha;
-    for (int i = k + 2; i < n; ++i) v[i] = A[(size_t)i * n + k];
     const double beta = 2.0 / (v[k + 1] * v[k + 1] + sigma);
     // p = beta * A v over the trailing block, reading the lower triangle
     // only: row i contributes A[i][j] v[j] to p[i] and A[i][j] v[i] to p[j]
@@ -194,7 +203,7 @@ bool sym_eigen(int n, double* A, double* w, int nthreads) {
       const double vi = v[i], wi = p[i];
       for (int j = k + 1; j <= i; ++j) ai[j] -= vi * p[j] + wi * v[j];
     }
-    A[(size_t)(k + 1) * n + k] = alpha;
+    A[(size_t)(k + 1) * n + k] = alpha * scale;
     for (int i = k + 2; i < n; ++i) A[(size_t)i * n + k] = 0.0;
     betas[k] = beta;
     std::copy(v.begin() + k + 1, v.end(), R.begin() + (size_t)k * n + k + 1);

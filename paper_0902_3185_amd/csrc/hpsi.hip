@@ -217,47 +217,49 @@ __device__ inline double gg_term(const SegDesc& sg, const TileDesc& t, int m, in
 }
 
 // ---------------------------------------------------------------------------
-// y = alpha * H psi + beta * y.  Workgroup slot b takes tile order[b]
-// (-1: idle slot), so that the blocks of one target pair share an XCD.
+// y = alpha * H psi + beta * y.  Workgroup slot b owns the 32 x 32 output
+// tile described by image b (see plan.h): the host orders the slots so that
+// the blocks of one target pair share an XCD.
 //
-// Phase 0  the gather entries of the tile's 32 rows / columns for every
-//          matrix-core segment go to LDS; the elementwise (gather-gather)
-//          terms of each thread's output elements are loaded.
+// Phase 0  the image is copied into LDS (one coalesced read).
 // Phase 1  the tile's contraction chunks (all matrix-core segments, in
-//          order) are dealt round-robin to the waves; each wave loads its
-//          next chunk while the current one runs on the matrix cores.
+//          order) are dealt round-robin to the waves.  A chunk's operands
+//          are loaded raw into registers two chunks ahead and converted,
+//          scaled and masked only when the chunk goes to the matrix cores,
+//          so no load is waited for at issue.  Out-of-range rows, columns
+//          and contraction indices load from clamped in-range addresses and
+//          are zeroed at conversion.  The elementwise terms' psi entries are
+//          loaded together with the first chunks and summed in FP64.
 // Phase 2  the waves' 32x32 partial tiles are summed through LDS in wave
-//          order, the elementwise terms added in FP64, and y written.
+//          order (FP64), the elementwise terms added, and y written.
+//
+// Contraction index of element s of a lane's chunk registers: FP32 and
+// BF16 k = 8*(lane/32) + s, FP64 k = 4*(lane/16) + s (A and B agree, so the
+// order inside a chunk is immaterial).
 // ---------------------------------------------------------------------------
-constexpr int kMaxSeg = 32;   // segments per target block (checked by the host)
 constexpr int kMaxGG = 8;     // elementwise segments whose operands are loaded early
 
-struct TileShared {
-  int32_t gsrc[kMaxSeg][kTile];
-  float gscl[kMaxSeg][kTile];
-};
+__device__ inline int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Gather entry of index idx (row or column of the output block) for segment sg.
-__device__ inline void gather_entry(const SegDesc& sg, const TileDesc& t, int i,
-                                    const int32_t* gsrc, const double* gscale, int32_t& src,
-                                    float& scl) {
-  const bool kn = sg.kind == SEG_KN;
-  const int idx = (kn ? t.n0 : t.m0) + i;
-  const int limit = kn ? t.b : t.a;
-  const int32_t g = kn ? sg.gB : sg.gA;
-  src = -1;
-  scl = 0.f;
-  if (idx < limit) {
-    if (g < 0) {
-      src = idx;
-      scl = 1.f;
-    } else {
-      src = gsrc[g + idx];
-      scl = (float)gscale[g + idx];
-    }
-  }
+__device__ inline const ImgHeader& img_header(const uint32_t* img) {
+  return *reinterpret_cast<const ImgHeader*>(img);
+}
+__device__ inline const ImgSeg& img_seg(const uint32_t* img, int s) {
+  return *reinterpret_cast<const ImgSeg*>(img + kHdrWords + s * kSegWords);
+}
+__device__ inline const ImgGG& img_gg(const uint32_t* img, int ngemm, int q) {
+  return *reinterpret_cast<const ImgGG*>(img + kHdrWords + ngemm * kSegWords + q * kGGWords);
 }
 
+// Tile geometry, uniform over the workgroup.
+struct TileGeo {
+  int a, b, m0, n0;
+};
+
+// FP32 matrix cores, v_mfma_f32_32x32x2f32: A[i][k] from lane i + 32k,
+// B[k][j] from lane j + 32k; D[i][j] in lane j + 32*((i/4)%2), register
+// (i%4) + 4*(i/8).  One chunk is 8 instructions; element s of lane half h
+// carries k = 8h + s.
 struct F32Tile {
   using op_t = float;
   using red_t = float;
@@ -265,62 +267,68 @@ struct F32Tile {
   struct Acc {
     f32x16 d;
   };
-  struct Regs {
-    float a[8], b[8];
+  struct Raw {
+    float f[8];    // SEG_KN: A;  SEG_MK: B
+    double d[8];   // SEG_KN: B;  SEG_MK: A  (psi)
   };
   __device__ static void zero(Acc& a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) a.d[r] = 0.f;
   }
-  __device__ static void load(Regs& R, const SegDesc& sg, const TileDesc& t, int ch, int si,
-                              const TileShared& sh, const op_t* dense, const double* psi,
-                              int lane) {
-    const int i = lane & 31, kh = lane >> 5;
-    const double* P = psi + sg.psi_off;
-    const int64_t ldp = sg.psi_ld;
-    const int32_t src = sh.gsrc[si][i];
-    const float scl = sh.gscl[si][i];
-    if (sg.kind == SEG_KN) {
-      const op_t* At = dense + sg.op_off;
+  __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
+                              const op_t* dense, const double* psi, int lane) {
+    const int i = lane & 31, kb = ch * kChunk + 8 * (lane >> 5);
+    if (kind == SEG_KN) {
+      const op_t* At = dense + sg.op_off + min(g.m0 + i, g.a - 1);
       const int64_t lda = sg.op_ld;
-      const int m = t.m0 + i;
-      const bool mok = m < t.a;
-      const bool nok = src >= 0;
-      const float cs = (float)sg.c;
+      const double* P = psi + sg.psi_off + max(sg.src[i], 0);
+      const int64_t ldp = sg.psi_ld;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const int k = ch * kChunk + 2 * s + kh;
-        const bool kok = k < sg.K;
-        R.a[s] = (mok && kok) ? cs * At[k * lda + m] : 0.f;
-        R.b[s] = (nok && kok) ? scl * (float)P[k * ldp + src] : 0.f;
+        const int64_t k = min(kb + s, K - 1);
+        R.f[s] = At[k * lda];
+        R.d[s] = P[k * ldp];
       }
     } else {
-      const bool mok = src >= 0;
-      const double* Arow = P + (int64_t)(mok ? src : 0) * ldp;
-      const int n = t.n0 + i;
-      const bool nok = n < t.b;
-      const op_t* Brow = dense + sg.op_off + (int64_t)(nok ? n : 0) * sg.op_ld;
-      const float ca = (float)sg.c * scl;
-      const int k0 = ch * kChunk + 8 * kh;
-      if (k0 + 8 <= sg.K) {
+      const double* Arow = psi + sg.psi_off + (int64_t)max(sg.src[i], 0) * sg.psi_ld;
+      const op_t* Brow = dense + sg.op_off + (int64_t)min(g.n0 + i, g.b - 1) * sg.op_ld;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          R.a[s] = mok ? ca * (float)Arow[k0 + s] : 0.f;
-          R.b[s] = nok ? Brow[k0 + s] : 0.f;
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const bool kok = k0 + s < sg.K;
-          R.a[s] = (mok && kok) ? ca * (float)Arow[k0 + s] : 0.f;
-          R.b[s] = (nok && kok) ? Brow[k0 + s] : 0.f;
-        }
+      for (int s = 0; s < 8; ++s) {
+        const int k = min(kb + s, K - 1);
+        R.d[s] = Arow[k];
+        R.f[s] = Brow[k];
       }
     }
   }
-  __device__ static void mma(Acc& acc, const Regs& R) {
+  // operands of one chunk in FP32, scaled and masked
+  __device__ static void operands(const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
+                                  const TileGeo& g, int lane, float (&a)[8], float (&b)[8]) {
+    const int i = lane & 31, kv = K - ch * kChunk - 8 * (lane >> 5);
+    const int src = sg.src[i];
+    if (kind == SEG_KN) {
+      const float cA = g.m0 + i < g.a ? (float)sg.c : 0.f;
+      const float sB = src >= 0 ? (float)sg.scl[i] : 0.f;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc.d = __builtin_amdgcn_mfma_f32_32x32x2f32(R.a[s], R.b[s], acc.d, 0, 0, 0);
+      for (int s = 0; s < 8; ++s) {
+        a[s] = s < kv ? cA * R.f[s] : 0.f;
+        b[s] = s < kv ? sB * (float)R.d[s] : 0.f;
+      }
+    } else {
+      const float cA = src >= 0 ? (float)(sg.c * sg.scl[i]) : 0.f;
+      const float sB = g.n0 + i < g.b ? 1.f : 0.f;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        a[s] = s < kv ? cA * (float)R.d[s] : 0.f;
+        b[s] = s < kv ? sB * R.f[s] : 0.f;
+      }
+    }
+  }
+  __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
+                             const TileGeo& g, int lane) {
+    float a[8], b[8];
+    operands(R, sg, kind, K, ch, g, lane, a, b);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc.d = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc.d, 0, 0, 0);
   }
   static constexpr int kRegs = 16;
   __device__ static float value(const Acc& a, int r) { return a.d[r]; }
@@ -330,101 +338,22 @@ struct F32Tile {
   }
 };
 
-struct F64Tile {
-  using op_t = double;
-  using red_t = double;
-  static constexpr int kWaves = 8;
-  struct Acc {
-    f64x4 d[4];
-  };
-  struct Regs {
-    double a0[4], a1[4], b0[4], b1[4];
-  };
-  __device__ static void zero(Acc& a) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a.d[b][r] = 0.0;
-  }
-  __device__ static void load(Regs& R, const SegDesc& sg, const TileDesc& t, int ch, int si,
-                              const TileShared& sh, const op_t* dense, const double* psi,
-                              int lane) {
-    const int i = lane & 15, kq = lane >> 4;
-    const double* P = psi + sg.psi_off;
-    const int64_t ldp = sg.psi_ld;
-    const int32_t src0 = sh.gsrc[si][i], src1 = sh.gsrc[si][16 + i];
-    const double scl0 = sh.gscl[si][i], scl1 = sh.gscl[si][16 + i];
-    if (sg.kind == SEG_KN) {
-      const op_t* At = dense + sg.op_off;
-      const int64_t lda = sg.op_ld;
-      const int m0 = t.m0 + i, m1 = t.m0 + 16 + i;
-      const bool mok0 = m0 < t.a, mok1 = m1 < t.a;
-      const double c = sg.c;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = ch * kChunk + 4 * s + kq;
-        const bool kok = k < sg.K;
-        R.a0[s] = (mok0 && kok) ? c * At[k * lda + m0] : 0.0;
-        R.a1[s] = (mok1 && kok) ? c * At[k * lda + m1] : 0.0;
-        R.b0[s] = (src0 >= 0 && kok) ? scl0 * P[k * ldp + src0] : 0.0;
-        R.b1[s] = (src1 >= 0 && kok) ? scl1 * P[k * ldp + src1] : 0.0;
-      }
-    } else {
-      const double* A0 = P + (int64_t)(src0 >= 0 ? src0 : 0) * ldp;
-      const double* A1 = P + (int64_t)(src1 >= 0 ? src1 : 0) * ldp;
-      const int n0 = t.n0 + i, n1 = t.n0 + 16 + i;
-      const bool nok0 = n0 < t.b, nok1 = n1 < t.b;
-      const op_t* B0 = dense + sg.op_off + (int64_t)(nok0 ? n0 : 0) * sg.op_ld;
-      const op_t* B1 = dense + sg.op_off + (int64_t)(nok1 ? n1 : 0) * sg.op_ld;
-      const double c0 = sg.c * scl0, c1 = sg.c * scl1;
-      const int k0 = ch * kChunk + 4 * kq;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const bool kok = k0 + s < sg.K;
-        R.a0[s] = (src0 >= 0 && kok) ? c0 * A0[k0 + s] : 0.0;
-        R.a1[s] = (src1 >= 0 && kok) ? c1 * A1[k0 + s] : 0.0;
-        R.b0[s] = (nok0 && kok) ? B0[k0 + s] : 0.0;
-        R.b1[s] = (nok1 && kok) ? B1[k0 + s] : 0.0;
-      }
-    }
-  }
-  __device__ static void mma(Acc& acc, const Regs& R) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      acc.d[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a0[s], R.b0[s], acc.d[0], 0, 0, 0);
-      acc.d[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a0[s], R.b1[s], acc.d[1], 0, 0, 0);
-      acc.d[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a1[s], R.b0[s], acc.d[2], 0, 0, 0);
-      acc.d[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(R.a1[s], R.b1[s], acc.d[3], 0, 0, 0);
-    }
-  }
-  static constexpr int kRegs = 16;
-  __device__ static double value(const Acc& a, int r) { return a.d[r >> 2][r & 3]; }
-  __device__ static void coords(int lane, int r, int& row, int& col) {
-    const int b = r >> 2, bi = b >> 1, bj = b & 1;
-    row = 16 * bi + 4 * (r & 3) + (lane >> 4);
-    col = 16 * bj + (lane & 15);
-  }
-};
-
 // BF16 hi/lo split on the matrix cores: v_mfma_f32_32x32x16_bf16, A[i][k]
 // from lane i + 32*(k/8), element k%8 (B likewise with column j); D as in the
 // FP32 32x32 layout.  Every FP32 operand x is split into hi = bf16(x) and
 // lo = bf16(x - hi); a product is hi*hi + hi*lo + lo*hi (the lo*lo term and
 // the rounding of lo leave a relative error of about 2^-16), accumulated in
-// FP32.  The operators are read from the FP32 pool and split on load.
+// FP32.  Raw loads and masking are those of the FP32 tile.
 struct BF16Tile {
   using op_t = float;
   using red_t = float;
   static constexpr int kWaves = 16;
-  struct Acc {
-    f32x16 d;
-  };
-  struct Regs {
-    bf16x8 ah, al, bh, bl;
-  };
-  __device__ static void zero(Acc& a) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) a.d[r] = 0.f;
+  using Acc = F32Tile::Acc;
+  using Raw = F32Tile::Raw;
+  __device__ static void zero(Acc& a) { F32Tile::zero(a); }
+  __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
+                              const op_t* dense, const double* psi, int lane) {
+    F32Tile::load(R, sg, kind, K, ch, g, dense, psi, lane);
   }
   __device__ static void split(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
 #pragma unroll
@@ -434,130 +363,207 @@ struct BF16Tile {
       lo[j] = (__bf16)(x[j] - (float)h);
     }
   }
-  __device__ static void load(Regs& R, const SegDesc& sg, const TileDesc& t, int ch, int si,
-                              const TileShared& sh, const op_t* dense, const double* psi,
-                              int lane) {
-    const int i = lane & 31, kh = lane >> 5;
-    const double* P = psi + sg.psi_off;
-    const int64_t ldp = sg.psi_ld;
-    const int32_t src = sh.gsrc[si][i];
-    const float scl = sh.gscl[si][i];
-    const int k0 = ch * kChunk + 8 * kh;
+  __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
+                             const TileGeo& g, int lane) {
     float a[8], b[8];
-    if (sg.kind == SEG_KN) {
-      const op_t* At = dense + sg.op_off;
-      const int64_t lda = sg.op_ld;
-      const int m = t.m0 + i;
-      const bool mok = m < t.a;
-      const bool nok = src >= 0;
-      const float cs = (float)sg.c;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + j;
-        const bool kok = k < sg.K;
-        a[j] = (mok && kok) ? cs * At[k * lda + m] : 0.f;
-        b[j] = (nok && kok) ? scl * (float)P[k * ldp + src] : 0.f;
-      }
-    } else {
-      const bool mok = src >= 0;
-      const double* Arow = P + (int64_t)(mok ? src : 0) * ldp;
-      const int n = t.n0 + i;
-      const bool nok = n < t.b;
-      const op_t* Brow = dense + sg.op_off + (int64_t)(nok ? n : 0) * sg.op_ld;
-      const float ca = (float)sg.c * scl;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const bool kok = k0 + j < sg.K;
-        a[j] = (mok && kok) ? ca * (float)Arow[k0 + j] : 0.f;
-        b[j] = (nok && kok) ? Brow[k0 + j] : 0.f;
-      }
-    }
-    split(a, R.ah, R.al);
-    split(b, R.bh, R.bl);
-  }
-  __device__ static void mma(Acc& acc, const Regs& R) {
-    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.ah, R.bh, acc.d, 0, 0, 0);
-    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.ah, R.bl, acc.d, 0, 0, 0);
-    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(R.al, R.bh, acc.d, 0, 0, 0);
+    F32Tile::operands(R, sg, kind, K, ch, g, lane, a, b);
+    bf16x8 ah, al, bh, bl;
+    split(a, ah, al);
+    split(b, bh, bl);
+    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc.d, 0, 0, 0);
+    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc.d, 0, 0, 0);
+    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc.d, 0, 0, 0);
   }
   static constexpr int kRegs = 16;
   __device__ static float value(const Acc& a, int r) { return a.d[r]; }
+  __device__ static void coords(int lane, int r, int& row, int& col) { F32Tile::coords(lane, r, row, col); }
+};
+
+// FP64 matrix cores, v_mfma_f64_16x16x4f64 on the four 16x16 quarters of the
+// tile: A[i][k] from lane i + 16k, B[k][j] from lane j + 16k; D row
+// 4*reg + lane/16, column lane%16.  Element s of lane group q = lane/16
+// carries k = 4q + s.
+struct F64Tile {
+  using op_t = double;
+  using red_t = double;
+  static constexpr int kWaves = 8;
+  struct Acc {
+    f64x4 d[4];
+  };
+  struct Raw {
+    double a0[4], a1[4], b0[4], b1[4];
+  };
+  __device__ static void zero(Acc& a) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a.d[q][r] = 0.0;
+  }
+  __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
+                              const op_t* dense, const double* psi, int lane) {
+    const int i = lane & 15, kb = ch * kChunk + 4 * (lane >> 4);
+    if (kind == SEG_KN) {
+      const op_t* A0 = dense + sg.op_off + min(g.m0 + i, g.a - 1);
+      const op_t* A1 = dense + sg.op_off + min(g.m0 + 16 + i, g.a - 1);
+      const int64_t lda = sg.op_ld;
+      const double* P0 = psi + sg.psi_off + max(sg.src[i], 0);
+      const double* P1 = psi + sg.psi_off + max(sg.src[16 + i], 0);
+      const int64_t ldp = sg.psi_ld;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t k = min(kb + s, K - 1);
+        R.a0[s] = A0[k * lda];
+        R.a1[s] = A1[k * lda];
+        R.b0[s] = P0[k * ldp];
+        R.b1[s] = P1[k * ldp];
+      }
+    } else {
+      const double* A0 = psi + sg.psi_off + (int64_t)max(sg.src[i], 0) * sg.psi_ld;
+      const double* A1 = psi + sg.psi_off + (int64_t)max(sg.src[16 + i], 0) * sg.psi_ld;
+      const op_t* B0 = dense + sg.op_off + (int64_t)min(g.n0 + i, g.b - 1) * sg.op_ld;
+      const op_t* B1 = dense + sg.op_off + (int64_t)min(g.n0 + 16 + i, g.b - 1) * sg.op_ld;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = min(kb + s, K - 1);
+        R.a0[s] = A0[k];
+        R.a1[s] = A1[k];
+        R.b0[s] = B0[k];
+        R.b1[s] = B1[k];
+      }
+    }
+  }
+  __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
+                             const TileGeo& g, int lane) {
+    const int i = lane & 15, kv = K - ch * kChunk - 4 * (lane >> 4);
+    const int src0 = sg.src[i], src1 = sg.src[16 + i];
+    double cA0, cA1, sB0, sB1;
+    if (kind == SEG_KN) {
+      cA0 = g.m0 + i < g.a ? sg.c : 0.0;
+      cA1 = g.m0 + 16 + i < g.a ? sg.c : 0.0;
+      sB0 = src0 >= 0 ? sg.scl[i] : 0.0;
+      sB1 = src1 >= 0 ? sg.scl[16 + i] : 0.0;
+    } else {
+      cA0 = src0 >= 0 ? sg.c * sg.scl[i] : 0.0;
+      cA1 = src1 >= 0 ? sg.c * sg.scl[16 + i] : 0.0;
+      sB0 = g.n0 + i < g.b ? 1.0 : 0.0;
+      sB1 = g.n0 + 16 + i < g.b ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool v = s < kv;
+      const double a0 = v ? cA0 * R.a0[s] : 0.0, a1 = v ? cA1 * R.a1[s] : 0.0;
+      const double b0 = v ? sB0 * R.b0[s] : 0.0, b1 = v ? sB1 * R.b1[s] : 0.0;
+      acc.d[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.d[0], 0, 0, 0);
+      acc.d[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.d[1], 0, 0, 0);
+      acc.d[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.d[2], 0, 0, 0);
+      acc.d[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.d[3], 0, 0, 0);
+    }
+  }
+  static constexpr int kRegs = 16;
+  __device__ static double value(const Acc& a, int r) { return a.d[r >> 2][r & 3]; }
   __device__ static void coords(int lane, int r, int& row, int& col) {
-    row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    col = lane & 31;
+    const int q = r >> 2, qi = q >> 1, qj = q & 1;
+    row = 16 * qi + 4 * (r & 3) + (lane >> 4);
+    col = 16 * qj + (lane & 15);
   }
 };
 
-// Matrix-core segment holding global chunk g of the tile.
-__device__ inline int seg_of_chunk(const SegDesc* segs, const TileDesc& t, int g) {
-  int found = 0;
-  for (int s = 1; s < t.ngemm; ++s)
-    if (g >= segs[t.seg0 + s].ch0) found = s;
-  return found;
+// Elementwise term q at local element (mi, nj): c * rs * cs * psi[row + col].
+__device__ inline double img_gg_term(const ImgGG& G, int mi, int nj, const double* psi) {
+  const int64_t row = G.row[mi];
+  const int32_t col = G.col[nj];
+  if (row < 0 || col < 0) return 0.0;
+  return G.c * G.rs[mi] * G.cs[nj] * psi[row + col];
 }
 
 template <class Cfg>
-__global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_grouped(
-    const int32_t* __restrict__ order, const TileDesc* __restrict__ tiles,
-    const SegDesc* __restrict__ segs, const typename Cfg::op_t* __restrict__ dense,
-    const int32_t* __restrict__ gsrc, const double* __restrict__ gscale,
-    const double* __restrict__ psi, double* __restrict__ y, double alpha, double beta) {
+__global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
+    const uint32_t* __restrict__ images, int32_t stride,
+    const typename Cfg::op_t* __restrict__ dense, const double* __restrict__ psi,
+    double* __restrict__ y, double alpha, double beta) {
   constexpr int kW = Cfg::kWaves;
   constexpr int kT = kW * 64;
   constexpr int kPer = kTile * kTile / kT;   // output elements per thread
-  __shared__ TileShared sh;
+  __shared__ __align__(16) uint32_t img[kImgWords];
   __shared__ typename Cfg::red_t red[kW][kTile * kTile];
-  const int ti = order ? order[blockIdx.x] : (int)blockIdx.x;
-  if (ti < 0) return;
-  const TileDesc t = tiles[ti];
-  // the wave index is uniform in a wave: say so, so that chunk and segment
-  // bookkeeping stays in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
 
-  // phase 0: gather entries of the matrix-core segments; elementwise operands
-  for (int x = threadIdx.x; x < t.ngemm * kTile; x += kT) {
-    const int s = x / kTile, i = x % kTile;
-    gather_entry(segs[t.seg0 + s], t, i, gsrc, gscale, sh.gsrc[s][i], sh.gscl[s][i]);
-  }
-  const int ngg = t.nseg - t.ngemm;
-  double gg[kPer];
-#pragma unroll
-  for (int e = 0; e < kPer; ++e) {
-    const int el = threadIdx.x + e * kT;
-    const int m = t.m0 + el / kTile, n = t.n0 + el % kTile;
-    double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < kMaxGG; ++q)
-      if (q < ngg) v += gg_term(segs[t.seg0 + t.ngemm + q], t, m, n, gsrc, gscale, psi);
-    gg[e] = v;
+  // phase 0: the slot's image into LDS
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(images + (int64_t)blockIdx.x * stride);
+    uint4* dst = reinterpret_cast<uint4*>(img);
+    for (int x = threadIdx.x; x < stride / 4; x += kT) dst[x] = src[x];
   }
   __syncthreads();
+  const ImgHeader& H = img_header(img);
+  TileGeo g;
+  g.a = rfl(H.a);
+  if (g.a == 0) return;   // idle slot
+  g.b = rfl(H.b);
+  g.m0 = rfl(H.m0);
+  g.n0 = rfl(H.n0);
+  const int ngemm = rfl(H.ngemm), ngg = rfl(H.ngg), nchunk = rfl(H.nchunk);
+  // the wave index is uniform in a wave: say so, so that chunk and segment
+  // bookkeeping stays in scalar registers
+  const int wave = rfl(threadIdx.x >> 6), lane = threadIdx.x & 63;
 
-  // phase 1: contraction chunks, round-robin over the waves, one chunk ahead
+  // phase 1
   typename Cfg::Acc acc;
   Cfg::zero(acc);
-  const int nw = t.nchunk < kW ? t.nchunk : kW;   // waves that get work
-  if (wave < t.nchunk) {
-    // two register buffers, used alternately: load chunk g + kW while chunk g
-    // is on the matrix cores
-    typename Cfg::Regs ra, rb;
-    auto fetch = [&](typename Cfg::Regs& R, int g) {
-      const int si = seg_of_chunk(segs, t, g);
-      const SegDesc sg = segs[t.seg0 + si];
-      Cfg::load(R, sg, t, g - sg.ch0, si, sh, dense, psi, lane);
+  double ggv[kPer];
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) ggv[e] = 0.0;
+  auto add_gg = [&]() {
+    double t[kPer][kMaxGG];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int el = threadIdx.x + e * kT;
+#pragma unroll
+      for (int q = 0; q < kMaxGG; ++q)
+        t[e][q] = q < ngg ? img_gg_term(img_gg(img, ngemm, q), el / kTile, el % kTile, psi) : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < kPer; ++e)
+#pragma unroll
+      for (int q = 0; q < kMaxGG; ++q) ggv[e] += t[e][q];
+  };
+  if (wave < nchunk) {
+    typename Cfg::Raw ra, rb;
+    int si = 0;   // segment of the latest chunk handed out (chunks come in increasing order)
+    auto seg_for = [&](int gc) {
+      while (si + 1 < ngemm && gc >= rfl(img_seg(img, si + 1).ch0)) ++si;
+      return si;
     };
-    int g = wave;
-    fetch(ra, g);
+    auto fetch = [&](typename Cfg::Raw& R, int gc, int s) {
+      const ImgSeg& sg = img_seg(img, s);
+      Cfg::load(R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, dense, psi, lane);
+    };
+    auto run = [&](const typename Cfg::Raw& R, int gc, int s) {
+      const ImgSeg& sg = img_seg(img, s);
+      Cfg::mma(acc, R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, lane);
+    };
+    int gA = wave, sA = seg_for(gA);
+    fetch(ra, gA, sA);
+    int gB = gA + kW, sB = 0;
+    if (gB < nchunk) {
+      sB = seg_for(gB);
+      fetch(rb, gB, sB);
+    }
+    add_gg();   // its loads went out with the first chunks'
     for (;;) {
-      const int g2 = g + kW;
-      if (g2 < t.nchunk) fetch(rb, g2);
-      Cfg::mma(acc, ra);
-      if (g2 >= t.nchunk) break;
-      const int g3 = g2 + kW;
-      if (g3 < t.nchunk) fetch(ra, g3);
-      Cfg::mma(acc, rb);
-      if (g3 >= t.nchunk) break;
-      g = g3;
+      run(ra, gA, sA);
+      if (gB >= nchunk) break;
+      gA = gB + kW;
+      if (gA < nchunk) {
+        sA = seg_for(gA);
+        fetch(ra, gA, sA);
+      }
+      run(rb, gB, sB);
+      if (gA >= nchunk) break;
+      gB = gA + kW;
+      if (gB < nchunk) {
+        sB = seg_for(gB);
+        fetch(rb, gB, sB);
+      }
     }
 #pragma unroll
     for (int r = 0; r < Cfg::kRegs; ++r) {
@@ -565,20 +571,26 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_grouped(
       Cfg::coords(lane, r, row, col);
       red[wave][row * kTile + col] = Cfg::value(acc, r);
     }
+  } else {
+    add_gg();
   }
   __syncthreads();
 
   // phase 2: fixed-order sum, elementwise terms, y
+  const int nw = nchunk < kW ? nchunk : kW;   // waves that wrote a partial tile
+  const int ldy = rfl(H.ldy);
+  const int64_t y_off = H.y_off;
 #pragma unroll
   for (int e = 0; e < kPer; ++e) {
     const int el = threadIdx.x + e * kT;
-    const int m = t.m0 + el / kTile, n = t.n0 + el % kTile;
+    const int mi = el / kTile, nj = el % kTile;
     double v = 0.0;
     for (int w = 0; w < nw; ++w) v += (double)red[w][el];
-    v += gg[e];
-    for (int q = kMaxGG; q < ngg; ++q) v += gg_term(segs[t.seg0 + t.ngemm + q], t, m, n, gsrc, gscale, psi);
-    if (m < t.a && n < t.b) {
-      const int64_t idx = t.y_off + (int64_t)m * t.ldy + n;
+    v += ggv[e];
+    for (int q = kMaxGG; q < ngg; ++q) v += img_gg_term(img_gg(img, ngemm, q), mi, nj, psi);
+    const int m = g.m0 + mi, n = g.n0 + nj;
+    if (m < g.a && n < g.b) {
+      const int64_t idx = y_off + (int64_t)m * ldy + n;
       y[idx] = beta == 0.0 ? alpha * v : alpha * v + beta * y[idx];
     }
   }
@@ -692,21 +704,19 @@ __global__ __launch_bounds__(256) void plain_segment(SegDesc sg, TileDesc t,
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_hpsi(int prec, int nslots, const int32_t* order, const TileDesc* tiles,
-                       const SegDesc* segs, const void* dense, const int32_t* gsrc,
-                       const double* gscale, const double* psi, double* y, double alpha,
-                       double beta, hipStream_t stream) {
+hipError_t launch_hpsi(int prec, int nslots, const uint32_t* images, int32_t stride,
+                       const void* dense, const double* psi, double* y, double alpha, double beta,
+                       hipStream_t stream) {
   if (nslots <= 0) return hipSuccess;
   if (prec == kPrecF32) {
-    hipLaunchKernelGGL(hpsi_grouped<F32Tile>, dim3(nslots), dim3(F32Tile::kWaves * 64), 0, stream,
-                       order, tiles, segs, (const float*)dense, gsrc, gscale, psi, y, alpha, beta);
+    hipLaunchKernelGGL(hpsi_tiles<F32Tile>, dim3(nslots), dim3(F32Tile::kWaves * 64), 0, stream,
+                       images, stride, (const float*)dense, psi, y, alpha, beta);
   } else if (prec == kPrecBF16X3) {
-    hipLaunchKernelGGL(hpsi_grouped<BF16Tile>, dim3(nslots), dim3(BF16Tile::kWaves * 64), 0,
-                       stream, order, tiles, segs, (const float*)dense, gsrc, gscale, psi, y, alpha,
-                       beta);
+    hipLaunchKernelGGL(hpsi_tiles<BF16Tile>, dim3(nslots), dim3(BF16Tile::kWaves * 64), 0, stream,
+                       images, stride, (const float*)dense, psi, y, alpha, beta);
   } else {
-    hipLaunchKernelGGL(hpsi_grouped<F64Tile>, dim3(nslots), dim3(F64Tile::kWaves * 64), 0, stream,
-                       order, tiles, segs, (const double*)dense, gsrc, gscale, psi, y, alpha, beta);
+    hipLaunchKernelGGL(hpsi_tiles<F64Tile>, dim3(nslots), dim3(F64Tile::kWaves * 64), 0, stream,
+                       images, stride, (const double*)dense, psi, y, alpha, beta);
   }
   return hipGetLastError();
 }

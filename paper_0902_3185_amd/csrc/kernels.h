@@ -15,15 +15,13 @@ constexpr int kPrecF32 = 1;
 constexpr int kPrecBF16X3 = 2;
 constexpr int kMaxSegPerBlock = 32;
 
-// y = alpha * H psi + beta * y with the grouped kernel; `dense` holds the
-// operator pool in the kernel's precision (double for F64, float for F32,
-// interleaved bf16 hi/lo pairs for BF16X3).
-// nslots workgroups; slot b takes tile order[b] (-1: idle); order == nullptr
-// means slot b takes tile b.  Every target block may have at most 32 segments.
-hipError_t launch_hpsi(int prec, int nslots, const int32_t* order, const TileDesc* tiles,
-                       const SegDesc* segs, const void* dense, const int32_t* gsrc,
-                       const double* gscale, const double* psi, double* y, double alpha,
-                       double beta, hipStream_t stream);
+// y = alpha * H psi + beta * y with the fused kernel: nslots workgroups, slot
+// b working from the tile image at images + b * stride (words; see
+// build_images).  `dense` holds the operator pool in the kernel's precision
+// (double for F64, float for F32 and BF16X3).
+hipError_t launch_hpsi(int prec, int nslots, const uint32_t* images, int32_t stride,
+                       const void* dense, const double* psi, double* y, double alpha, double beta,
+                       hipStream_t stream);
 
 // partial[tile * stride + s] = < G tile, segment s of the tile with c = 1 >
 hipError_t launch_term_dots(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 #include <sstream>
 
@@ -380,6 +381,97 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
   }
   plan.bytes_dense = 8.0 * plan.dense.size();
   return DMRG_OK;
+}
+
+bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>& segs,
+                  const std::vector<int32_t>& order, const std::vector<int32_t>& gsrc,
+                  const std::vector<double>& gscale, std::vector<uint32_t>& out,
+                  int32_t& stride, std::string& err) {
+  const size_t nslots = order.empty() ? tiles.size() : order.size();
+  auto tile_of = [&](size_t slot) { return order.empty() ? (int32_t)slot : order[slot]; };
+  // gather entry of output index idx (< limit) through pool offset g (-1: identity)
+  auto gather = [&](int32_t g, int32_t idx, int32_t limit, int32_t& src, double& scl) {
+    src = -1;
+    scl = 0.0;
+    if (idx >= limit) return;
+    if (g < 0) {
+      src = idx;
+      scl = 1.0;
+    } else {
+      src = gsrc[g + idx];
+      scl = src >= 0 ? gscale[g + idx] : 0.0;
+    }
+  };
+  int32_t words = kHdrWords;
+  for (size_t slot = 0; slot < nslots; ++slot) {
+    const int32_t ti = tile_of(slot);
+    if (ti < 0) continue;
+    const TileDesc& t = tiles[ti];
+    words = std::max(words, kHdrWords + t.ngemm * kSegWords + (t.nseg - t.ngemm) * kGGWords);
+  }
+  if (words > kImgWords) {
+    std::ostringstream os;
+    os << "a target block's terms need a " << 4 * words << "-byte tile image; the fused kernel holds "
+       << 4 * kImgWords;
+    err = os.str();
+    return false;
+  }
+  stride = (words + 3) / 4 * 4;
+  out.assign(nslots * (size_t)stride, 0u);
+  for (size_t slot = 0; slot < nslots; ++slot) {
+    const int32_t ti = tile_of(slot);
+    uint32_t* img = out.data() + slot * (size_t)stride;
+    ImgHeader h{};
+    if (ti >= 0) {
+      const TileDesc& t = tiles[ti];
+      h.y_off = t.y_off;
+      h.a = t.a;
+      h.b = t.b;
+      h.m0 = t.m0;
+      h.n0 = t.n0;
+      h.ldy = t.ldy;
+      h.ngemm = t.ngemm;
+      h.ngg = t.nseg - t.ngemm;
+      h.nchunk = t.nchunk;
+      for (int32_t s = 0; s < t.ngemm; ++s) {
+        const SegDesc& sg = segs[t.seg0 + s];
+        ImgSeg r{};
+        r.kind = sg.kind;
+        r.K = sg.K;
+        r.psi_ld = sg.psi_ld;
+        r.op_ld = sg.op_ld;
+        r.psi_off = sg.psi_off;
+        r.op_off = sg.op_off;
+        r.c = sg.c;
+        r.ch0 = sg.ch0;
+        for (int32_t i = 0; i < kTile; ++i) {
+          if (sg.kind == SEG_KN)
+            gather(sg.gB, t.n0 + i, t.b, r.src[i], r.scl[i]);
+          else
+            gather(sg.gA, t.m0 + i, t.a, r.src[i], r.scl[i]);
+        }
+        std::memcpy(img + kHdrWords + s * kSegWords, &r, sizeof(r));
+      }
+      for (int32_t q = 0; q < t.nseg - t.ngemm; ++q) {
+        const SegDesc& sg = segs[t.seg0 + t.ngemm + q];
+        ImgGG r{};
+        r.c = sg.c;
+        for (int32_t i = 0; i < kTile; ++i) {
+          int32_t src;
+          double scl;
+          gather(sg.gA, t.m0 + i, t.a, src, scl);
+          r.row[i] = src >= 0 ? sg.psi_off + (int64_t)src * sg.psi_ld : -1;
+          r.rs[i] = scl;
+          gather(sg.gB, t.n0 + i, t.b, src, scl);
+          r.col[i] = src;
+          r.cs[i] = scl;
+        }
+        std::memcpy(img + kHdrWords + t.ngemm * kSegWords + q * kGGWords, &r, sizeof(r));
+      }
+    }
+    std::memcpy(img, &h, sizeof(h));
+  }
+  return true;
 }
 
 double plan_bytes_alg(const Plan& p, int elem_bytes) {

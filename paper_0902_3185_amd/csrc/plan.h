@@ -57,6 +57,50 @@ constexpr int kXcds = 8;     // MI355X: 8 XCDs; workgroup b runs on XCD b % 8
 constexpr int kTile = 32;    // output tile edge
 constexpr int kChunk = 16;   // contraction chunk
 
+// ---------------------------------------------------------------------------
+// Tile images: for every workgroup slot of the fused product, one contiguous
+// record of everything its 32 x 32 output tile needs, so that the workgroup
+// fetches it into LDS with a single coalesced read and no later lookup
+// depends on another load.  Layout (32-bit words, 8-byte aligned records):
+//   ImgHeader, then ngemm ImgSeg (matrix-core segments, in chunk order),
+//   then ngg ImgGG (elementwise segments).  An image with a == 0 is an idle
+//   slot.
+// ---------------------------------------------------------------------------
+struct ImgHeader {
+  int64_t y_off;
+  int32_t a, b, m0, n0, ldy;
+  int32_t ngemm, ngg, nchunk;
+  int32_t pad[6];
+};
+struct ImgSeg {
+  int32_t kind, K, psi_ld, op_ld;
+  int64_t psi_off, op_off;
+  double c;
+  int32_t ch0, pad;
+  int32_t src[kTile];   // gathered side (SEG_KN: columns, SEG_MK: rows): source index, -1 = zero
+  double scl[kTile];    // and its scale
+};
+struct ImgGG {
+  double c;
+  int64_t row[kTile];   // psi_off + srcA(m0 + i) * psi_ld, -1 = zero row
+  int32_t col[kTile];   // srcB(n0 + j), -1 = zero column
+  double rs[kTile], cs[kTile];
+};
+constexpr int kHdrWords = (int)(sizeof(ImgHeader) / 4);
+constexpr int kSegWords = (int)(sizeof(ImgSeg) / 4);
+constexpr int kGGWords = (int)(sizeof(ImgGG) / 4);
+constexpr int kImgWords = 6144;   // LDS room for one image (24 KiB)
+static_assert(sizeof(ImgHeader) == 64 && sizeof(ImgSeg) % 8 == 0 && sizeof(ImgGG) % 8 == 0,
+              "image records must keep 8-byte alignment");
+
+// Images of the given tiles in launch order (order[slot] = tile, -1 idle; an
+// empty order means slot = tile).  stride (words, a multiple of 4) is the
+// largest image.  Returns false with err set if an image exceeds kImgWords.
+bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>& segs,
+                  const std::vector<int32_t>& order, const std::vector<int32_t>& gsrc,
+                  const std::vector<double>& gscale, std::vector<uint32_t>& out,
+                  int32_t& stride, std::string& err);
+
 struct Plan {
   // bases
   std::vector<int64_t> qS, qE;

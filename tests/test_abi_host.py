@@ -154,6 +154,27 @@ def test_host_sym_eigen_rank_deficient_density_matrices():
         assert np.allclose(A @ a, a * w[None, :], atol=1e-14 * n)
 
 
+def test_host_sym_eigen_columns_near_underflow():
+    """Householder columns whose entries sit near the underflow threshold (the
+    trailing rounding-level part of a rank-one density matrix decays there):
+    the reflector must be formed on the scaled column."""
+    rng = np.random.default_rng(11)
+    for n, k in ((40, 20), (87, 3), (130, 1)):
+        X = rng.standard_normal((k, k))
+        Y = rng.standard_normal((n - k, n - k))
+        A = np.zeros((n, n))
+        A[:k, :k] = 1e-3 * (X @ X.T)
+        A[k:, k:] = 1e-158 * (Y @ Y.T)
+        a = np.ascontiguousarray(A.copy())
+        w = np.zeros(n)
+        _lib.check(_lib.lib().dmrg_host_sym_eigen(n, a.ctypes.data_as(C.POINTER(C.c_double)),
+                                                  w.ctypes.data_as(C.POINTER(C.c_double))))
+        wr = np.linalg.eigvalsh(A)
+        assert np.all(np.isfinite(w)) and np.all(np.isfinite(a))
+        assert np.allclose(w, wr, atol=1e-14 * n * np.abs(wr).max())
+        assert np.allclose(a.T @ a, np.eye(n), atol=1e-12 * n)
+
+
 def test_host_tridiag_lowest():
     rng = np.random.default_rng(1)
     for n in (1, 2, 5, 40, 300):

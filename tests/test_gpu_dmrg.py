@@ -102,6 +102,6 @@ def test_ldos_matches_exact_diagonalisation(ctx, U, spin):
     omega = np.linspace(-4, 4, 81)
     eta = 0.1
     N = DR.ldos(ctx, Sp, Ep, DR.hubbard(U), L, desc["q_target"], r["psi"], site, spin, omega,
-                eta, nsteps=400)
+                eta, nsteps=800)
     ref, _, w, _ = OLD.hubbard_ldos_lehmann(L, M.chain_bonds(L), U, site, spin, omega, eta)
     assert np.max(np.abs(N - ref)) <= 1e-9 * np.max(ref)
