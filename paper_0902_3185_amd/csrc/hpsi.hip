@@ -17,6 +17,8 @@ namespace dmrg {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Per-precision contraction of one segment's chunks into a wave's 32x32 tile.
@@ -290,13 +292,35 @@ struct F32Tile {
         R.d[s] = P[k * ldp];
       }
     } else {
+      // each lane walks its own row along k: 16-byte loads keep the
+      // per-lane runs whole (rows are only element-aligned, which the
+      // memory system takes for vector loads)
       const double* Arow = psi + sg.psi_off + (int64_t)max(sg.src[i], 0) * sg.psi_ld;
       const op_t* Brow = dense + sg.op_off + (int64_t)min(g.n0 + i, g.b - 1) * sg.op_ld;
+      if (K - (ch + 1) * kChunk >= 0) {   // whole chunk in range (uniform)
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int k = min(kb + s, K - 1);
-        R.d[s] = Arow[k];
-        R.f[s] = Brow[k];
+        for (int s = 0; s < 8; s += 2) {
+          d2 t;
+          __builtin_memcpy(&t, Arow + kb + s, sizeof(t));
+          R.d[s] = t.x;
+          R.d[s + 1] = t.y;
+        }
+#pragma unroll
+        for (int s = 0; s < 8; s += 4) {
+          f4 t;
+          __builtin_memcpy(&t, Brow + kb + s, sizeof(t));
+          R.f[s] = t.x;
+          R.f[s + 1] = t.y;
+          R.f[s + 2] = t.z;
+          R.f[s + 3] = t.w;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = min(kb + s, K - 1);
+          R.d[s] = Arow[k];
+          R.f[s] = Brow[k];
+        }
       }
     }
   }
@@ -422,13 +446,32 @@ struct F64Tile {
       const double* A1 = psi + sg.psi_off + (int64_t)max(sg.src[16 + i], 0) * sg.psi_ld;
       const op_t* B0 = dense + sg.op_off + (int64_t)min(g.n0 + i, g.b - 1) * sg.op_ld;
       const op_t* B1 = dense + sg.op_off + (int64_t)min(g.n0 + 16 + i, g.b - 1) * sg.op_ld;
+      if (K - (ch + 1) * kChunk >= 0) {   // whole chunk in range (uniform): 16-byte row loads
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = min(kb + s, K - 1);
-        R.a0[s] = A0[k];
-        R.a1[s] = A1[k];
-        R.b0[s] = B0[k];
-        R.b1[s] = B1[k];
+        for (int s = 0; s < 4; s += 2) {
+          d2 t;
+          __builtin_memcpy(&t, A0 + kb + s, sizeof(t));
+          R.a0[s] = t.x;
+          R.a0[s + 1] = t.y;
+          __builtin_memcpy(&t, A1 + kb + s, sizeof(t));
+          R.a1[s] = t.x;
+          R.a1[s + 1] = t.y;
+          __builtin_memcpy(&t, B0 + kb + s, sizeof(t));
+          R.b0[s] = t.x;
+          R.b0[s + 1] = t.y;
+          __builtin_memcpy(&t, B1 + kb + s, sizeof(t));
+          R.b1[s] = t.x;
+          R.b1[s + 1] = t.y;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int k = min(kb + s, K - 1);
+          R.a0[s] = A0[k];
+          R.a1[s] = A1[k];
+          R.b0[s] = B0[k];
+          R.b1[s] = B1[k];
+        }
       }
     }
   }
@@ -468,12 +511,21 @@ struct F64Tile {
   }
 };
 
-// Elementwise term q at local element (mi, nj): c * rs * cs * psi[row + col].
-__device__ inline double img_gg_term(const ImgGG& G, int mi, int nj, const double* psi) {
+// Elementwise term at local element (mi, nj): c * rs * cs * psi[row + col].
+// A zero row or column has scale 0 in the image; its load is clamped to
+// psi[0] and dropped by that scale, so loads need no branch and the loads
+// of several terms go out together.
+__device__ inline double img_gg_load(const ImgGG& G, int mi, int nj, const double* psi) {
   const int64_t row = G.row[mi];
   const int32_t col = G.col[nj];
-  if (row < 0 || col < 0) return 0.0;
-  return G.c * G.rs[mi] * G.cs[nj] * psi[row + col];
+  return psi[(row < 0 ? 0 : row) + (col < 0 ? 0 : col)];
+}
+__device__ inline double img_gg_coef(const ImgGG& G, int mi, int nj) {
+  return G.c * G.rs[mi] * G.cs[nj];
+}
+__device__ inline double img_gg_term(const ImgGG& G, int mi, int nj, const double* psi) {
+  const double v = img_gg_load(G, mi, nj, psi);
+  return img_gg_coef(G, mi, nj) * v;
 }
 
 template <class Cfg>
@@ -512,19 +564,28 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
   double ggv[kPer];
 #pragma unroll
   for (int e = 0; e < kPer; ++e) ggv[e] = 0.0;
-  auto add_gg = [&]() {
-    double t[kPer][kMaxGG];
+  // elementwise terms: their loads go out before the first chunks' (terms
+  // beyond ngg re-read term 0's), the FP64 sum in term order comes after
+  double ggt[kPer][kMaxGG];
+  auto gg_issue = [&]() {
+    if (ngg == 0) return;
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int el = threadIdx.x + e * kT;
 #pragma unroll
       for (int q = 0; q < kMaxGG; ++q)
-        t[e][q] = q < ngg ? img_gg_term(img_gg(img, ngemm, q), el / kTile, el % kTile, psi) : 0.0;
+        ggt[e][q] = img_gg_load(img_gg(img, ngemm, q < ngg ? q : 0), el / kTile, el % kTile, psi);
     }
+  };
+  auto gg_sum = [&]() {
+    if (ngg == 0) return;
 #pragma unroll
-    for (int e = 0; e < kPer; ++e)
+    for (int e = 0; e < kPer; ++e) {
+      const int el = threadIdx.x + e * kT;
 #pragma unroll
-      for (int q = 0; q < kMaxGG; ++q) ggv[e] += t[e][q];
+      for (int q = 0; q < kMaxGG; ++q)
+        if (q < ngg) ggv[e] += img_gg_coef(img_gg(img, ngemm, q), el / kTile, el % kTile) * ggt[e][q];
+    }
   };
   if (wave < nchunk) {
     typename Cfg::Raw ra, rb;
@@ -542,13 +603,17 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
       Cfg::mma(acc, R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, lane);
     };
     int gA = wave, sA = seg_for(gA);
+    gg_issue();
     fetch(ra, gA, sA);
     int gB = gA + kW, sB = 0;
     if (gB < nchunk) {
       sB = seg_for(gB);
       fetch(rb, gB, sB);
     }
-    add_gg();   // its loads went out with the first chunks'
+    // keep the scheduler from hoisting the sum (and its wait) above the
+    // second chunk's loads
+    __builtin_amdgcn_sched_barrier(0);
+    gg_sum();
     for (;;) {
       run(ra, gA, sA);
       if (gB >= nchunk) break;
@@ -572,7 +637,8 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
       red[wave][row * kTile + col] = Cfg::value(acc, r);
     }
   } else {
-    add_gg();
+    gg_issue();
+    gg_sum();
   }
   __syncthreads();
 

@@ -302,7 +302,7 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
   }
 
   // tiles; each block's segments know where their chunks start
-  std::vector<int64_t> pair_cost(npairs, 0), tile_cost;
+  std::vector<int64_t> tile_cost;
   std::vector<int32_t> tile_pair;
   for (int32_t p = 0; p < npairs; ++p) {
     const int32_t a = plan.dS[plan.pair_s[p]], b = plan.dE[plan.pair_e[p]];
@@ -344,35 +344,35 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
         plan.tiles.push_back(t);
         tile_cost.push_back(tcost);
         tile_pair.push_back(p);
-        pair_cost[p] += tcost;
         plan.flops_exec += 2.0 * kTile * kTile * (double)kpad;
         plan.gemm_elems += kpad;
       }
   }
-  // XCD-aware order: whole blocks go to one XCD (its L2 then holds the
-  // block's operators and psi), blocks spread over the XCDs by LPT on their
-  // cost, and inside an XCD tiles run most expensive first.  Slot b of the
-  // launch runs on XCD b % kXcds and takes the (b / kXcds)-th tile of it.
+  // XCD-aware order.  Tiles go to the XCDs by LPT on their cost (most
+  // expensive first, each to the least loaded XCD), so that every XCD ends
+  // at about the same time even when a few large blocks hold most of the
+  // work; ties go to the XCD that already holds tiles of the same block, so
+  // that a block's operators and psi rows tend to stay in one L2.  Slot b of
+  // the launch runs on XCD b % kXcds and takes the (b / kXcds)-th tile of
+  // that XCD's list, most expensive first.
   {
-    std::vector<int32_t> pidx(npairs);
-    for (int32_t p = 0; p < npairs; ++p) pidx[p] = p;
-    std::stable_sort(pidx.begin(), pidx.end(),
-                     [&](int32_t x, int32_t y) { return pair_cost[x] > pair_cost[y]; });
-    std::vector<int64_t> load(kXcds, 0);
-    std::vector<int32_t> xcd_of(npairs, 0);
-    for (int32_t p : pidx) {
-      int best = 0;
-      for (int x = 1; x < kXcds; ++x)
-        if (load[x] < load[best]) best = x;
-      xcd_of[p] = best;
-      load[best] += pair_cost[p];
-    }
-    std::vector<std::vector<int32_t>> lists(kXcds);
     std::vector<int32_t> tidx(plan.tiles.size());
     for (size_t t = 0; t < tidx.size(); ++t) tidx[t] = (int32_t)t;
     std::stable_sort(tidx.begin(), tidx.end(),
                      [&](int32_t x, int32_t y) { return tile_cost[x] > tile_cost[y]; });
-    for (int32_t t : tidx) lists[xcd_of[tile_pair[t]]].push_back(t);
+    std::vector<int64_t> load(kXcds, 0);
+    std::vector<int32_t> last_xcd(npairs, -1);
+    std::vector<std::vector<int32_t>> lists(kXcds);
+    for (int32_t t : tidx) {
+      int best = 0;
+      for (int x = 1; x < kXcds; ++x)
+        if (load[x] < load[best]) best = x;
+      const int pref = last_xcd[tile_pair[t]];
+      if (pref >= 0 && load[pref] == load[best]) best = pref;
+      lists[best].push_back(t);
+      load[best] += tile_cost[t];
+      last_xcd[tile_pair[t]] = best;
+    }
     size_t rows = 0;
     for (auto& l : lists) rows = std::max(rows, l.size());
     plan.order.assign(rows * kXcds, -1);
