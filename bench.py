@@ -57,6 +57,42 @@ def time_products(sb, ctx, psi, y, prec, n):
     return 1e3 * ms / max(k, 1)
 
 
+def kernel_only(sb, ctx, psi, flops, n):
+    import torch
+    y = torch.empty_like(psi)
+    us = time_products(sb, ctx, psi, y, "fp32", n)
+    # calibration copies: 512 MiB, larger than the last-level cache, so every
+    # byte read comes from HBM
+    big = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(big)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(big)
+    torch.cuda.synchronize()
+    print(json.dumps({"kernel_only": n, "fp32_product_us": round(us, 3),
+                      "tflops": round(flops / us / 1e6, 3),
+                      "copy_bytes_read": 8 * big.numel(), "copy_bytes_written": 8 * big.numel()}),
+          flush=True)
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the FP32 product kernel from the committed
+    counter summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hpsi_tiles_hubbard_L64_U4_m512.traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
 def cpu_baseline(desc, flops, seconds):
     import numpy as np
     from oracle import superblock as OS
@@ -90,6 +126,9 @@ def main():
     ap.add_argument("--workload", default="hubbard_L64_U4_m512")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-only", type=int, default=0, metavar="N",
+                    help="for profilers: N FP32 products, then N plain copies of a vector of "
+                         "the same length (the copy calibrates HBM byte counters), and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -115,6 +154,9 @@ def main():
     psi0 = torch.tensor(seeded_vector(sb.D, 0), dtype=torch.float64, device="cuda")
     log(f"[bench] {args.workload}: D={sb.D} pairs={len(sb.s_sec)} terms={sb.nterms} "
         f"tiles={st['ntiles']} F_alg={F:.3e} flop/product build={build_ms:.0f} ms")
+    if args.kernel_only:
+        kernel_only(sb, ctx, psi0, F, args.kernel_only)
+        return
 
     parts = {"lanczos": 0.0, "rho_S": 0.0, "adjoint": 0.0}
 
@@ -178,7 +220,8 @@ def main():
                    "D": sb.D, "sector_pairs": int(len(sb.s_sec)), "terms": sb.nterms,
                    "tiles": st["ntiles"], "flops_alg_per_product": F},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK["fp32"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 5), "traffic": None},
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 5),
+                     "traffic": traffic_per_launch()},
         "product_us": {k: round(v, 3) for k, v in us.items()},
         "speedup_fp32_vs_fp64_plain": round(us["fp64_plain"] / us["fp32"], 3),
         "speedup_fp32_vs_fp64_fused": round(us["fp64"] / us["fp32"], 3),

@@ -192,7 +192,8 @@ dmrg_status dmrg_sb_layout(dmrg_sb sb, int64_t* D, int32_t* npairs, const int64_
 /* Work statistics of one H*psi: algorithmic flops (dense blocks at their
  * stored size, gathers at 2 flops per element touched), flops the matrix
  * cores issue (padded tiles), algorithmic bytes (operators once in the
- * compute precision, psi read and y read+written in FP64), and the number of
+ * compute precision, psi read once and y written once in FP64; a product
+ * with beta != 0 also reads y, 8 bytes per element more), and the number of
  * work tiles.  Any pointer may be NULL.                                      */
 dmrg_status dmrg_sb_stats(dmrg_sb sb, double* flops_alg, double* flops_exec,
                           double* bytes_alg, int32_t* ntiles);

@@ -220,31 +220,31 @@ hipError_t take_event(dmrg_ctx c, hipEvent_t* e) {
 }
 
 dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
-                              double alpha, double beta);
+                              double alpha, double beta, hipEvent_t t0, hipEvent_t t1);
 
 // y = alpha H psi + beta y with a given plan and precision (timed if asked).
 dmrg_status run_product(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
                         double alpha, double beta) {
   dmrg_ctx c = sb->ctx;
-  if (!c->timing) return run_product_inner(sb, st, prec, psi, y, alpha, beta);
+  if (!c->timing) return run_product_inner(sb, st, prec, psi, y, alpha, beta, nullptr, nullptr);
   dmrg_ctx_s::Mark mk;
   HIP_TRY(take_event(c, &mk.a));
   HIP_TRY(take_event(c, &mk.b));
   mk.prec = (int)prec;
-  HIP_TRY(hipEventRecord(mk.a, c->stream));
-  dmrg_status st2 = run_product_inner(sb, st, prec, psi, y, alpha, beta);
-  HIP_TRY(hipEventRecord(mk.b, c->stream));
+  dmrg_status st2 = run_product_inner(sb, st, prec, psi, y, alpha, beta, mk.a, mk.b);
   c->marks.push_back(mk);
   return st2;
 }
 
 dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
-                              double alpha, double beta) {
+                              double alpha, double beta, hipEvent_t t0, hipEvent_t t1) {
   hipStream_t s = sb->ctx->stream;
   const Plan& p = st.plan;
   if (prec == DMRG_FP64_PLAIN) {
+    if (t0) HIP_TRY(hipEventRecord(t0, s));
     HIP_TRY(launch_plain(st.plain, p.D, st.dense64.as<double>(), st.gsrc.as<int32_t>(),
                          st.gscale.as<double>(), psi, y, alpha, beta, s));
+    if (t1) HIP_TRY(hipEventRecord(t1, s));
     return DMRG_OK;
   }
   const void* dense = st.dense64.p;
@@ -253,7 +253,7 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
     dense = st.dense32.p;
   }
   HIP_TRY(launch_hpsi(kernel_prec(prec), st.nslots, st.images.as<uint32_t>(), st.img_stride, dense,
-                      psi, y, alpha, beta, s));
+                      psi, y, alpha, beta, s, t0, t1));
   return DMRG_OK;
 }
 

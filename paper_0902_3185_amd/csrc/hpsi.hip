@@ -9,6 +9,7 @@
 // operators on both sides are elementwise and are added in FP64 afterwards.
 // No atomics are used on y.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include "kernels.h"
 
@@ -772,17 +773,19 @@ __global__ __launch_bounds__(256) void plain_segment(SegDesc sg, TileDesc t,
 // ---------------------------------------------------------------------------
 hipError_t launch_hpsi(int prec, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
-                       hipStream_t stream) {
+                       hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
   if (nslots <= 0) return hipSuccess;
+  // hipExtLaunchKernelGGL records t0/t1 (when given) at the dispatch's own
+  // start and end, so the interval is the kernel alone
   if (prec == kPrecF32) {
-    hipLaunchKernelGGL(hpsi_tiles<F32Tile>, dim3(nslots), dim3(F32Tile::kWaves * 64), 0, stream,
-                       images, stride, (const float*)dense, psi, y, alpha, beta);
+    hipExtLaunchKernelGGL(hpsi_tiles<F32Tile>, dim3(nslots), dim3(F32Tile::kWaves * 64), 0, stream, t0,
+                          t1, 0, images, stride, (const float*)dense, psi, y, alpha, beta);
   } else if (prec == kPrecBF16X3) {
-    hipLaunchKernelGGL(hpsi_tiles<BF16Tile>, dim3(nslots), dim3(BF16Tile::kWaves * 64), 0, stream,
-                       images, stride, (const float*)dense, psi, y, alpha, beta);
+    hipExtLaunchKernelGGL(hpsi_tiles<BF16Tile>, dim3(nslots), dim3(BF16Tile::kWaves * 64), 0, stream,
+                          t0, t1, 0, images, stride, (const float*)dense, psi, y, alpha, beta);
   } else {
-    hipLaunchKernelGGL(hpsi_tiles<F64Tile>, dim3(nslots), dim3(F64Tile::kWaves * 64), 0, stream,
-                       images, stride, (const double*)dense, psi, y, alpha, beta);
+    hipExtLaunchKernelGGL(hpsi_tiles<F64Tile>, dim3(nslots), dim3(F64Tile::kWaves * 64), 0, stream, t0,
+                          t1, 0, images, stride, (const double*)dense, psi, y, alpha, beta);
   }
   return hipGetLastError();
 }

@@ -18,10 +18,11 @@ constexpr int kMaxSegPerBlock = 32;
 // y = alpha * H psi + beta * y with the fused kernel: nslots workgroups, slot
 // b working from the tile image at images + b * stride (words; see
 // build_images).  `dense` holds the operator pool in the kernel's precision
-// (double for F64, float for F32 and BF16X3).
+// (double for F64, float for F32 and BF16X3).  Events t0/t1, when not null,
+// are recorded at the start and end of the kernel itself.
 hipError_t launch_hpsi(int prec, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
-                       hipStream_t stream);
+                       hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // partial[tile * stride + s] = < G tile, segment s of the tile with c = 1 >
 hipError_t launch_term_dots(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,

@@ -351,10 +351,12 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
   // XCD-aware order.  Tiles go to the XCDs by LPT on their cost (most
   // expensive first, each to the least loaded XCD), so that every XCD ends
   // at about the same time even when a few large blocks hold most of the
-  // work; ties go to the XCD that already holds tiles of the same block, so
-  // that a block's operators and psi rows tend to stay in one L2.  Slot b of
-  // the launch runs on XCD b % kXcds and takes the (b / kXcds)-th tile of
-  // that XCD's list, most expensive first.
+  // work.  A tile stays on the XCD that took the previous tile of its block
+  // while that XCD is within one tile's cost of the least loaded one, so
+  // that a block's operators and psi rows are fetched into few L2s.  Slot b
+  // of the launch runs on XCD b % kXcds and takes the (b / kXcds)-th tile of
+  // that XCD's list, most expensive first; the hardware starts each slot as
+  // a compute unit frees up.
   {
     std::vector<int32_t> tidx(plan.tiles.size());
     for (size_t t = 0; t < tidx.size(); ++t) tidx[t] = (int32_t)t;
@@ -368,7 +370,7 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
       for (int x = 1; x < kXcds; ++x)
         if (load[x] < load[best]) best = x;
       const int pref = last_xcd[tile_pair[t]];
-      if (pref >= 0 && load[pref] == load[best]) best = pref;
+      if (pref >= 0 && load[pref] <= load[best] + tile_cost[t]) best = pref;
       lists[best].push_back(t);
       load[best] += tile_cost[t];
       last_xcd[tile_pair[t]] = best;
@@ -475,7 +477,8 @@ bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>
 }
 
 double plan_bytes_alg(const Plan& p, int elem_bytes) {
-  return (double)elem_bytes * p.dense.size() + 12.0 * p.gsrc.size() + 24.0 * p.D;
+  // operators once, gather entries once, psi read once and y written once
+  return (double)elem_bytes * p.dense.size() + 12.0 * p.gsrc.size() + 8.0 * (p.D_in + p.D);
 }
 
 }  // namespace dmrg
