@@ -156,8 +156,11 @@ constexpr int kAxSpan = kLzThreads * kAxPer;     // elements per block (axpy)
 int dot_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kDotSpan - 1) / kDotSpan); }
 int axpy_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kAxSpan - 1) / kAxSpan); }
 
+constexpr int kFusedMaxNv = 64;   // basis size up to which axpy and dot share a pass
+
 size_t lz_partial_size(int64_t n, int nv) {
-  return std::max((size_t)nv * dot_blocks(n), (size_t)axpy_blocks(n));
+  const size_t fused = (size_t)std::min(nv, kFusedMaxNv) * (size_t)((n + kLzThreads - 1) / kLzThreads);
+  return std::max({(size_t)nv * dot_blocks(n), (size_t)axpy_blocks(n), fused});
 }
 
 __device__ inline double wave_sum(double v) {
@@ -319,6 +322,67 @@ __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
   if (i < n) v[i] = w[i] * inv;
 }
 
+// w -= sum_{i<nv} h[i] V_i, then partial[i * gridDim.x + blockIdx.x] = the
+// block's part of <V_i, w> for the updated w: one pass over the basis for
+// both (the first CGS pass's update and the second pass's products).  Each
+// thread keeps its element of every basis vector in registers, so kNv (32 or
+// 64) bounds nv; one element per thread, 256 per block.  The kNv per-lane
+// products are summed over a wave by a reduce-scatter butterfly: at every
+// step a lane sends half of its values to its partner and keeps the other
+// half, so after the last step lane l holds the wave's sum for vector
+// l mod kNv (kNv - 1 exchanges instead of 6 kNv).
+template <int kNv>
+__global__ __launch_bounds__(kLzThreads) void lz_axpy_dot(double* __restrict__ w,
+                                                          const double* __restrict__ V,
+                                                          int64_t ldv, int nv, int64_t n,
+                                                          const double* __restrict__ h,
+                                                          double* __restrict__ partial) {
+  static_assert(kNv == 32 || kNv == 64, "the butterfly covers 32 or 64 vectors");
+  __shared__ double sh[kLzThreads / 64][kNv];
+  const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
+  const bool ok = e < n;
+  const int64_t ec = ok ? e : n - 1;   // in-range address for the tail block
+  double v[kNv];
+#pragma unroll
+  for (int i = 0; i < kNv; ++i) v[i] = V[(int64_t)(i < nv ? i : 0) * ldv + ec];
+  double x = ok ? w[ec] : 0.0;
+#pragma unroll
+  for (int i = 0; i < kNv; ++i)
+    if (i < nv) x -= h[i] * v[i];
+  if (ok) w[e] = x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double p[kNv];
+#pragma unroll
+  for (int i = 0; i < kNv; ++i) p[i] = (ok && i < nv) ? v[i] * x : 0.0;
+  // reduce-scatter over offsets kNv/2, ..., 1: values [0, c) -> [0, c/2)
+#pragma unroll
+  for (int c = kNv; c > 1; c >>= 1) {
+    const int half = c >> 1;
+    const bool upper = (lane & half) != 0;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      const double send = upper ? p[j] : p[j + half];
+      const double keep = upper ? p[j + half] : p[j];
+      p[j] = keep + __shfl_xor(send, half, 64);
+    }
+  }
+  // lane l now holds the sum over its group of kNv lanes for vector l % kNv
+  double t = p[0];
+  if (kNv == 32) t += __shfl_xor(t, 32, 64);
+  if (lane < kNv) sh[wave][lane] = t;
+  __syncthreads();
+  if (threadIdx.x < nv)
+    partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] =
+        ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+}
+
+template <int kNv>
+void launch_axpy_dot(double* w, const double* V, int64_t ldv, int nv, int64_t n, const double* h,
+                     double* partial, int nb, hipStream_t stream) {
+  hipLaunchKernelGGL(lz_axpy_dot<kNv>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h,
+                     partial);
+}
+
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
                           hipStream_t stream) {
@@ -326,10 +390,20 @@ hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64
   const int na = axpy_blocks(n);
   hipLaunchKernelGGL(lz_dot, gd, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
   hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, (int)gd.x, h1);
-  hipLaunchKernelGGL(lz_axpy<false>, dim3(na), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
-                     partial);
-  hipLaunchKernelGGL(lz_dot, gd, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
-  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, (int)gd.x, h2);
+  if (nv <= kFusedMaxNv) {
+    // first update and second products in one pass over the basis
+    const int nb = (int)((n + kLzThreads - 1) / kLzThreads);
+    if (nv <= 32)
+      launch_axpy_dot<32>(w, V, ldv, nv, n, h1, partial, nb, stream);
+    else
+      launch_axpy_dot<64>(w, V, ldv, nv, n, h1, partial, nb, stream);
+    hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
+  } else {
+    hipLaunchKernelGGL(lz_axpy<false>, dim3(na), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
+                       partial);
+    hipLaunchKernelGGL(lz_dot, gd, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+    hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, (int)gd.x, h2);
+  }
   hipLaunchKernelGGL(lz_axpy<true>, dim3(na), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h2,
                      partial);
   const unsigned nfin = vnext ? (unsigned)((n + kThreads - 1) / kThreads) : 1u;
