@@ -147,6 +147,7 @@ def main():
     ctx = Context(0)
     t0 = time.perf_counter()
     sb = Superblock(desc, prec="fp32", ctx=ctx)
+    variant = sb.autotune(reps=20)   # tile-kernel variant for this superblock (same results)
     torch.cuda.synchronize()
     build_ms = 1e3 * (time.perf_counter() - t0)
     st = sb.stats()
@@ -218,7 +219,7 @@ def main():
         "config": {"workload": "hubbard_L64_U4_m512 centre superblock: Hubbard chain L=64, U=4, "
                                "t=1, half filling, m=512, synthetic sectors/operators seed 0",
                    "D": sb.D, "sector_pairs": int(len(sb.s_sec)), "terms": sb.nterms,
-                   "tiles": st["ntiles"], "flops_alg_per_product": F},
+                   "tiles": st["ntiles"], "flops_alg_per_product": F, "kernel_variant": variant},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK["fp32"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 5),
                      "traffic": traffic_per_launch()},

@@ -206,6 +206,19 @@ dmrg_status dmrg_sb_set_coeffs(dmrg_sb sb, const double* c_h);
  * or if this call stages them).                                            */
 dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec);
 
+/* Tile-shape autotuner: times every variant of the fused product kernel for
+ * the current precision on this superblock (reps launches each, on zeroed
+ * device vectors the call allocates and frees) and keeps the fastest for
+ * later products.  The variants differ only in how row-walking operands are
+ * read (per lane, or whole rows per group of lanes through LDS): results are
+ * identical.  *variant (may be NULL) receives the choice; FP64 and the plain
+ * baseline have one variant (0).  Synchronous.                              */
+dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant);
+
+/* Pin the fused-kernel variant for the current precision (0 or 1, as
+ * dmrg_sb_autotune reports it); DMRG_E_ARG for an unknown variant.         */
+dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant);
+
 /* y_d = alpha * H psi_d + beta * y_d (paper Sec. 3.3: the Lanczos solver's
  * only need, x += H y, with alpha = beta = 1).  psi_d and y_d are device FP64
  * arrays of length D in the dmrg_sb_layout order and must not overlap.

@@ -85,6 +85,8 @@ _SIGS = {
     "dmrg_rho_truncate": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(dmrg_trunc)]),
     "dmrg_transform_blocks": (C.c_int, [_P, C.c_int32, C.POINTER(dmrg_tblock), _P, _P, _P]),
     "dmrg_host_sym_eigen": (C.c_int, [C.c_int32, _D, _D]),
+    "dmrg_sb_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32)]),
+    "dmrg_sb_set_variant": (C.c_int, [_P, C.c_int32]),
     "dmrg_host_tridiag_lowest": (C.c_int, [C.c_int32, _D, _D, _D, _D]),
 }
 

@@ -142,6 +142,7 @@ struct dmrg_sb_s {
   std::vector<std::unique_ptr<OpCopy>> opA, opB;
   Staged fwd;
   std::unique_ptr<Staged> adj;
+  int variant[3] = {0, 0, 0};   // fused-kernel variant per kernel precision (autotuner)
   // density-matrix scratch and results
   DevBuf rho_images, rho_out;
   std::vector<double> tr_lambda;
@@ -252,7 +253,8 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
     if (!st.has32) return fail(DMRG_E_ARG, "FP32 operators not staged (use dmrg_sb_set_prec)");
     dense = st.dense32.p;
   }
-  HIP_TRY(launch_hpsi(kernel_prec(prec), st.nslots, st.images.as<uint32_t>(), st.img_stride, dense,
+  const int kp = kernel_prec(prec);
+  HIP_TRY(launch_hpsi(kp, sb->variant[kp], st.nslots, st.images.as<uint32_t>(), st.img_stride, dense,
                       psi, y, alpha, beta, s, t0, t1));
   return DMRG_OK;
 }
@@ -509,6 +511,61 @@ dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec) {
   return DMRG_OK;
 }
 
+dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant) {
+  dmrg_status st = need_device(sb);
+  if (st != DMRG_OK) return st;
+  if (reps < 1) return fail(DMRG_E_ARG, "reps must be >= 1");
+  const int kp = kernel_prec(sb->prec);
+  if (sb->prec == DMRG_FP64 || sb->prec == DMRG_FP64_PLAIN) {
+    if (variant) *variant = 0;
+    return DMRG_OK;
+  }
+  if (!sb->fwd.has32) return fail(DMRG_E_ARG, "FP32 operators not staged (use dmrg_sb_set_prec)");
+  DeviceGuard g(sb->ctx->device);
+  hipStream_t s = sb->ctx->stream;
+  const Staged& stg = sb->fwd;
+  DevBuf x, y;
+  HIP_TRY(x.ensure((size_t)std::max<int64_t>(stg.plan.D_in, 1) * sizeof(double)));
+  HIP_TRY(y.ensure((size_t)std::max<int64_t>(stg.plan.D, 1) * sizeof(double)));
+  HIP_TRY(hipMemsetAsync(x.p, 0, (size_t)stg.plan.D_in * sizeof(double), s));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.f;
+  hipError_t err = hipSuccess;
+  for (int v = 0; v < kVariants && err == hipSuccess; ++v) {
+    auto go = [&]() {
+      return launch_hpsi(kp, v, stg.nslots, stg.images.as<uint32_t>(), stg.img_stride, stg.dense32.p,
+                         x.as<double>(), y.as<double>(), 1.0, 0.0, s);
+    };
+    for (int w = 0; w < 2 && err == hipSuccess; ++w) err = go();
+    if (err == hipSuccess) err = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = go();
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err == hipSuccess && (v == 0 || ms < best_ms)) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(err);
+  sb->variant[kp] = best;
+  if (variant) *variant = best;
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant) {
+  if (!sb) return fail(DMRG_E_ARG, "null superblock");
+  if (variant < 0 || variant >= kVariants) return fail(DMRG_E_ARG, "unknown kernel variant");
+  sb->variant[kernel_prec(sb->prec)] = variant;
+  return DMRG_OK;
+}
+
 dmrg_status dmrg_hpsi(dmrg_sb sb, const double* psi_d, double* y_d, double alpha, double beta) {
   dmrg_status st = need_device(sb);
   if (st != DMRG_OK) return st;
@@ -755,7 +812,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   }
   if ((st = upload(sb->rho_images, img.data(), img.size() * sizeof(uint32_t), s)) != DMRG_OK) return st;
   HIP_TRY(sb->rho_out.ensure((size_t)std::max<int64_t>(total, 1) * sizeof(double)));
-  HIP_TRY(launch_hpsi(kPrecF64, (int)tiles.size(), sb->rho_images.as<uint32_t>(), stride, psi_d, psi_d,
+  HIP_TRY(launch_hpsi(kPrecF64, 0, (int)tiles.size(), sb->rho_images.as<uint32_t>(), stride, psi_d, psi_d,
                       sb->rho_out.as<double>(), 1.0, 0.0, s));
   std::vector<double> rho((size_t)total);
   HIP_TRY(hipMemcpyAsync(rho.data(), sb->rho_out.p, rho.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -986,8 +1043,8 @@ dmrg_status dmrg_transform_blocks(dmrg_ctx ctx, int32_t nblk, const dmrg_tblock*
   if ((st = upload(ctx->tr_images, img1.data(), img1.size() * sizeof(uint32_t), s)) != DMRG_OK) return st;
   HIP_TRY(ctx->tr_tmp.ensure((size_t)std::max<int64_t>(utot, 1) * sizeof(double)));
   const uint32_t* di = ctx->tr_images.as<uint32_t>();
-  HIP_TRY(launch_hpsi(kPrecF64, (int)n1, di, stride1, O_d, W_d, ctx->tr_tmp.as<double>(), 1.0, 0.0, s));
-  HIP_TRY(launch_hpsi(kPrecF64, (int)n2, di + w1, stride2, ctx->tr_tmp.as<double>(), W_d, out_d, 1.0,
+  HIP_TRY(launch_hpsi(kPrecF64, 0, (int)n1, di, stride1, O_d, W_d, ctx->tr_tmp.as<double>(), 1.0, 0.0, s));
+  HIP_TRY(launch_hpsi(kPrecF64, 0, (int)n2, di + w1, stride2, ctx->tr_tmp.as<double>(), W_d, out_d, 1.0,
                       0.0, s));
   HIP_TRY(hipStreamSynchronize(s));   // the host tile lists die here
   return DMRG_OK;

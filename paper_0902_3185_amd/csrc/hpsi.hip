@@ -278,6 +278,7 @@ struct F32Tile {
 #pragma unroll
     for (int r = 0; r < 16; ++r) a.d[r] = 0.f;
   }
+  template <bool kStage>
   __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
                               const op_t* dense, const double* psi, int lane) {
     const int i = lane & 31, kb = ch * kChunk + 8 * (lane >> 5);
@@ -292,10 +293,9 @@ struct F32Tile {
         R.f[s] = At[k * lda];
         R.d[s] = P[k * ldp];
       }
-    } else {
-      // each lane walks its own row along k: 16-byte loads keep the
-      // per-lane runs whole (rows are only element-aligned, which the
-      // memory system takes for vector loads)
+    } else if (!kStage) {
+      // each lane walks its own row along k with 16-byte loads (rows are
+      // only element-aligned, which the memory system takes for vector loads)
       const double* Arow = psi + sg.psi_off + (int64_t)max(sg.src[i], 0) * sg.psi_ld;
       const op_t* Brow = dense + sg.op_off + (int64_t)min(g.n0 + i, g.b - 1) * sg.op_ld;
       if (K - (ch + 1) * kChunk >= 0) {   // whole chunk in range (uniform)
@@ -323,12 +323,54 @@ struct F32Tile {
           R.f[s] = Brow[k];
         }
       }
+    } else {
+      // whole rows per group of lanes, so that each load instruction covers
+      // few cache lines: A rows are 16 doubles, 8 lanes x 16 bytes per row,
+      // 8 rows per instruction; B rows are 16 floats, 4 lanes x 16 bytes, 16
+      // rows per instruction.  operands() transposes them through LDS.
+      const int q8 = lane & 7, r8 = lane >> 3, q4 = lane & 3, r4 = lane >> 2;
+      const int kc = ch * kChunk;
+      const bool full = K - (ch + 1) * kChunk >= 0;   // whole chunk in range (uniform)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double* Arow = psi + sg.psi_off + (int64_t)max(sg.src[8 * j + r8], 0) * sg.psi_ld;
+        if (full) {
+          d2 t;
+          __builtin_memcpy(&t, Arow + kc + 2 * q8, sizeof(t));
+          R.d[2 * j] = t.x;
+          R.d[2 * j + 1] = t.y;
+        } else {
+          R.d[2 * j] = Arow[min(kc + 2 * q8, K - 1)];
+          R.d[2 * j + 1] = Arow[min(kc + 2 * q8 + 1, K - 1)];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const op_t* Brow = dense + sg.op_off + (int64_t)min(g.n0 + 16 * j + r4, g.b - 1) * sg.op_ld;
+        if (full) {
+          f4 t;
+          __builtin_memcpy(&t, Brow + kc + 4 * q4, sizeof(t));
+          R.f[4 * j] = t.x;
+          R.f[4 * j + 1] = t.y;
+          R.f[4 * j + 2] = t.z;
+          R.f[4 * j + 3] = t.w;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) R.f[4 * j + t] = Brow[min(kc + 4 * q4 + t, K - 1)];
+        }
+      }
     }
   }
+  // LDS staging of one wave's row-walking chunk: A and B as [row][k] floats,
+  // rows padded to kStageLd (16-byte aligned rows).
+  static constexpr int kStageLd = 20;
+  static constexpr int kStageFloats = 2 * kTile * kStageLd;   // per wave
   // operands of one chunk in FP32, scaled and masked
+  template <bool kStage>
   __device__ static void operands(const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
-                                  const TileGeo& g, int lane, float (&a)[8], float (&b)[8]) {
-    const int i = lane & 31, kv = K - ch * kChunk - 8 * (lane >> 5);
+                                  const TileGeo& g, int lane, float* stage, float (&a)[8],
+                                  float (&b)[8]) {
+    const int i = lane & 31, kh = lane >> 5, kv = K - ch * kChunk - 8 * kh;
     const int src = sg.src[i];
     if (kind == SEG_KN) {
       const float cA = g.m0 + i < g.a ? (float)sg.c : 0.f;
@@ -338,7 +380,7 @@ struct F32Tile {
         a[s] = s < kv ? cA * R.f[s] : 0.f;
         b[s] = s < kv ? sB * (float)R.d[s] : 0.f;
       }
-    } else {
+    } else if (!kStage) {
       const float cA = src >= 0 ? (float)(sg.c * sg.scl[i]) : 0.f;
       const float sB = g.n0 + i < g.b ? 1.f : 0.f;
 #pragma unroll
@@ -346,12 +388,54 @@ struct F32Tile {
         a[s] = s < kv ? cA * (float)R.d[s] : 0.f;
         b[s] = s < kv ? sB * R.f[s] : 0.f;
       }
+    } else {
+      // transpose through the wave's LDS stage: rows as loaded, then each
+      // lane reads its own row's 8 contraction elements (the wave's LDS
+      // operations complete in order)
+      float* As = stage;
+      float* Bs = stage + kTile * kStageLd;
+      const int q8 = lane & 7, r8 = lane >> 3, q4 = lane & 3, r4 = lane >> 2;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float2 t;
+        t.x = (float)R.d[2 * j];
+        t.y = (float)R.d[2 * j + 1];
+        *reinterpret_cast<float2*>(As + (8 * j + r8) * kStageLd + 2 * q8) = t;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        float4 t;
+        t.x = R.f[4 * j];
+        t.y = R.f[4 * j + 1];
+        t.z = R.f[4 * j + 2];
+        t.w = R.f[4 * j + 3];
+        *reinterpret_cast<float4*>(Bs + (16 * j + r4) * kStageLd + 4 * q4) = t;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const float4 a0 = *reinterpret_cast<const float4*>(As + i * kStageLd + 8 * kh);
+      const float4 a1 = *reinterpret_cast<const float4*>(As + i * kStageLd + 8 * kh + 4);
+      const float4 b0 = *reinterpret_cast<const float4*>(Bs + i * kStageLd + 8 * kh);
+      const float4 b1 = *reinterpret_cast<const float4*>(Bs + i * kStageLd + 8 * kh + 4);
+      const float ar[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+      const float br[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+      const float cA = src >= 0 ? (float)(sg.c * sg.scl[i]) : 0.f;
+      const float sB = g.n0 + i < g.b ? 1.f : 0.f;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        a[s] = s < kv ? cA * ar[s] : 0.f;
+        b[s] = s < kv ? sB * br[s] : 0.f;
+      }
+      // the stage is rewritten by the wave's next chunk only after these reads
+      __builtin_amdgcn_wave_barrier();
     }
   }
+  template <bool kStage>
   __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
-                             const TileGeo& g, int lane) {
+                             const TileGeo& g, int lane, float* stage) {
     float a[8], b[8];
-    operands(R, sg, kind, K, ch, g, lane, a, b);
+    operands<kStage>(R, sg, kind, K, ch, g, lane, stage, a, b);
 #pragma unroll
     for (int s = 0; s < 8; ++s) acc.d = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc.d, 0, 0, 0);
   }
@@ -376,9 +460,10 @@ struct BF16Tile {
   using Acc = F32Tile::Acc;
   using Raw = F32Tile::Raw;
   __device__ static void zero(Acc& a) { F32Tile::zero(a); }
+  template <bool kStage>
   __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
                               const op_t* dense, const double* psi, int lane) {
-    F32Tile::load(R, sg, kind, K, ch, g, dense, psi, lane);
+    F32Tile::load<kStage>(R, sg, kind, K, ch, g, dense, psi, lane);
   }
   __device__ static void split(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
 #pragma unroll
@@ -388,10 +473,12 @@ struct BF16Tile {
       lo[j] = (__bf16)(x[j] - (float)h);
     }
   }
+  static constexpr int kStageFloats = F32Tile::kStageFloats;
+  template <bool kStage>
   __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
-                             const TileGeo& g, int lane) {
+                             const TileGeo& g, int lane, float* stage) {
     float a[8], b[8];
-    F32Tile::operands(R, sg, kind, K, ch, g, lane, a, b);
+    F32Tile::operands<kStage>(R, sg, kind, K, ch, g, lane, stage, a, b);
     bf16x8 ah, al, bh, bl;
     split(a, ah, al);
     split(b, bh, bl);
@@ -424,6 +511,7 @@ struct F64Tile {
 #pragma unroll
       for (int r = 0; r < 4; ++r) a.d[q][r] = 0.0;
   }
+  template <bool kStage>
   __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
                               const op_t* dense, const double* psi, int lane) {
     const int i = lane & 15, kb = ch * kChunk + 4 * (lane >> 4);
@@ -476,8 +564,10 @@ struct F64Tile {
       }
     }
   }
+  static constexpr int kStageFloats = 0;   // rows are read per lane, no LDS stage
+  template <bool kStage>
   __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
-                             const TileGeo& g, int lane) {
+                             const TileGeo& g, int lane, float* /*stage*/) {
     const int i = lane & 15, kv = K - ch * kChunk - 4 * (lane >> 4);
     const int src0 = sg.src[i], src1 = sg.src[16 + i];
     double cA0, cA1, sB0, sB1;
@@ -529,7 +619,7 @@ __device__ inline double img_gg_term(const ImgGG& G, int mi, int nj, const doubl
   return img_gg_coef(G, mi, nj) * v;
 }
 
-template <class Cfg>
+template <class Cfg, bool kStage>
 __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
     const uint32_t* __restrict__ images, int32_t stride,
     const typename Cfg::op_t* __restrict__ dense, const double* __restrict__ psi,
@@ -538,7 +628,12 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
   constexpr int kT = kW * 64;
   constexpr int kPer = kTile * kTile / kT;   // output elements per thread
   __shared__ __align__(16) uint32_t img[kImgWords];
-  __shared__ typename Cfg::red_t red[kW][kTile * kTile];
+  // the waves' partial tiles (phase 2) share LDS with their chunk stages (phase 1)
+  using red_t = typename Cfg::red_t;
+  constexpr size_t kRedBytes = sizeof(red_t) * kW * kTile * kTile;
+  constexpr size_t kStageBytes = kStage ? sizeof(float) * kW * Cfg::kStageFloats : 0;
+  __shared__ __align__(16) char pool[kRedBytes > kStageBytes ? kRedBytes : kStageBytes];
+  auto red = reinterpret_cast<red_t(*)[kTile * kTile]>(pool);
 
   // phase 0: the slot's image into LDS
   {
@@ -597,11 +692,12 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
     };
     auto fetch = [&](typename Cfg::Raw& R, int gc, int s) {
       const ImgSeg& sg = img_seg(img, s);
-      Cfg::load(R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, dense, psi, lane);
+      Cfg::template load<kStage>(R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, dense, psi, lane);
     };
+    float* stage = reinterpret_cast<float*>(pool) + wave * Cfg::kStageFloats;
     auto run = [&](const typename Cfg::Raw& R, int gc, int s) {
       const ImgSeg& sg = img_seg(img, s);
-      Cfg::mma(acc, R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, lane);
+      Cfg::template mma<kStage>(acc, R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, lane, stage);
     };
     int gA = wave, sA = seg_for(gA);
     gg_issue();
@@ -631,15 +727,18 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
         fetch(rb, gB, sB);
       }
     }
+  } else {
+    gg_issue();
+    gg_sum();
+  }
+  __syncthreads();   // every wave is done with its chunk stage
+  if (wave < nchunk) {
 #pragma unroll
     for (int r = 0; r < Cfg::kRegs; ++r) {
       int row, col;
       Cfg::coords(lane, r, row, col);
       red[wave][row * kTile + col] = Cfg::value(acc, r);
     }
-  } else {
-    gg_issue();
-    gg_sum();
   }
   __syncthreads();
 
@@ -771,21 +870,33 @@ __global__ __launch_bounds__(256) void plain_segment(SegDesc sg, TileDesc t,
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_hpsi(int prec, int nslots, const uint32_t* images, int32_t stride,
+template <class Cfg, bool kStage>
+void launch_tiles(int nslots, const uint32_t* images, int32_t stride, const void* dense,
+                  const double* psi, double* y, double alpha, double beta, hipStream_t stream,
+                  hipEvent_t t0, hipEvent_t t1) {
+  // hipExtLaunchKernelGGL records t0/t1 (when given) at the dispatch's own
+  // start and end, so the interval is the kernel alone
+  hipExtLaunchKernelGGL(hpsi_tiles<Cfg, kStage>, dim3(nslots), dim3(Cfg::kWaves * 64), 0, stream, t0,
+                        t1, 0, images, stride, (const typename Cfg::op_t*)dense, psi, y, alpha, beta);
+}
+
+hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
                        hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
   if (nslots <= 0) return hipSuccess;
-  // hipExtLaunchKernelGGL records t0/t1 (when given) at the dispatch's own
-  // start and end, so the interval is the kernel alone
+  const bool stage = variant == kVariantStagedRows;
   if (prec == kPrecF32) {
-    hipExtLaunchKernelGGL(hpsi_tiles<F32Tile>, dim3(nslots), dim3(F32Tile::kWaves * 64), 0, stream, t0,
-                          t1, 0, images, stride, (const float*)dense, psi, y, alpha, beta);
+    if (stage)
+      launch_tiles<F32Tile, true>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
+    else
+      launch_tiles<F32Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
   } else if (prec == kPrecBF16X3) {
-    hipExtLaunchKernelGGL(hpsi_tiles<BF16Tile>, dim3(nslots), dim3(BF16Tile::kWaves * 64), 0, stream,
-                          t0, t1, 0, images, stride, (const float*)dense, psi, y, alpha, beta);
+    if (stage)
+      launch_tiles<BF16Tile, true>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
+    else
+      launch_tiles<BF16Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
   } else {
-    hipExtLaunchKernelGGL(hpsi_tiles<F64Tile>, dim3(nslots), dim3(F64Tile::kWaves * 64), 0, stream, t0,
-                          t1, 0, images, stride, (const double*)dense, psi, y, alpha, beta);
+    launch_tiles<F64Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
   }
   return hipGetLastError();
 }

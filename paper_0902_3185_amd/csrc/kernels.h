@@ -18,9 +18,14 @@ constexpr int kMaxSegPerBlock = 32;
 // y = alpha * H psi + beta * y with the fused kernel: nslots workgroups, slot
 // b working from the tile image at images + b * stride (words; see
 // build_images).  `dense` holds the operator pool in the kernel's precision
-// (double for F64, float for F32 and BF16X3).  Events t0/t1, when not null,
-// are recorded at the start and end of the kernel itself.
-hipError_t launch_hpsi(int prec, int nslots, const uint32_t* images, int32_t stride,
+// (double for F64, float for F32 and BF16X3).  `variant` selects how the
+// FP32 / BF16 kernel reads row-walking operands (kVariant*; results are
+// identical); the FP64 kernel has one.  Events t0/t1, when not null, are
+// recorded at the start and end of the kernel itself.
+constexpr int kVariantRowPerLane = 0;   // each lane reads its own row
+constexpr int kVariantStagedRows = 1;   // groups of lanes read whole rows, transposed through LDS
+constexpr int kVariants = 2;
+hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
                        hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 

@@ -172,6 +172,17 @@ class Superblock:
             raise ValueError("need one coefficient per term")
         check(lib().dmrg_sb_set_coeffs(self.handle, c.ctypes.data_as(C.POINTER(C.c_double))))
 
+    def autotune(self, reps=20):
+        """dmrg_sb_autotune: time the fused kernel's variants for the current
+        precision and keep the fastest; returns the chosen variant."""
+        v = C.c_int32()
+        check(lib().dmrg_sb_autotune(self.handle, int(reps), C.byref(v)))
+        return v.value
+
+    def set_variant(self, variant):
+        """dmrg_sb_set_variant: pin the fused kernel's variant."""
+        check(lib().dmrg_sb_set_variant(self.handle, int(variant)))
+
     def set_prec(self, prec):
         check(lib().dmrg_sb_set_prec(self.handle, PREC[prec]))
         self.prec = prec

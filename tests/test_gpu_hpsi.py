@@ -169,3 +169,27 @@ def test_argument_errors(ctx):
     assert _lib.STATUS[st] == "DMRG_E_ARG"
     with pytest.raises(ValueError):
         sb.hpsi(_dev(np.zeros(sb.D + 1)))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name,m", [("hubbard_L64_U4_m512", 96), ("ladder_2x32_m1024", 80),
+                                    ("heisenberg_L100_m256", None)])
+def test_kernel_variants_identical_and_autotune(ctx, name, m, prec):
+    """Both ways of reading row-walking operands give the same bits; the
+    autotuner picks one of them and the product stays within tolerance."""
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock(name, m=m, seed=5)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    psi = seeded_vector(sb.D, 51)
+    outs = []
+    for v in (0, 1):
+        sb.set_variant(v)
+        outs.append(_host(sb.hpsi(_dev(psi))))
+    assert np.array_equal(outs[0], outs[1])
+    chosen = sb.autotune(reps=3)
+    assert chosen in (0, 1)
+    y = _host(sb.hpsi(_dev(psi)))
+    assert np.array_equal(y, outs[chosen])
+    assert np.linalg.norm(y - OS.hpsi_blocks(desc, psi)) <= TOL[prec] * _scale(desc, psi)
+    with pytest.raises(Exception):
+        sb.set_variant(7)
