@@ -115,6 +115,7 @@ struct dmrg_ctx_s {
   hipStream_t stream = nullptr;
   DevBuf tr_images, tr_tmp;   // basis-change scratch
   // optional per-launch timing of the product kernels (HIP events on `stream`)
+  hipEvent_t chk[2] = {nullptr, nullptr};   // Lanczos check copies
   bool timing = false;
   struct Mark {
     hipEvent_t a, b;
@@ -344,6 +345,8 @@ void dmrg_ctx_destroy(dmrg_ctx ctx) {
     (void)hipEventDestroy(mk.b);
   }
   for (auto e : ctx->spare) (void)hipEventDestroy(e);
+  for (auto e : ctx->chk)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   delete ctx;
 }
@@ -669,47 +672,42 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   double E = 0.0, res = INFINITY;
   bool converged = false;
   std::vector<double> alphas, betas, u;
+  // The host reads (alpha, beta) every kCheck steps without draining the
+  // stream: the copy for a check point goes out behind that step's kernels
+  // into one of two pinned buffers, the steps after it are launched, and the
+  // check is evaluated one check point later (the first step of a cycle and
+  // the last one allowed are evaluated at once).  A cycle that stops at a
+  // check leaves at most kCheck further steps queued; their vectors are not
+  // used.
+  if (!ctx->chk[0]) {
+    HIP_TRY(hipEventCreateWithFlags(&ctx->chk[0], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ctx->chk[1], hipEventDisableTiming));
+  }
+  double* hbuf[2] = {hs, hs + 2 * nvec};
   while (!converged && total < max_iter) {
     double beta0 = 0.0;
     int nv = 0;      // basis vectors that enter the Ritz vector of this cycle
-    int seen = 0;    // steps whose alpha/beta the host has read
     u.clear();
-    for (int j = 0;; ++j) {
-      double* vj = V + (size_t)j * D;
-      const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
-      if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
-      ++total;
-      HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
-                             j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, s));
-      const bool last = j + 2 >= nvec || total >= max_iter;
-      if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
-      HIP_TRY(hipMemcpyAsync(hs + 2 * seen, ab + 2 * seen, 2 * (j + 1 - seen) * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      seen = j + 1;
-      alphas.assign(hs, hs + 0);
+    // evaluates the check taken after step jc from h; true: the cycle stops
+    auto evaluate = [&](int jc, const double* h) {
+      alphas.clear();
       betas.clear();
       // the recursion is valid up to the first vanishing beta
-      int m = 0;
-      for (; m <= j; ++m) {
-        alphas.push_back(hs[2 * m]);
-        const double b = hs[2 * m + 1];
-        if (m == j || b <= 1e-13 * std::max(1.0, std::fabs(hs[2 * m]))) {
-          betas.push_back(b);
-          ++m;
-          break;
-        }
+      for (int m = 0; m <= jc; ++m) {
+        alphas.push_back(h[2 * m]);
+        const double b = h[2 * m + 1];
         betas.push_back(b);
+        if (b <= 1e-13 * std::max(1.0, std::fabs(h[2 * m]))) break;
       }
       const int steps = (int)alphas.size();
-      if (j == 0) {
+      if (jc == 0) {
         E = alphas[0];
         res = betas[0];
         beta0 = betas[0];
         if (res <= tol) {
           converged = true;
           nv = 1;
-          break;
+          return true;
         }
       }
       double theta;
@@ -719,9 +717,34 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       const double bl = betas[steps - 1];
       const double est = bl * std::fabs(u[steps - 1]);
       const double ctol = reduced ? std::max(tol, 1e-4 * beta0) : tol;
-      const bool breakdown = bl <= 1e-13 * std::max(1.0, std::fabs(theta)) || steps < j + 1;
-      if (j > 0 && (est <= ctol || breakdown)) break;
-      if (last) break;
+      const bool breakdown = bl <= 1e-13 * std::max(1.0, std::fabs(theta)) || steps < jc + 1;
+      return jc > 0 && (est <= ctol || breakdown);
+    };
+    int pend = -1, pbuf = 0, nbuf = 0;   // check in flight: its step and buffer
+    for (int j = 0;; ++j) {
+      double* vj = V + (size_t)j * D;
+      const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
+      if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
+      ++total;
+      HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
+                             j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, s));
+      const bool last = j + 2 >= nvec || total >= max_iter;
+      if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
+      HIP_TRY(hipMemcpyAsync(hbuf[nbuf], ab, 2 * (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(ctx->chk[nbuf], s));
+      if (pend >= 0) {   // the previous check: its copy is behind older steps only
+        HIP_TRY(hipEventSynchronize(ctx->chk[pbuf]));
+        if (evaluate(pend, hbuf[pbuf])) break;
+        pend = -1;
+      }
+      if (j == 0 || last) {
+        HIP_TRY(hipEventSynchronize(ctx->chk[nbuf]));
+        if (evaluate(j, hbuf[nbuf]) || last) break;
+      } else {
+        pend = j;
+        pbuf = nbuf;
+      }
+      nbuf ^= 1;
     }
     if (converged) break;
     // Ritz vector of the cycle -> start of the next one
