@@ -59,7 +59,9 @@ def build(verbose=False):
     cmds = []
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        # host C++ (the eigen-solvers, plan and API) for the AVX2/FMA level
+        # of the EPYC hosts MI355X boards sit in
+        lang = ["-x", "hip"] if src.endswith(".hip") else ["-Xarch_host", "-march=x86-64-v3"]
         cmds.append(([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj], src))
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as ex:

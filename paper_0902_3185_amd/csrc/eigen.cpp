@@ -262,8 +262,9 @@ bool sym_eigen(int n, double* A, double* w, int nthreads) {
       const double r = safe_hypot(x, z);
       double c = 1.0, s = 0.0;
       if (r != 0.0) {
-        c = x / r;
-        s = -z / r;
+        const double inv = 1.0 / r;
+        c = x * inv;
+        s = -z * inv;
       }
       if (k > lo) e[k - 1] = r;
       const double a0 = d[k], b0 = e[k], d1 = d[k + 1];
