@@ -57,6 +57,59 @@ def time_products(sb, ctx, psi, y, prec, n):
     return 1e3 * ms / max(k, 1)
 
 
+def time_products_graph(sb, ctx, psi, y, prec, n=200, reps=5):
+    """Median over reps of (replay time / n) of a hipGraph holding n
+    back-to-back products (captured through torch on a side stream; the
+    library is pointed at that stream during capture)."""
+    import torch
+    sb.set_prec(prec)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(5):            # warm-up outside capture, same stream
+            ctx.set_stream(side)
+            sb.hpsi(psi, y)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        ctx.set_stream(side)
+        for _ in range(n):
+            sb.hpsi(psi, y)
+    ctx.set_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(1e3 * a.elapsed_time(b) / n)
+    del g
+    times.sort()
+    return times[len(times) // 2]
+
+
+def sustained_fp32_gemm(n=8192, reps=5):
+    """FP32 TFLOP/s of a large square library GEMM (no TF32), for context."""
+    import torch
+    torch.backends.cuda.matmul.allow_tf32 = False
+    a = torch.randn(n, n, device="cuda", dtype=torch.float32)
+    b = torch.randn(n, n, device="cuda", dtype=torch.float32)
+    for _ in range(2):
+        torch.matmul(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.matmul(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * n ** 3 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12
+
+
 def kernel_only(sb, ctx, psi, flops, n):
     import torch
     y = torch.empty_like(psi)
@@ -202,6 +255,13 @@ def main():
     y = torch.empty_like(psi0)
     us = {p: time_products(sb, ctx, psi0, y, p, 200 if p != "fp64_plain" else 20)
           for p in ("fp32", "fp64", "fp64_plain")}
+    try:
+        us_graph = {p: time_products_graph(sb, ctx, psi0, y, p) for p in ("fp32", "bf16x3", "fp64")}
+    except Exception as e:   # report, do not fail the run
+        log(f"[bench] graph timing unavailable: {e}")
+        ctx.set_stream(torch.cuda.current_stream())
+        us_graph = {}
+    gemm_peak = sustained_fp32_gemm()
     sb.set_prec("fp64")
     r64 = sb.lanczos(psi0, max_iter=4000, tol=1e-8)
     sb.set_prec("fp32")
@@ -224,6 +284,10 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 5),
                      "traffic": traffic_per_launch()},
         "product_us": {k: round(v, 3) for k, v in us.items()},
+        "product_us_graph_median": {k: round(v, 3) for k, v in us_graph.items()},
+        "product_tflops_graph": {k: round(F / (v * 1e-6) / 1e12, 3) for k, v in us_graph.items()},
+        "sustained_fp32_library_gemm_tflops": round(gemm_peak, 2),
+        "lanczos_step_us": round(1e6 * parts["lanczos"] / args.steps / max(r["iters"], 1), 2),
         "speedup_fp32_vs_fp64_plain": round(us["fp64_plain"] / us["fp32"], 3),
         "speedup_fp32_vs_fp64_fused": round(us["fp64"] / us["fp32"], 3),
         "fp64_fused_tflops": round(F / (us["fp64"] * 1e-6) / 1e12, 4),

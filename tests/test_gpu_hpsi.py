@@ -193,3 +193,35 @@ def test_kernel_variants_identical_and_autotune(ctx, name, m, prec):
     assert np.linalg.norm(y - OS.hpsi_blocks(desc, psi)) <= TOL[prec] * _scale(desc, psi)
     with pytest.raises(Exception):
         sb.set_variant(7)
+
+
+def test_product_in_captured_graph(ctx):
+    """Products captured in a hipGraph (through torch) replay to the eager
+    result, several times, with eager work and synchronisation between."""
+    import torch
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("hubbard_L64_U4_m512", m=96, seed=7)
+    sb = Superblock(desc, prec="fp32", ctx=ctx)
+    psi = _dev(seeded_vector(sb.D, 61))
+    ref = _host(sb.hpsi(psi))
+    y = torch.empty_like(psi)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ctx.set_stream(side)
+        sb.hpsi(psi, y)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    try:
+        with torch.cuda.graph(g, stream=side):
+            ctx.set_stream(side)
+            sb.hpsi(psi, y)
+    finally:
+        ctx.set_stream(torch.cuda.current_stream())
+    for rep in range(4):
+        y.fill_(float("nan"))
+        sb.hpsi(psi, torch.empty_like(psi))     # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(_host(y), ref), rep
