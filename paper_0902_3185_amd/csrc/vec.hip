@@ -136,31 +136,29 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 
 // ---------------------------------------------------------------------------
 // One CGS2 step of the Lanczos recursion in bandwidth-shaped launches:
-//   dot     partial sums of V^T w   grid (element chunks) x (groups of kDotG vectors)
+//   dot     partial sums of V^T w
 //   reduce  h1 = sum of the partials, one wave per basis vector
-//   axpy    w -= V h1               grid (element chunks), all basis vectors per thread
-//   dot, reduce  h2 = V^T w
+//   axpy+dot  w -= V h1, then partial sums of V^T w for the updated w
+//   reduce  h2
 //   axpy    w -= V h2 and partial sums of ||w||^2
 //   finish  (alpha, beta) and v_next = w / beta
-// Partial sums are added in a fixed order by the next launch, so results are
-// repeatable; the kernel boundary makes them visible across the chip without
-// any cache maintenance inside the kernels.
+// Every pass gives each thread one element of w (256 per block, a grid of
+// ceil(n / 256) blocks) and walks the basis vectors in batches whose loads
+// are all issued before the first use, so a wave keeps a batch of basis
+// elements in flight instead of one memory latency per vector.  Partial sums
+// are added in a fixed order by the next launch, so results are repeatable;
+// the kernel boundary makes them visible across the chip without any cache
+// maintenance inside the kernels.
 // ---------------------------------------------------------------------------
 constexpr int kLzThreads = 256;
-constexpr int kDotPer = 4;                       // elements per thread (dot)
-constexpr int kDotSpan = kLzThreads * kDotPer;   // elements per block (dot)
-constexpr int kDotG = 8;                         // basis vectors per block (dot)
-constexpr int kAxPer = 2;                        // elements per thread (axpy)
-constexpr int kAxSpan = kLzThreads * kAxPer;     // elements per block (axpy)
-
-int dot_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kDotSpan - 1) / kDotSpan); }
-int axpy_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kAxSpan - 1) / kAxSpan); }
-
+constexpr int kBatch = 32;        // basis vectors per batch of loads
+constexpr int kTailBatch = 8;     // batch for the last nv % kBatch vectors
 constexpr int kFusedMaxNv = 64;   // basis size up to which axpy and dot share a pass
 
+int lz_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kLzThreads - 1) / kLzThreads); }
+
 size_t lz_partial_size(int64_t n, int nv) {
-  const size_t fused = (size_t)std::min(nv, kFusedMaxNv) * (size_t)((n + kLzThreads - 1) / kLzThreads);
-  return std::max({(size_t)nv * dot_blocks(n), (size_t)axpy_blocks(n), fused});
+  return (size_t)std::max(nv, 1) * (size_t)lz_blocks(n);
 }
 
 __device__ inline double wave_sum(double v) {
@@ -170,67 +168,106 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Sum of row[0..cnt) by one wave: lane l adds l, l+64, ... in order, then a
-// fixed butterfly.  Every lane returns the total.
-__device__ inline double wave_row_sum(const double* row, int cnt) {
+// fixed butterfly.  Every lane returns the total.  The loads of a batch of
+// kRowBatch values per lane are all issued before the first add, so a row of
+// up to 64 * kRowBatch partials costs one memory latency rather than one per
+// value (the partials were written by the previous launch and are read from
+// another XCD's cache or from memory).
+constexpr int kRowBatch = 16;
+__device__ inline double wave_row_sum(const double* __restrict__ row, int cnt) {
   const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int b = lane; b < cnt; b += 64) s += row[b];
+  for (int b0 = 0; b0 < cnt; b0 += 64 * kRowBatch) {
+    double t[kRowBatch];
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) {
+      const int b = b0 + lane + 64 * u;
+      t[u] = b < cnt ? row[b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kRowBatch; ++u) s += t[u];
+  }
   return wave_sum(s);
 }
 
-// partial[(g0 + g) * gridDim.x + blockIdx.x] = block part of <V_{g0+g}, w>,
-// g < kDotG; blockIdx.y selects g0.
+// Reduce-scatter of kB per-lane values over a wave: at the step of width H a
+// lane sends half of its values to the lane H away and keeps (and adds) the
+// other half, so after log2(kB) steps lane l holds the sum over its group of
+// kB lanes of p[l % kB]; the 64 / kB groups are then added by a butterfly.
+// kB - 1 + log2(64 / kB) exchanges instead of 6 kB.  Every lane l returns
+// the wave's sum for value l % kB.
+template <int H, int kB>
+__device__ __forceinline__ void rs_step(double (&p)[kB], int lane) {
+  const bool upper = (lane & H) != 0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double send = upper ? p[j] : p[j + H];
+    const double keep = upper ? p[j + H] : p[j];
+    p[j] = keep + __shfl_xor(send, H, 64);
+  }
+}
+template <int kB>
+__device__ __forceinline__ double wave_reduce_scatter(double (&p)[kB]) {
+  static_assert(kB == 8 || kB == 16 || kB == 32 || kB == 64, "batch of 8, 16, 32 or 64 values");
+  const int lane = threadIdx.x & 63;
+  if constexpr (kB >= 64) rs_step<32>(p, lane);
+  if constexpr (kB >= 32) rs_step<16>(p, lane);
+  if constexpr (kB >= 16) rs_step<8>(p, lane);
+  rs_step<4>(p, lane);
+  rs_step<2>(p, lane);
+  rs_step<1>(p, lane);
+  double t = p[0];
+#pragma unroll
+  for (int off = kB; off < 64; off <<= 1) t += __shfl_xor(t, off, 64);
+  return t;
+}
+
+// Block sums of kB per-thread values of one batch of basis vectors [i0,
+// i0 + nb) into partial[(i0 + k) * gridDim.x + blockIdx.x].  sh is double
+// buffered by batch parity, so one barrier per batch suffices.
+template <int kB>
+__device__ __forceinline__ void block_batch_partials(double (&p)[kB], double (*sh)[kLzThreads / 64][kBatch],
+                                                     int parity, int i0, int nb,
+                                                     double* __restrict__ partial) {
+  const double t = wave_reduce_scatter<kB>(p);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane < kB) sh[parity][wave][lane] = t;
+  __syncthreads();
+  if (threadIdx.x < nb) {
+    const int k = threadIdx.x;
+    partial[(int64_t)(i0 + k) * gridDim.x + blockIdx.x] =
+        ((sh[parity][0][k] + sh[parity][1][k]) + sh[parity][2][k]) + sh[parity][3][k];
+  }
+}
+
+// partial[i * gridDim.x + blockIdx.x] = the block's part of <V_i, w>, i < nv.
 __global__ __launch_bounds__(kLzThreads) void lz_dot(const double* __restrict__ V, int64_t ldv,
                                                      int nv, const double* __restrict__ w,
                                                      int64_t n, double* __restrict__ partial) {
-  __shared__ double sh[kLzThreads / 64][kDotG];
-  const int nbx = gridDim.x;
-  const int g0 = blockIdx.y * kDotG;
-  const int ng = min(kDotG, nv - g0);
-  const int64_t start = (int64_t)blockIdx.x * kDotSpan;
-  const int64_t base = start + threadIdx.x;
-  const bool full = start + kDotSpan <= n;
-  double x[kDotPer];
-  double s[kDotG];
+  __shared__ double sh[2][kLzThreads / 64][kBatch];
+  const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
+  const bool ok = e < n;
+  const double* Vb = V + (ok ? e : 0);   // in-range address for the tail block
+  const double x = ok ? w[e] : 0.0;
+  int i0 = 0, parity = 0;
+#pragma unroll 1
+  for (; i0 + kBatch <= nv; i0 += kBatch, parity ^= 1) {
+    double p[kBatch];
 #pragma unroll
-  for (int q = 0; q < kDotPer; ++q) {
-    const int64_t i = base + (int64_t)q * kLzThreads;
-    x[q] = (full || i < n) ? w[i] : 0.0;
+    for (int b = 0; b < kBatch; ++b) p[b] = Vb[(int64_t)(i0 + b) * ldv];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) p[b] = ok ? p[b] * x : 0.0;
+    block_batch_partials<kBatch>(p, sh, parity, i0, kBatch, partial);
   }
-  if (ng == kDotG && full) {
+#pragma unroll 1
+  for (; i0 < nv; i0 += kTailBatch, parity ^= 1) {
+    const int nb = min(kTailBatch, nv - i0);
+    double p[kTailBatch];
 #pragma unroll
-    for (int g = 0; g < kDotG; ++g) {
-      const double* Vg = V + (int64_t)(g0 + g) * ldv + base;
-      double a = 0.0;
+    for (int b = 0; b < kTailBatch; ++b) p[b] = Vb[(int64_t)(i0 + (b < nb ? b : 0)) * ldv];
 #pragma unroll
-      for (int q = 0; q < kDotPer; ++q) a += Vg[(int64_t)q * kLzThreads] * x[q];
-      s[g] = a;
-    }
-  } else {
-#pragma unroll
-    for (int g = 0; g < kDotG; ++g) {
-      double a = 0.0;
-      if (g < ng) {
-        const double* Vg = V + (int64_t)(g0 + g) * ldv;
-#pragma unroll
-        for (int q = 0; q < kDotPer; ++q) {
-          const int64_t i = base + (int64_t)q * kLzThreads;
-          if (i < n) a += Vg[i] * x[q];
-        }
-      }
-      s[g] = a;
-    }
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int g = 0; g < kDotG; ++g) {
-    const double t = wave_sum(s[g]);
-    if (lane == 0) sh[wave][g] = t;
-  }
-  __syncthreads();
-  if (threadIdx.x < ng) {
-    const int g = threadIdx.x;
-    partial[(int64_t)(g0 + g) * nbx + blockIdx.x] = ((sh[0][g] + sh[1][g]) + sh[2][g]) + sh[3][g];
+    for (int b = 0; b < kTailBatch; ++b) p[b] = (ok && b < nb) ? p[b] * x : 0.0;
+    block_batch_partials<kTailBatch>(p, sh, parity, i0, nb, partial);
   }
 }
 
@@ -241,6 +278,31 @@ __global__ __launch_bounds__(64) void lz_reduce(const double* __restrict__ parti
   if (threadIdx.x == 0) h[blockIdx.x] = t;
 }
 
+// x -= sum_{i<nv} h[i] V_i[e] for this thread's element (Vb = V + e).
+__device__ __forceinline__ double axpy_walk(double x, const double* __restrict__ Vb, int64_t ldv,
+                                            int nv, const double* __restrict__ h) {
+  int i0 = 0;
+#pragma unroll 1
+  for (; i0 + kBatch <= nv; i0 += kBatch) {
+    double t[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) t[b] = Vb[(int64_t)(i0 + b) * ldv];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) x -= h[i0 + b] * t[b];
+  }
+#pragma unroll 1
+  for (; i0 < nv; i0 += kTailBatch) {
+    const int nb = min(kTailBatch, nv - i0);
+    double t[kTailBatch];
+#pragma unroll
+    for (int b = 0; b < kTailBatch; ++b) t[b] = Vb[(int64_t)(i0 + (b < nb ? b : 0)) * ldv];
+#pragma unroll
+    for (int b = 0; b < kTailBatch; ++b)
+      if (b < nb) x -= h[i0 + b] * t[b];
+  }
+  return x;
+}
+
 // w -= sum_{i<nv} h[i] V_i.  With kNorm, also partial[blockIdx.x] = the
 // block's part of ||w||^2.
 template <bool kNorm>
@@ -249,48 +311,15 @@ __global__ __launch_bounds__(kLzThreads) void lz_axpy(double* __restrict__ w,
                                                       int nv, int64_t n,
                                                       const double* __restrict__ h,
                                                       double* __restrict__ partial) {
-  const int64_t start = (int64_t)blockIdx.x * kAxSpan;
-  const int64_t base = start + threadIdx.x;
-  const bool full = start + kAxSpan <= n;
-  double x[kAxPer];
-#pragma unroll
-  for (int q = 0; q < kAxPer; ++q) {
-    const int64_t i = base + (int64_t)q * kLzThreads;
-    x[q] = (full || i < n) ? w[i] : 0.0;
-  }
-  if (full) {
-    const double* Vb = V + base;
-#pragma unroll 8
-    for (int i = 0; i < nv; ++i) {
-      const double hi = h[i];
-      const double* Vi = Vb + (int64_t)i * ldv;
-#pragma unroll
-      for (int q = 0; q < kAxPer; ++q) x[q] -= hi * Vi[(int64_t)q * kLzThreads];
-    }
-  } else {
-    for (int i = 0; i < nv; ++i) {
-      const double hi = h[i];
-      const double* Vi = V + (int64_t)i * ldv;
-#pragma unroll
-      for (int q = 0; q < kAxPer; ++q) {
-        const int64_t e = base + (int64_t)q * kLzThreads;
-        if (e < n) x[q] -= hi * Vi[e];
-      }
-    }
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int q = 0; q < kAxPer; ++q) {
-    const int64_t e = base + (int64_t)q * kLzThreads;
-    if (full || e < n) {
-      w[e] = x[q];
-      s += x[q] * x[q];
-    }
-  }
+  const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
+  const bool ok = e < n;
+  double x = ok ? w[e] : 0.0;
+  x = axpy_walk(x, V + (ok ? e : 0), ldv, nv, h);
+  if (ok) w[e] = x;
   if (!kNorm) return;
   __shared__ double sh[kLzThreads / 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  s = wave_sum(s);
+  const double s = wave_sum(ok ? x * x : 0.0);
   if (lane == 0) sh[wave] = s;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
@@ -325,23 +354,18 @@ __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
 // w -= sum_{i<nv} h[i] V_i, then partial[i * gridDim.x + blockIdx.x] = the
 // block's part of <V_i, w> for the updated w: one pass over the basis for
 // both (the first CGS pass's update and the second pass's products).  Each
-// thread keeps its element of every basis vector in registers, so kNv (32 or
-// 64) bounds nv; one element per thread, 256 per block.  The kNv per-lane
-// products are summed over a wave by a reduce-scatter butterfly: at every
-// step a lane sends half of its values to its partner and keeps the other
-// half, so after the last step lane l holds the wave's sum for vector
-// l mod kNv (kNv - 1 exchanges instead of 6 kNv).
+// thread keeps its element of every basis vector in registers, so kNv (8,
+// 16, 32 or 64, the smallest that holds nv) bounds nv.
 template <int kNv>
 __global__ __launch_bounds__(kLzThreads) void lz_axpy_dot(double* __restrict__ w,
                                                           const double* __restrict__ V,
                                                           int64_t ldv, int nv, int64_t n,
                                                           const double* __restrict__ h,
                                                           double* __restrict__ partial) {
-  static_assert(kNv == 32 || kNv == 64, "the butterfly covers 32 or 64 vectors");
   __shared__ double sh[kLzThreads / 64][kNv];
   const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
   const bool ok = e < n;
-  const int64_t ec = ok ? e : n - 1;   // in-range address for the tail block
+  const int64_t ec = ok ? e : 0;   // in-range address for the tail block
   double v[kNv];
 #pragma unroll
   for (int i = 0; i < kNv; ++i) v[i] = V[(int64_t)(i < nv ? i : 0) * ldv + ec];
@@ -351,24 +375,9 @@ __global__ __launch_bounds__(kLzThreads) void lz_axpy_dot(double* __restrict__ w
     if (i < nv) x -= h[i] * v[i];
   if (ok) w[e] = x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double p[kNv];
 #pragma unroll
-  for (int i = 0; i < kNv; ++i) p[i] = (ok && i < nv) ? v[i] * x : 0.0;
-  // reduce-scatter over offsets kNv/2, ..., 1: values [0, c) -> [0, c/2)
-#pragma unroll
-  for (int c = kNv; c > 1; c >>= 1) {
-    const int half = c >> 1;
-    const bool upper = (lane & half) != 0;
-#pragma unroll
-    for (int j = 0; j < half; ++j) {
-      const double send = upper ? p[j] : p[j + half];
-      const double keep = upper ? p[j + half] : p[j];
-      p[j] = keep + __shfl_xor(send, half, 64);
-    }
-  }
-  // lane l now holds the sum over its group of kNv lanes for vector l % kNv
-  double t = p[0];
-  if (kNv == 32) t += __shfl_xor(t, 32, 64);
+  for (int i = 0; i < kNv; ++i) v[i] = (ok && i < nv) ? v[i] * x : 0.0;
+  const double t = wave_reduce_scatter<kNv>(v);
   if (lane < kNv) sh[wave][lane] = t;
   __syncthreads();
   if (threadIdx.x < nv)
@@ -386,28 +395,29 @@ void launch_axpy_dot(double* w, const double* V, int64_t ldv, int nv, int64_t n,
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
                           hipStream_t stream) {
-  const dim3 gd(dot_blocks(n), (nv + kDotG - 1) / kDotG);
-  const int na = axpy_blocks(n);
-  hipLaunchKernelGGL(lz_dot, gd, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
-  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, (int)gd.x, h1);
+  const int nb = lz_blocks(n);
+  hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h1);
   if (nv <= kFusedMaxNv) {
     // first update and second products in one pass over the basis
-    const int nb = (int)((n + kLzThreads - 1) / kLzThreads);
-    if (nv <= 32)
+    if (nv <= 8)
+      launch_axpy_dot<8>(w, V, ldv, nv, n, h1, partial, nb, stream);
+    else if (nv <= 16)
+      launch_axpy_dot<16>(w, V, ldv, nv, n, h1, partial, nb, stream);
+    else if (nv <= 32)
       launch_axpy_dot<32>(w, V, ldv, nv, n, h1, partial, nb, stream);
     else
       launch_axpy_dot<64>(w, V, ldv, nv, n, h1, partial, nb, stream);
-    hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
   } else {
-    hipLaunchKernelGGL(lz_axpy<false>, dim3(na), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
+    hipLaunchKernelGGL(lz_axpy<false>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
                        partial);
-    hipLaunchKernelGGL(lz_dot, gd, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
-    hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, (int)gd.x, h2);
+    hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
   }
-  hipLaunchKernelGGL(lz_axpy<true>, dim3(na), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h2,
+  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
+  hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h2,
                      partial);
   const unsigned nfin = vnext ? (unsigned)((n + kThreads - 1) / kThreads) : 1u;
-  hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, na, h1, h2,
+  hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, nb, h1, h2,
                      nv - 1, ab, n);
   return hipGetLastError();
 }
