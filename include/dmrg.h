@@ -138,15 +138,21 @@ void dmrg_ctx_destroy(dmrg_ctx ctx);
 /* Set the stream later work is queued on (e.g. the caller's current stream). */
 dmrg_status dmrg_ctx_set_stream(dmrg_ctx ctx, void* hip_stream);
 
-/* Timing of the product kernels: when enabled, every product launch the
- * library makes on this context (dmrg_hpsi and the products inside
- * dmrg_lanczos_ground) is bracketed by HIP events on the context's stream.
- * dmrg_ctx_timing synchronises on the last event and returns the summed
- * event time (ms) and the number of launches of precision `prec`
- * (a dmrg_prec value); reset != 0 then forgets all recorded launches.      */
-dmrg_status dmrg_ctx_set_timing(dmrg_ctx ctx, int32_t enable);
+/* Timing of the product kernels.  dmrg_ctx_set_timing(ctx, every): with
+ * every >= 1, every every-th product launch the library makes on this
+ * context (dmrg_hpsi and the products inside dmrg_lanczos_ground, counted
+ * in launch order) is bracketed by HIP events on the context's stream, and
+ * all product launches are counted; every = 0 turns both off.  A stride
+ * above 1 keeps the events' own cost out of the timed work while the
+ * sampled launches still give the average kernel time.
+ * dmrg_ctx_timing synchronises on the last event and returns, for
+ * precision `prec` (a dmrg_prec value), the summed event time (ms) and the
+ * number of timed launches, and in *products (if not null) the number of
+ * all launches made while timing was on; reset != 0 then forgets all of
+ * them.  Negative `every` is DMRG_E_ARG.                                    */
+dmrg_status dmrg_ctx_set_timing(dmrg_ctx ctx, int32_t every);
 dmrg_status dmrg_ctx_timing(dmrg_ctx ctx, int32_t prec, double* ms_total, int64_t* launches,
-                            int32_t reset);
+                            int64_t* products, int32_t reset);
 
 /* Message describing the last failure on this host thread ("" if none).   */
 const char* dmrg_last_error(void);

@@ -59,7 +59,8 @@ _SIGS = {
     "dmrg_ctx_destroy": (None, [_P]),
     "dmrg_ctx_set_stream": (C.c_int, [_P, _P]),
     "dmrg_ctx_set_timing": (C.c_int, [_P, C.c_int32]),
-    "dmrg_ctx_timing": (C.c_int, [_P, C.c_int32, _D, C.POINTER(C.c_int64), C.c_int32]),
+    "dmrg_ctx_timing": (C.c_int, [_P, C.c_int32, _D, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.c_int32]),
     "dmrg_last_error": (C.c_char_p, []),
     "dmrg_version": (C.c_char_p, []),
     "dmrg_build_superblock": (C.c_int, [_P, C.POINTER(dmrg_basis), C.POINTER(dmrg_basis), C.c_int64,

@@ -116,7 +116,9 @@ struct dmrg_ctx_s {
   DevBuf tr_images, tr_tmp;   // basis-change scratch
   // optional per-launch timing of the product kernels (HIP events on `stream`)
   hipEvent_t chk[2] = {nullptr, nullptr};   // Lanczos check copies
-  bool timing = false;
+  int timing = 0;          // time every timing-th product launch (0: off)
+  int64_t tick = 0;        // product launches since timing was set
+  int64_t products[4] = {0, 0, 0, 0};   // launches per precision while timing was on
   struct Mark {
     hipEvent_t a, b;
     int prec;
@@ -228,7 +230,10 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
 dmrg_status run_product(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
                         double alpha, double beta) {
   dmrg_ctx c = sb->ctx;
-  if (!c->timing) return run_product_inner(sb, st, prec, psi, y, alpha, beta, nullptr, nullptr);
+  if (c->timing <= 0) return run_product_inner(sb, st, prec, psi, y, alpha, beta, nullptr, nullptr);
+  if ((int)prec >= 0 && (int)prec < 4) ++c->products[(int)prec];
+  if (c->tick++ % c->timing != 0)
+    return run_product_inner(sb, st, prec, psi, y, alpha, beta, nullptr, nullptr);
   dmrg_ctx_s::Mark mk;
   HIP_TRY(take_event(c, &mk.a));
   HIP_TRY(take_event(c, &mk.b));
@@ -351,14 +356,16 @@ void dmrg_ctx_destroy(dmrg_ctx ctx) {
   delete ctx;
 }
 
-dmrg_status dmrg_ctx_set_timing(dmrg_ctx ctx, int32_t enable) {
+dmrg_status dmrg_ctx_set_timing(dmrg_ctx ctx, int32_t every) {
   if (!ctx) return fail(DMRG_E_ARG, "null context");
-  ctx->timing = enable != 0;
+  if (every < 0) return fail(DMRG_E_ARG, "timing stride must be >= 0");
+  ctx->timing = every;
+  ctx->tick = 0;
   return DMRG_OK;
 }
 
 dmrg_status dmrg_ctx_timing(dmrg_ctx ctx, int32_t prec, double* ms_total, int64_t* launches,
-                            int32_t reset) {
+                            int64_t* products, int32_t reset) {
   if (!ctx || !ms_total || !launches) return fail(DMRG_E_ARG, "null argument");
   DeviceGuard g(ctx->device);
   double tot = 0.0;
@@ -373,12 +380,14 @@ dmrg_status dmrg_ctx_timing(dmrg_ctx ctx, int32_t prec, double* ms_total, int64_
   }
   *ms_total = tot;
   *launches = n;
+  if (products) *products = (prec >= 0 && prec < 4) ? ctx->products[prec] : 0;
   if (reset) {
     for (auto& mk : ctx->marks) {
       ctx->spare.push_back(mk.a);
       ctx->spare.push_back(mk.b);
     }
     ctx->marks.clear();
+    for (auto& c : ctx->products) c = 0;
   }
   return DMRG_OK;
 }
@@ -850,9 +859,11 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     int32_t sec;
   };
   std::vector<Ent> ents;
-  std::vector<std::vector<double>> vecs(nsec), vals(nsec);
+  std::vector<SymEig> eig(nsec);
   const double floor_ = 1e-13, rel_tie = 1e-6;
-  // Sectors are independent: solve them on host threads, largest first.
+  // Sectors are independent: all eigenvalues (and the data for the
+  // eigenvectors) on host threads, largest sector first; the eigenvectors
+  // are formed below for the kept states only.
   std::vector<int> work(nsec);
   for (int i = 0; i < nsec; ++i) work[i] = i;
   std::stable_sort(work.begin(), work.end(), [&](int x, int y) { return ds[x] > ds[y]; });
@@ -866,7 +877,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
       if (w >= nsec) return;
       const int sec = work[w];
       const int n = ds[sec];
-      std::vector<double> A((size_t)n * n, 0.0), wv(n, 0.0);
+      std::vector<double> A((size_t)n * n, 0.0);
       if (rho_off[sec] >= 0)
         std::copy(rho.begin() + rho_off[sec], rho.begin() + rho_off[sec] + (size_t)n * n, A.begin());
       for (int i = 0; i < n; ++i)   // symmetrise the computed block
@@ -874,7 +885,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
           const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
           A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
         }
-      if (!sym_eigen(n, A.data(), wv.data(), n >= 128 ? inner : 1)) {
+      if (!sym_eigen_reduce(n, A.data(), eig[sec], n >= 128 ? inner : 1)) {
         if (bad.fetch_add(1) == 0) {
           int nonfinite = 0;
           double amax = 0.0;
@@ -888,17 +899,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
              << " non-finite entries, max |rho| " << amax << ")";
           bad_what = os.str();
         }
-        continue;
       }
-      // decreasing order within the sector
-      std::vector<double> V((size_t)n * n), L(n);
-      for (int c = 0; c < n; ++c) {
-        const int src = n - 1 - c;
-        for (int r = 0; r < n; ++r) V[(size_t)r * n + c] = A[(size_t)r * n + src];
-        L[c] = wv[src];
-      }
-      vecs[sec].swap(V);
-      vals[sec].swap(L);
     }
   };
   {
@@ -910,9 +911,11 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   }
   if (bad.load() > 0)
     return fail(DMRG_E_NOCONV, "density-matrix eigen-solve did not converge in " + bad_what);
+  // within a sector, position c in decreasing order is ascending index n - 1 - c
+  auto val = [&](int sec, int c) { return eig[sec].w[ds[sec] - 1 - c]; };
   for (int sec = 0; sec < nsec; ++sec)
     for (int c = 0; c < ds[sec]; ++c) {
-      const double raw = vals[sec][c];
+      const double raw = val(sec, c);
       ents.push_back({raw >= floor_ ? raw : 0.0, raw, qs[sec], c, sec});
     }
   const int ntot = (int)ents.size();
@@ -959,17 +962,39 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   sb->tr_kps.assign(nsec, 0);
   sb->tr_W.assign(nsec, std::vector<double>());
   sb->tr_Wp.assign(nsec, nullptr);
+  // eigenvectors of the kept states: work items of up to four vectors of one
+  // sector, shared by the host threads
+  std::vector<std::vector<int>> cols(nsec);
+  std::vector<std::pair<int, int>> items;
   for (int sec = 0; sec < nsec; ++sec) {
     std::vector<int>& idx = per[sec];
     std::sort(idx.begin(), idx.end());
     const int n = ds[sec], k = (int)idx.size();
     sb->tr_kps[sec] = k;
     if (k == 0) continue;
-    std::vector<double>& W = sb->tr_W[sec];
-    W.assign((size_t)n * k, 0.0);
-    for (int r = 0; r < n; ++r)
-      for (int c = 0; c < k; ++c) W[(size_t)r * k + c] = vecs[sec][(size_t)r * n + idx[c]];
-    sb->tr_Wp[sec] = W.data();
+    sb->tr_W[sec].assign((size_t)n * k, 0.0);
+    sb->tr_Wp[sec] = sb->tr_W[sec].data();
+    cols[sec].resize(k);
+    for (int c = 0; c < k; ++c) cols[sec][c] = n - 1 - idx[c];
+    for (int q0 = 0; q0 < k; q0 += 4) items.push_back({sec, q0});
+  }
+  {
+    std::atomic<int> it(0);
+    auto vecs = [&]() {
+      for (;;) {
+        const int w = it.fetch_add(1);
+        if (w >= (int)items.size()) return;
+        const int sec = items[w].first, q0 = items[w].second;
+        const int k = (int)cols[sec].size();
+        sym_eigen_vectors(eig[sec], std::min(4, k - q0), cols[sec].data() + q0,
+                          sb->tr_W[sec].data() + q0, k, 1);
+      }
+    };
+    const int nthr = std::max(1, std::min(hw, (int)items.size()));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthr; ++t) pool.emplace_back(vecs);
+    vecs();
+    for (auto& th : pool) th.join();
   }
   out->trunc_err = eps;
   out->kept = keep;

@@ -9,6 +9,9 @@
 //   Sec. 8.3).  The QR sweeps run on the tridiagonal alone and record their
 //   rotations; applying those rotations and the Householder reflectors to
 //   the eigenvector matrix, the O(n^3) part, is split over host threads.
+//   The reflectors are applied per requested eigenvector, so a caller that
+//   keeps only some eigenvectors (the density-matrix truncation) pays for
+//   those only.
 #include "eigen.h"
 
 #include <algorithm>
@@ -150,13 +153,41 @@ inline double safe_hypot(double x, double z) {
 
 }  // namespace
 
-bool sym_eigen(int n, double* A, double* w, int nthreads) {
+namespace {
+
+// sum_{i in [lo, hi)} a[i] * b[i] in four interleaved partial sums (lane u
+// takes i = lo + u mod 4), added as (s0 + s1) + (s2 + s3) + tail: a fixed
+// order that the compiler keeps in one vector register.
+inline double dot4(const double* a, const double* b, int lo, int hi) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = lo;
+  for (; i + 4 <= hi; i += 4) {
+    s0 += a[i] * b[i];
+    s1 += a[i + 1] * b[i + 1];
+    s2 += a[i + 2] * b[i + 2];
+    s3 += a[i + 3] * b[i + 3];
+  }
+  double t = 0.0;
+  for (; i < hi; ++i) t += a[i] * b[i];
+  return ((s0 + s1) + (s2 + s3)) + t;
+}
+
+}  // namespace
+
+bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
+  out.n = n;
+  out.w.assign(n, 0.0);
+  out.row.assign(n, 0);
+  out.R.assign((size_t)n * n, 0.0);
+  out.beta.assign(n, 0.0);
   if (n <= 0) return true;
   nthreads = std::max(1, std::min(nthreads, (n + 31) / 32));
+  std::vector<double> A(Ain, Ain + (size_t)n * n);
+  std::vector<double>& R = out.R;
+  std::vector<double>& betas = out.beta;
   // 1. Householder reduction to tridiagonal form on the lower triangle.
   //    Reflector k is H_k = I - beta_k v_k v_k^T with v_k[0..k] = 0; its
   //    nonzero part v_k[k+1..n) is kept in R[k][k+1..n).
-  std::vector<double> R((size_t)n * n, 0.0), betas(n, 0.0);
   std::vector<double> v(n), p(n);
   for (int k = 0; k + 2 < n; ++k) {
     // The column is scaled by its largest entry first: the reflector does
@@ -184,12 +215,8 @@ bool sym_eigen(int n, double* A, double* w, int nthreads) {
     for (int i = k + 1; i < n; ++i) {
       const double* ai = &A[(size_t)i * n];
       const double vi = v[i];
-      double s = 0.0;
-      for (int j = k + 1; j < i; ++j) {
-        s += ai[j] * v[j];
-        p[j] += ai[j] * vi;
-      }
-      p[i] += s + ai[i] * vi;
+      for (int j = k + 1; j < i; ++j) p[j] += ai[j] * vi;
+      p[i] += dot4(ai, v.data(), k + 1, i) + ai[i] * vi;
     }
     double vtp = 0.0;
     for (int i = k + 1; i < n; ++i) {
@@ -287,13 +314,13 @@ bool sym_eigen(int n, double* A, double* w, int nthreads) {
   // 3. Z^T = (rotations) applied to the identity; the columns r of Z^T are
   //    independent, so threads take disjoint column ranges and every element
   //    sees the same operations in the same order for any thread count.
-  // 4. Eigenvectors V = H_0 H_1 ... H_{n-3} Z: column c of Z (row c of Z^T)
-  //    gets the reflectors applied last to first; columns are independent.
   // Rows of Z^T start on 64-byte boundaries with a stride of whole cache
   // lines, so the column ranges of different threads share no line.
   const int ld = (n + 7) / 8 * 8;
-  std::vector<double> zbuf((size_t)n * ld + 8, 0.0);
-  double* ZT = zbuf.data() + ((8 - (reinterpret_cast<uintptr_t>(zbuf.data()) / 8) % 8) % 8);
+  out.ld = ld;
+  out.zbuf.assign((size_t)n * ld + 8, 0.0);
+  out.zoff = (8 - (reinterpret_cast<uintptr_t>(out.zbuf.data()) / 8) % 8) % 8;
+  double* ZT = out.zbuf.data() + out.zoff;
   for (int i = 0; i < n; ++i) ZT[(size_t)i * ld + i] = 1.0;
   const size_t nrot = rk.size();
   // One thread sweeps the whole width; several threads take one-line strips
@@ -316,30 +343,68 @@ bool sym_eigen(int n, double* A, double* w, int nthreads) {
       }
     }
   });
-  parallel(nthreads, [&](int t) {
-    const int per = (n + nthreads - 1) / nthreads;
-    const int r0 = std::min(n, t * per), r1 = std::min(n, (t + 1) * per);
-    for (int row = r0; row < r1; ++row) {
-      double* z = &ZT[(size_t)row * ld];
-      for (int k = n - 3; k >= 0; --k) {
-        if (betas[k] == 0.0) continue;
-        const double* vk = &R[(size_t)k * n];
-        double s = 0.0;
-        for (int i = k + 1; i < n; ++i) s += vk[i] * z[i];
-        s *= betas[k];
-        for (int i = k + 1; i < n; ++i) z[i] -= s * vk[i];
-      }
-    }
-  });
-  // sort ascending; eigenvectors as columns of A
+  // ascending order of the eigenvalues; row[c] is the row of Z^T of w[c]
   std::vector<int> idx(n);
   std::iota(idx.begin(), idx.end(), 0);
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
   for (int c = 0; c < n; ++c) {
-    w[c] = d[idx[c]];
-    const double* q = &ZT[(size_t)idx[c] * ld];
-    for (int r = 0; r < n; ++r) A[(size_t)r * n + c] = q[r];
+    out.w[c] = d[idx[c]];
+    out.row[c] = idx[c];
   }
+  return true;
+}
+
+void sym_eigen_vectors(const SymEig& E, int k, const int* cols, double* out, int ldo,
+                       int nthreads) {
+  const int n = E.n;
+  if (n <= 0 || k <= 0) return;
+  nthreads = std::max(1, std::min(nthreads, (k + 7) / 8));
+  const double* ZT = E.zbuf.data() + E.zoff;
+  // 4. Eigenvector of w[c] = H_0 H_1 ... H_{n-3} z, z = row row[c] of Z^T:
+  //    the reflectors are applied last to first.  Vectors are independent;
+  //    four at a time share each reflector's loads, and threads take
+  //    disjoint groups of four.
+  const int ngroup = (k + 3) / 4;
+  parallel(nthreads, [&](int t) {
+    const int per = (ngroup + nthreads - 1) / nthreads;
+    const int g0 = std::min(ngroup, t * per), g1 = std::min(ngroup, (t + 1) * per);
+    std::vector<double> zb((size_t)4 * n);
+    for (int g = g0; g < g1; ++g) {
+      const int q0 = 4 * g, nq = std::min(4, k - q0);
+      double* z[4];
+      for (int q = 0; q < 4; ++q) {
+        z[q] = zb.data() + (size_t)q * n;
+        const double* src = &ZT[(size_t)E.row[cols[q0 + std::min(q, nq - 1)]] * E.ld];
+        std::copy(src, src + n, z[q]);
+      }
+      for (int kk = n - 3; kk >= 0; --kk) {
+        const double b = E.beta[kk];
+        if (b == 0.0) continue;
+        const double* vk = &E.R[(size_t)kk * n];
+        double s[4];
+        for (int q = 0; q < 4; ++q) s[q] = b * dot4(vk, z[q], kk + 1, n);
+        for (int i = kk + 1; i < n; ++i) {
+          const double vi = vk[i];
+          z[0][i] -= s[0] * vi;
+          z[1][i] -= s[1] * vi;
+          z[2][i] -= s[2] * vi;
+          z[3][i] -= s[3] * vi;
+        }
+      }
+      for (int q = 0; q < nq; ++q)
+        for (int r = 0; r < n; ++r) out[(size_t)r * ldo + q0 + q] = z[q][r];
+    }
+  });
+}
+
+bool sym_eigen(int n, double* A, double* w, int nthreads) {
+  if (n <= 0) return true;
+  SymEig E;
+  if (!sym_eigen_reduce(n, A, E, nthreads)) return false;
+  std::vector<int> all(n);
+  std::iota(all.begin(), all.end(), 0);
+  for (int c = 0; c < n; ++c) w[c] = E.w[c];
+  sym_eigen_vectors(E, n, all.data(), A, n, nthreads);
   return true;
 }
 

@@ -42,14 +42,21 @@ class Context:
         self._stream = stream
         check(lib().dmrg_ctx_set_stream(self.handle, C.c_void_p(stream.cuda_stream)))
 
-    def set_timing(self, enable=True):
-        check(lib().dmrg_ctx_set_timing(self.handle, int(bool(enable))))
+    def set_timing(self, every=1):
+        """Time every `every`-th product launch with HIP events (0 or False:
+        off); all product launches are counted while it is on."""
+        check(lib().dmrg_ctx_set_timing(self.handle, int(every)))
 
-    def timing(self, prec, reset=True):
-        """(summed event ms, launches) of the product kernels of one precision."""
+    def timing(self, prec, reset=True, products=False):
+        """(summed event ms, timed launches) of the product kernels of one
+        precision; with products=True also the number of all launches."""
         ms = C.c_double()
         n = C.c_int64()
-        check(lib().dmrg_ctx_timing(self.handle, PREC[prec], C.byref(ms), C.byref(n), int(bool(reset))))
+        tot = C.c_int64()
+        check(lib().dmrg_ctx_timing(self.handle, PREC[prec], C.byref(ms), C.byref(n), C.byref(tot),
+                                    int(bool(reset))))
+        if products:
+            return ms.value, n.value, tot.value
         return ms.value, n.value
 
     def transform_blocks(self, blocks, O, W, out):

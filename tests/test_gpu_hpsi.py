@@ -225,3 +225,25 @@ def test_product_in_captured_graph(ctx):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(_host(y), ref), rep
+
+
+def test_sampled_product_timing(ctx):
+    """dmrg_ctx_set_timing(ctx, k): every k-th product launch is event-timed
+    and every launch is counted; the sampled launches give a positive time."""
+    import ctypes as C
+    from paper_0902_3185_amd import _lib
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("heisenberg_L16_m32", seed=0)
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    x = _dev(seeded_vector(sb.D, 1))
+    y = _dev(np.zeros(sb.D))
+    ctx.timing("fp64", reset=True)
+    ctx.set_timing(3)
+    for _ in range(10):
+        sb.hpsi(x, y)
+    ms, timed, total = ctx.timing("fp64", reset=True, products=True)
+    ctx.set_timing(0)
+    assert (timed, total) == (4, 10) and ms > 0.0
+    ms, timed, total = ctx.timing("fp64", reset=True, products=True)
+    assert (ms, timed, total) == (0.0, 0, 0)
+    assert _lib.STATUS[_lib.lib().dmrg_ctx_set_timing(ctx.handle, -1)] == "DMRG_E_ARG"
