@@ -698,6 +698,21 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
     int nv = 0;      // basis vectors that enter the Ritz vector of this cycle
     u.clear();
     // evaluates the check taken after step jc from h; true: the cycle stops
+    double ctol = tol;                   // this cycle's stopping residual
+    double est_prev = -1.0, est_last = -1.0;   // the last two evaluated estimates
+    // Gram-Schmidt against the basis runs twice in the first step of a cycle
+    // and once after it.  One pass leaves v_{j+1} orthogonal to the basis up
+    // to about eps * ||H v_j|| / beta_j; the start vector of a restarted
+    // cycle is close to an eigenvector (small beta_0), later steps have
+    // ||H v_j|| / beta_j = sqrt(alpha_j^2 + beta_{j-1}^2 + beta_j^2) / beta_j
+    // of order one.  Should that ratio exceed kOncePassMax at a check, the
+    // rest of the cycle runs both passes.  A basis that is not small against
+    // the dimension always runs both: the Krylov space may be exhausted (or
+    // confined to a small invariant subspace) within the cycle, and one pass
+    // would not leave the vanishing beta that ends the recursion there.
+    constexpr double kOncePassMax = 1e3;
+    constexpr int64_t kOncePassMinRatio = 32;   // D >= 32 * vectors per cycle
+    bool twice = D < kOncePassMinRatio * nvec;
     auto evaluate = [&](int jc, const double* h) {
       alphas.clear();
       betas.clear();
@@ -709,10 +724,16 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
         if (b <= 1e-13 * std::max(1.0, std::fabs(h[2 * m]))) break;
       }
       const int steps = (int)alphas.size();
+      for (int m = 1; m < steps && !twice; ++m) {
+        const double b = betas[m];
+        const double g = std::sqrt(alphas[m] * alphas[m] + betas[m - 1] * betas[m - 1] + b * b);
+        if (!(g <= kOncePassMax * b)) twice = true;
+      }
       if (jc == 0) {
         E = alphas[0];
         res = betas[0];
         beta0 = betas[0];
+        ctol = reduced ? std::max(tol, 1e-4 * beta0) : tol;
         if (res <= tol) {
           converged = true;
           nv = 1;
@@ -725,7 +746,10 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       nv = steps;
       const double bl = betas[steps - 1];
       const double est = bl * std::fabs(u[steps - 1]);
-      const double ctol = reduced ? std::max(tol, 1e-4 * beta0) : tol;
+      if (jc > 0) {
+        est_prev = est_last;
+        est_last = est;
+      }
       const bool breakdown = bl <= 1e-13 * std::max(1.0, std::fabs(theta)) || steps < jc + 1;
       return jc > 0 && (est <= ctol || breakdown);
     };
@@ -736,7 +760,7 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
       ++total;
       HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
-                             j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, s));
+                             j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, j == 0 || twice, s));
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
       HIP_TRY(hipMemcpyAsync(hbuf[nbuf], ab, 2 * (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -746,7 +770,13 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
         if (evaluate(pend, hbuf[pbuf])) break;
         pend = -1;
       }
-      if (j == 0 || last) {
+      // When the estimates' last rate of decrease says this check point
+      // will meet the cycle's tolerance, it is evaluated at once: one wait
+      // for the queue to drain instead of kCheck more steps that would be
+      // thrown away.
+      const bool likely = est_prev > 0.0 && est_last > 0.0 &&
+                          est_last * (est_last / est_prev) <= 4.0 * ctol;
+      if (j == 0 || last || likely) {
         HIP_TRY(hipEventSynchronize(ctx->chk[nbuf]));
         if (evaluate(j, hbuf[nbuf]) || last) break;
       } else {
@@ -1128,7 +1158,7 @@ dmrg_status dmrg_lanczos_tridiag(dmrg_sb sb, const double* v0_d, int32_t nsteps,
   for (int j = 0; j < nsteps; ++j) {
     if ((st = run_product(sb, sb->fwd, sb->prec, V + (size_t)j * D, w, 1.0, 0.0)) != DMRG_OK) return st;
     HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
-                           V + (size_t)(j + 1) * D, s));
+                           V + (size_t)(j + 1) * D, true, s));
   }
   std::vector<double> hs(2 * nsteps + 1);
   HIP_TRY(hipMemcpyAsync(hs.data(), ab, 2 * nsteps * sizeof(double), hipMemcpyDeviceToHost, s));

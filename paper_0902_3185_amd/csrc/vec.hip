@@ -135,12 +135,13 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 }
 
 // ---------------------------------------------------------------------------
-// One CGS2 step of the Lanczos recursion in bandwidth-shaped launches:
+// One step of the Lanczos recursion with classical Gram-Schmidt against the
+// whole basis, once or twice, in bandwidth-shaped launches:
 //   dot     partial sums of V^T w
 //   reduce  h1 = sum of the partials, one wave per basis vector
-//   axpy+dot  w -= V h1, then partial sums of V^T w for the updated w
-//   reduce  h2
-//   axpy    w -= V h2 and partial sums of ||w||^2
+//   (twice: axpy+dot  w -= V h1, then partial sums of V^T w for the
+//    updated w; reduce  h2)
+//   axpy    w -= V h (h2 or h1) and partial sums of ||w||^2
 //   finish  (alpha, beta) and v_next = w / beta
 // Every pass gives each thread one element of w (256 per block, a grid of
 // ceil(n / 256) blocks) and walks the basis vectors in batches whose loads
@@ -326,8 +327,8 @@ __global__ __launch_bounds__(kLzThreads) void lz_axpy(double* __restrict__ w,
 }
 
 // beta = sqrt(sum of partial[0..np)) (every block adds the same partials in
-// the same order); block 0 writes ab[0] = h1[j] + h2[j] and ab[1] = beta;
-// v_next = w / beta where v_next is given.
+// the same order); block 0 writes ab[0] = h1[j] (+ h2[j] when h2 is given)
+// and ab[1] = beta; v_next = w / beta where v_next is given.
 __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
                                                       const double* __restrict__ w,
                                                       const double* __restrict__ partial, int np,
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
   __syncthreads();
   const double b = beta;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ab[0] = h1[j] + h2[j];
+    ab[0] = h2 ? h1[j] + h2[j] : h1[j];
     ab[1] = b;
   }
   if (!v) return;
@@ -394,31 +395,35 @@ void launch_axpy_dot(double* w, const double* V, int64_t ldv, int nv, int64_t n,
 
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
-                          hipStream_t stream) {
+                          bool twice, hipStream_t stream) {
   const int nb = lz_blocks(n);
   hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
   hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h1);
-  if (nv <= kFusedMaxNv) {
-    // first update and second products in one pass over the basis
-    if (nv <= 8)
-      launch_axpy_dot<8>(w, V, ldv, nv, n, h1, partial, nb, stream);
-    else if (nv <= 16)
-      launch_axpy_dot<16>(w, V, ldv, nv, n, h1, partial, nb, stream);
-    else if (nv <= 32)
-      launch_axpy_dot<32>(w, V, ldv, nv, n, h1, partial, nb, stream);
-    else
-      launch_axpy_dot<64>(w, V, ldv, nv, n, h1, partial, nb, stream);
-  } else {
-    hipLaunchKernelGGL(lz_axpy<false>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
-                       partial);
-    hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+  const double* hlast = h1;   // coefficients of the last update
+  if (twice) {
+    if (nv <= kFusedMaxNv) {
+      // first update and second products in one pass over the basis
+      if (nv <= 8)
+        launch_axpy_dot<8>(w, V, ldv, nv, n, h1, partial, nb, stream);
+      else if (nv <= 16)
+        launch_axpy_dot<16>(w, V, ldv, nv, n, h1, partial, nb, stream);
+      else if (nv <= 32)
+        launch_axpy_dot<32>(w, V, ldv, nv, n, h1, partial, nb, stream);
+      else
+        launch_axpy_dot<64>(w, V, ldv, nv, n, h1, partial, nb, stream);
+    } else {
+      hipLaunchKernelGGL(lz_axpy<false>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
+                         partial);
+      hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+    }
+    hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
+    hlast = h2;
   }
-  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
-  hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h2,
+  hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, hlast,
                      partial);
   const unsigned nfin = vnext ? (unsigned)((n + kThreads - 1) / kThreads) : 1u;
-  hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, nb, h1, h2,
-                     nv - 1, ab, n);
+  hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, nb, h1,
+                     twice ? h2 : nullptr, nv - 1, ab, n);
   return hipGetLastError();
 }
 
