@@ -5,7 +5,11 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <thread>
+#include <unistd.h>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -34,6 +38,76 @@ int host_threads() {
   }
   return std::max(1, std::min(n, 32));
 }
+
+// Host worker threads kept for the life of the process, so that the
+// density-matrix solves do not start and join threads on every call.
+// run(n, f) calls f(0..n-1) once each, f(0) on the calling thread, and
+// returns when all have finished; calls from several host threads queue.
+class HostPool {
+ public:
+  static HostPool& get() {
+    static HostPool pool(host_threads() - 1);
+    return pool;
+  }
+  void run(int n, const std::function<void(int)>& f) {
+    std::lock_guard<std::mutex> one(run_mu_);
+    if (getpid() != pid_) {   // a forked child has no workers: run serially
+      for (int t = 0; t < std::max(1, n); ++t) f(t);
+      return;
+    }
+    n = std::max(1, std::min(n, (int)workers_.size() + 1));
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &f;
+      active_ = n - 1;
+      pending_ = n - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    f(0);
+    std::unique_lock<std::mutex> lk(mu_);
+    done_.wait(lk, [&] { return pending_ == 0; });
+    job_ = nullptr;
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : workers_) t.join();
+  }
+
+ private:
+  explicit HostPool(int nworkers) : pid_(getpid()) {
+    for (int i = 0; i < nworkers; ++i) workers_.emplace_back([this, i] { loop(i + 1); });
+  }
+  void loop(int id) {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int)>* job = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        if (id > active_) continue;
+        job = job_;
+      }
+      (*job)(id);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--pending_ == 0) done_.notify_one();
+    }
+  }
+  pid_t pid_;
+  std::vector<std::thread> workers_;
+  std::mutex run_mu_, mu_;
+  std::condition_variable cv_, done_;
+  const std::function<void(int)>* job_ = nullptr;
+  uint64_t gen_ = 0;
+  int active_ = 0, pending_ = 0;
+  bool stop_ = false;
+};
 
 dmrg_status fail(dmrg_status st, const std::string& msg) {
   g_err = msg;
@@ -900,8 +974,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   std::atomic<int> next(0), bad(0);
   std::string bad_what;
   const int hw = host_threads();
-  const int inner = std::max(1, hw / 2);   // threads inside one large sector's solve
-  auto solve = [&]() {
+  auto solve = [&](int) {
     for (;;) {
       const int w = next.fetch_add(1);
       if (w >= nsec) return;
@@ -915,7 +988,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
           const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
           A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
         }
-      if (!sym_eigen_reduce(n, A.data(), eig[sec], n >= 128 ? inner : 1)) {
+      if (!sym_eigen_reduce(n, A.data(), eig[sec], 1)) {
         if (bad.fetch_add(1) == 0) {
           int nonfinite = 0;
           double amax = 0.0;
@@ -932,13 +1005,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
       }
     }
   };
-  {
-    const int nthr = std::min(hw, nsec);
-    std::vector<std::thread> pool;
-    for (int t = 1; t < nthr; ++t) pool.emplace_back(solve);
-    solve();
-    for (auto& th : pool) th.join();
-  }
+  HostPool::get().run(std::min(hw, nsec), solve);
   if (bad.load() > 0)
     return fail(DMRG_E_NOCONV, "density-matrix eigen-solve did not converge in " + bad_what);
   // within a sector, position c in decreasing order is ascending index n - 1 - c
@@ -1010,7 +1077,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   }
   {
     std::atomic<int> it(0);
-    auto vecs = [&]() {
+    auto vecs = [&](int) {
       for (;;) {
         const int w = it.fetch_add(1);
         if (w >= (int)items.size()) return;
@@ -1020,11 +1087,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
                           sb->tr_W[sec].data() + q0, k, 1);
       }
     };
-    const int nthr = std::max(1, std::min(hw, (int)items.size()));
-    std::vector<std::thread> pool;
-    for (int t = 1; t < nthr; ++t) pool.emplace_back(vecs);
-    vecs();
-    for (auto& th : pool) th.join();
+    HostPool::get().run(std::min(hw, (int)items.size()), vecs);
   }
   out->trunc_err = eps;
   out->kept = keep;

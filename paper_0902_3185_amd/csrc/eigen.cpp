@@ -211,12 +211,32 @@ bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
     // p = beta * A v over the trailing block, reading the lower triangle
     // only: row i contributes A[i][j] v[j] to p[i] and A[i][j] v[i] to p[j]
     // for j < i, both along contiguous memory.
+    // One pass over each row does both, the dot in four interleaved
+    // partial sums (as dot4) so that the loop stays in vector registers.
     for (int i = k + 1; i < n; ++i) p[i] = 0.0;
     for (int i = k + 1; i < n; ++i) {
       const double* ai = &A[(size_t)i * n];
       const double vi = v[i];
-      for (int j = k + 1; j < i; ++j) p[j] += ai[j] * vi;
-      p[i] += dot4(ai, v.data(), k + 1, i) + ai[i] * vi;
+      double* pp = p.data();
+      const double* vv = v.data();
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int j = k + 1;
+      for (; j + 4 <= i; j += 4) {
+        pp[j] += ai[j] * vi;
+        pp[j + 1] += ai[j + 1] * vi;
+        pp[j + 2] += ai[j + 2] * vi;
+        pp[j + 3] += ai[j + 3] * vi;
+        s0 += ai[j] * vv[j];
+        s1 += ai[j + 1] * vv[j + 1];
+        s2 += ai[j + 2] * vv[j + 2];
+        s3 += ai[j + 3] * vv[j + 3];
+      }
+      double t = 0.0;
+      for (; j < i; ++j) {
+        pp[j] += ai[j] * vi;
+        t += ai[j] * vv[j];
+      }
+      pp[i] += (((s0 + s1) + (s2 + s3)) + t) + ai[i] * vi;
     }
     double vtp = 0.0;
     for (int i = k + 1; i < n; ++i) {
