@@ -203,6 +203,8 @@ struct dmrg_ctx_s {
   DevBuf V, w, partial, small;
   double* host_small = nullptr;   // pinned, for per-iteration scalars
   size_t host_small_n = 0;
+  double* host_rho = nullptr;     // pinned, density-matrix blocks on their way to the host
+  size_t host_rho_n = 0;
 };
 
 struct dmrg_sb_s {
@@ -220,8 +222,17 @@ struct dmrg_sb_s {
   Staged fwd;
   std::unique_ptr<Staged> adj;
   int variant[3] = {0, 0, 0};   // fused-kernel variant per kernel precision (autotuner)
-  // density-matrix scratch and results
-  DevBuf rho_images, rho_out;
+  // density-matrix blocks: tile images per side (built on first use), output
+  struct RhoPlan {
+    bool built = false;
+    std::vector<int64_t> off;   // per sector of the side: offset of its block, -1 if none
+    int ntiles = 0;
+    int32_t stride = 0;
+    int64_t total = 0;
+    DevBuf images;
+  };
+  RhoPlan rho_plan[2];
+  DevBuf rho_out;
   std::vector<double> tr_lambda;
   std::vector<int32_t> tr_sec, tr_kps;
   std::vector<std::vector<double>> tr_W;
@@ -427,6 +438,7 @@ void dmrg_ctx_destroy(dmrg_ctx ctx) {
   for (auto e : ctx->chk)
     if (e) (void)hipEventDestroy(e);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
+  if (ctx->host_rho) (void)hipHostFree(ctx->host_rho);
   delete ctx;
 }
 
@@ -893,65 +905,83 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   const std::vector<int64_t>& qs = side == 0 ? sb->qS : sb->qE;
   const std::vector<int32_t>& ds = side == 0 ? sb->dS : sb->dE;
   const int nsec = (int)qs.size();
-  // rho blocks of the sectors that appear in a target pair, on the matrix cores
-  std::vector<int64_t> rho_off(nsec, -1);
-  std::vector<TileDesc> tiles;
-  std::vector<SegDesc> segs;
-  int64_t total = 0;
-  for (size_t q = 0; q < p.pair_s.size(); ++q) {
-    const int32_t a = p.dS[p.pair_s[q]], b = p.dE[p.pair_e[q]];
-    const int32_t sec = side == 0 ? p.pair_s[q] : p.pair_e[q];
-    const int32_t n = side == 0 ? a : b;
-    rho_off[sec] = total;
-    SegDesc sg{};
-    sg.c = 1.0;
-    sg.term = 0;
-    sg.psi_off = p.pair_off[q];
-    sg.psi_ld = b;
-    sg.psi_rows = a;
-    sg.op_off = p.pair_off[q];
-    sg.op_ld = b;
-    sg.gA = -1;
-    sg.gB = -1;
-    if (side == 0) {          // rho[m][n] = sum_k Psi[m][k] Psi[n][k]
-      sg.kind = SEG_MK;
-      sg.K = b;
-    } else {                  // rho[m][n] = sum_k Psi[k][m] Psi[k][n]
-      sg.kind = SEG_KN;
-      sg.K = a;
-    }
-    sg.ch0 = 0;
-    const int32_t s0 = (int32_t)segs.size();
-    segs.push_back(sg);
-    for (int32_t m0 = 0; m0 < n; m0 += kTile)
-      for (int32_t n0 = 0; n0 < n; n0 += kTile) {
-        TileDesc t{};
-        t.y_off = total;
-        t.a = n;
-        t.b = n;
-        t.m0 = m0;
-        t.n0 = n0;
-        t.seg0 = s0;
-        t.nseg = 1;
-        t.nchunk = (sg.K + kChunk - 1) / kChunk;
-        t.ngemm = 1;
-        t.ldy = n;
-        tiles.push_back(t);
+  // rho blocks of the sectors that appear in a target pair, on the matrix
+  // cores; the tile images depend only on the plan and are kept per side
+  dmrg_sb_s::RhoPlan& rp = sb->rho_plan[side];
+  if (!rp.built) {
+    rp.off.assign(nsec, -1);
+    std::vector<TileDesc> tiles;
+    std::vector<SegDesc> segs;
+    int64_t total = 0;
+    for (size_t q = 0; q < p.pair_s.size(); ++q) {
+      const int32_t a = p.dS[p.pair_s[q]], b = p.dE[p.pair_e[q]];
+      const int32_t sec = side == 0 ? p.pair_s[q] : p.pair_e[q];
+      const int32_t n = side == 0 ? a : b;
+      rp.off[sec] = total;
+      SegDesc sg{};
+      sg.c = 1.0;
+      sg.term = 0;
+      sg.psi_off = p.pair_off[q];
+      sg.psi_ld = b;
+      sg.psi_rows = a;
+      sg.op_off = p.pair_off[q];
+      sg.op_ld = b;
+      sg.gA = -1;
+      sg.gB = -1;
+      if (side == 0) {          // rho[m][n] = sum_k Psi[m][k] Psi[n][k]
+        sg.kind = SEG_MK;
+        sg.K = b;
+      } else {                  // rho[m][n] = sum_k Psi[k][m] Psi[k][n]
+        sg.kind = SEG_KN;
+        sg.K = a;
       }
-    total += (int64_t)n * n;
-  }
-  std::vector<uint32_t> img;
-  int32_t stride = 0;
-  {
+      sg.ch0 = 0;
+      const int32_t s0 = (int32_t)segs.size();
+      segs.push_back(sg);
+      for (int32_t m0 = 0; m0 < n; m0 += kTile)
+        for (int32_t n0 = 0; n0 < n; n0 += kTile) {
+          TileDesc t{};
+          t.y_off = total;
+          t.a = n;
+          t.b = n;
+          t.m0 = m0;
+          t.n0 = n0;
+          t.seg0 = s0;
+          t.nseg = 1;
+          t.nchunk = (sg.K + kChunk - 1) / kChunk;
+          t.ngemm = 1;
+          t.ldy = n;
+          tiles.push_back(t);
+        }
+      total += (int64_t)n * n;
+    }
+    std::vector<uint32_t> img;
     std::string err;
-    if (!build_images(tiles, segs, {}, {}, {}, img, stride, err)) return fail(DMRG_E_UNSUPPORTED, err);
+    if (!build_images(tiles, segs, {}, {}, {}, img, rp.stride, err)) return fail(DMRG_E_UNSUPPORTED, err);
+    if ((st = upload(rp.images, img.data(), img.size() * sizeof(uint32_t), s)) != DMRG_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));   // the host image vector dies here
+    rp.ntiles = (int)tiles.size();
+    rp.total = total;
+    rp.built = true;
   }
-  if ((st = upload(sb->rho_images, img.data(), img.size() * sizeof(uint32_t), s)) != DMRG_OK) return st;
+  const std::vector<int64_t>& rho_off = rp.off;
+  const int64_t total = rp.total;
   HIP_TRY(sb->rho_out.ensure((size_t)std::max<int64_t>(total, 1) * sizeof(double)));
-  HIP_TRY(launch_hpsi(kPrecF64, 0, (int)tiles.size(), sb->rho_images.as<uint32_t>(), stride, psi_d, psi_d,
+  HIP_TRY(launch_hpsi(kPrecF64, 0, rp.ntiles, rp.images.as<uint32_t>(), rp.stride, psi_d, psi_d,
                       sb->rho_out.as<double>(), 1.0, 0.0, s));
-  std::vector<double> rho((size_t)total);
-  HIP_TRY(hipMemcpyAsync(rho.data(), sb->rho_out.p, rho.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  dmrg_ctx ctx = sb->ctx;
+  if (ctx->host_rho_n < (size_t)std::max<int64_t>(total, 1)) {
+    if (ctx->host_rho) (void)hipHostFree(ctx->host_rho);
+    ctx->host_rho = nullptr;
+    ctx->host_rho_n = 0;
+    const size_t want = (size_t)std::max<int64_t>(total, 1);
+    HIP_TRY(hipHostMalloc((void**)&ctx->host_rho, want * sizeof(double), hipHostMallocDefault));
+    ctx->host_rho_n = want;
+  }
+  const double* rho = ctx->host_rho;
+  if (total > 0)
+    HIP_TRY(hipMemcpyAsync(ctx->host_rho, sb->rho_out.p, (size_t)total * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
 
   // per-sector FP64 eigen; zero blocks for sectors without a target pair
@@ -982,7 +1012,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
       const int n = ds[sec];
       std::vector<double> A((size_t)n * n, 0.0);
       if (rho_off[sec] >= 0)
-        std::copy(rho.begin() + rho_off[sec], rho.begin() + rho_off[sec] + (size_t)n * n, A.begin());
+        std::copy(rho + rho_off[sec], rho + rho_off[sec] + (size_t)n * n, A.begin());
       for (int i = 0; i < n; ++i)   // symmetrise the computed block
         for (int j = i + 1; j < n; ++j) {
           const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);

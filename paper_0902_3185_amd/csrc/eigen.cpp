@@ -172,6 +172,61 @@ inline double dot4(const double* a, const double* b, int lo, int hi) {
   return ((s0 + s1) + (s2 + s3)) + t;
 }
 
+// Row i of the lower triangle (ai = A + i n), columns [lo, i]: with kUpd the
+// rank-2 update a_ij -= u_i w_j + w_i u_j first; with kMv its part of A x
+// (row i adds a_ij x_j to acc_i and a_ij x_i to acc_j, j < i; the dot in four
+// interleaved partial sums so that the loop stays in vector registers).
+template <bool kUpd, bool kMv>
+inline void row_pass(double* __restrict__ ai, int i, int lo, const double* __restrict__ u,
+                     const double* __restrict__ w, const double* __restrict__ x,
+                     double* __restrict__ acc) {
+  const double ui = kUpd ? u[i] : 0.0, wi = kUpd ? w[i] : 0.0;
+  if (!kMv) {
+    for (int j = lo; j <= i; ++j) ai[j] -= ui * w[j] + wi * u[j];
+    return;
+  }
+  const double xi = x[i];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int j = lo;
+  for (; j + 4 <= i; j += 4) {
+    double a0 = ai[j], a1 = ai[j + 1], a2 = ai[j + 2], a3 = ai[j + 3];
+    if (kUpd) {
+      a0 -= ui * w[j] + wi * u[j];
+      a1 -= ui * w[j + 1] + wi * u[j + 1];
+      a2 -= ui * w[j + 2] + wi * u[j + 2];
+      a3 -= ui * w[j + 3] + wi * u[j + 3];
+      ai[j] = a0;
+      ai[j + 1] = a1;
+      ai[j + 2] = a2;
+      ai[j + 3] = a3;
+    }
+    acc[j] += a0 * xi;
+    acc[j + 1] += a1 * xi;
+    acc[j + 2] += a2 * xi;
+    acc[j + 3] += a3 * xi;
+    s0 += a0 * x[j];
+    s1 += a1 * x[j + 1];
+    s2 += a2 * x[j + 2];
+    s3 += a3 * x[j + 3];
+  }
+  double t = 0.0;
+  for (; j < i; ++j) {
+    double a = ai[j];
+    if (kUpd) {
+      a -= ui * w[j] + wi * u[j];
+      ai[j] = a;
+    }
+    acc[j] += a * xi;
+    t += a * x[j];
+  }
+  double a = ai[i];
+  if (kUpd) {
+    a -= ui * w[i] + wi * u[i];
+    ai[i] = a;
+  }
+  acc[i] += (((s0 + s1) + (s2 + s3)) + t) + a * xi;
+}
+
 }  // namespace
 
 bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
@@ -187,56 +242,42 @@ bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
   std::vector<double>& betas = out.beta;
   // 1. Householder reduction to tridiagonal form on the lower triangle.
   //    Reflector k is H_k = I - beta_k v_k v_k^T with v_k[0..k] = 0; its
-  //    nonzero part v_k[k+1..n) is kept in R[k][k+1..n).
-  std::vector<double> v(n), p(n);
-  for (int k = 0; k + 2 < n; ++k) {
-    // The column is scaled by its largest entry first: the reflector does
-    // not change, and its norm neither underflows nor overflows (the
-    // trailing columns of a low-rank density matrix decay towards the
-    // underflow threshold).
+  //    nonzero part v_k[k+1..n) is kept in R[k][k+1..n).  Step k needs
+  //    p = beta_k A v_k over the trailing block and then the rank-2 update
+  //    A -= v w^T + w v^T.  Column k+1 is updated first, which fixes
+  //    reflector k+1; the rest of the update and the next step's p are then
+  //    one pass over the trailing rows instead of two.
+  std::vector<double> v(n), v2(n), p(n), p2(n);
+  // Reflector of column k: v[k+1..n), beta and the new subdiagonal entry.
+  // The column is scaled by its largest entry first: the reflector does not
+  // change, and its norm neither underflows nor overflows (the trailing
+  // columns of a low-rank density matrix decay towards the underflow
+  // threshold).  False if the column is zero below the subdiagonal.
+  auto reflector = [&](int k, double* vk, double& beta, double& sub) {
     double scale = 0.0;
     for (int i = k + 1; i < n; ++i) scale = std::max(scale, std::fabs(A[(size_t)i * n + k]));
-    if (scale == 0.0) continue;
+    if (scale == 0.0) return false;
     double sigma = 0.0;
     for (int i = k + 2; i < n; ++i) {
-      v[i] = A[(size_t)i * n + k] / scale;
-      sigma += v[i] * v[i];
+      vk[i] = A[(size_t)i * n + k] / scale;
+      sigma += vk[i] * vk[i];
     }
-    if (sigma == 0.0) continue;
+    if (sigma == 0.0) return false;
     const double x0 = A[(size_t)(k + 1) * n + k] / scale;
     const double norm = std::sqrt(x0 * x0 + sigma);
     const double alpha = x0 <= 0.0 ? norm : -norm;
-    v[k + 1] = x0 - alpha;
-    const double beta = 2.0 / (v[k + 1] * v[k + 1] + sigma);
-    // p = beta * A v over the trailing block, reading the lower triangle
-    // only: row i contributes A[i][j] v[j] to p[i] and A[i][j] v[i] to p[j]
-    // for j < i, both along contiguous memory.
-    // One pass over each row does both, the dot in four interleaved
-    // partial sums (as dot4) so that the loop stays in vector registers.
-    for (int i = k + 1; i < n; ++i) p[i] = 0.0;
-    for (int i = k + 1; i < n; ++i) {
-      const double* ai = &A[(size_t)i * n];
-      const double vi = v[i];
-      double* pp = p.data();
-      const double* vv = v.data();
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int j = k + 1;
-      for (; j + 4 <= i; j += 4) {
-        pp[j] += ai[j] * vi;
-        pp[j + 1] += ai[j + 1] * vi;
-        pp[j + 2] += ai[j + 2] * vi;
-        pp[j + 3] += ai[j + 3] * vi;
-        s0 += ai[j] * vv[j];
-        s1 += ai[j + 1] * vv[j + 1];
-        s2 += ai[j + 2] * vv[j + 2];
-        s3 += ai[j + 3] * vv[j + 3];
-      }
-      double t = 0.0;
-      for (; j < i; ++j) {
-        pp[j] += ai[j] * vi;
-        t += ai[j] * vv[j];
-      }
-      pp[i] += (((s0 + s1) + (s2 + s3)) + t) + ai[i] * vi;
+    vk[k + 1] = x0 - alpha;
+    beta = 2.0 / (vk[k + 1] * vk[k + 1] + sigma);
+    sub = alpha * scale;
+    return true;
+  };
+  double beta = 0.0, sub = 0.0;
+  bool have = false;     // reflector k (v, beta, sub) is known and p holds A v_k
+  for (int k = 0; k + 2 < n; ++k) {
+    if (!have) {
+      if (!reflector(k, v.data(), beta, sub)) continue;
+      for (int i = k + 1; i < n; ++i) p[i] = 0.0;
+      for (int i = k + 1; i < n; ++i) row_pass<false, true>(&A[(size_t)i * n], i, k + 1, nullptr, nullptr, v.data(), p.data());
     }
     double vtp = 0.0;
     for (int i = k + 1; i < n; ++i) {
@@ -245,15 +286,27 @@ bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
     }
     const double K = 0.5 * beta * vtp;
     for (int i = k + 1; i < n; ++i) p[i] -= K * v[i];   // p becomes w
-    for (int i = k + 1; i < n; ++i) {
-      double* ai = &A[(size_t)i * n];
-      const double vi = v[i], wi = p[i];
-      for (int j = k + 1; j <= i; ++j) ai[j] -= vi * p[j] + wi * v[j];
+    // column k+1 of the trailing block, then reflector k+1 from it
+    for (int i = k + 1; i < n; ++i) A[(size_t)i * n + k + 1] -= v[i] * p[k + 1] + p[i] * v[k + 1];
+    double beta2 = 0.0, sub2 = 0.0;
+    const bool next = k + 3 < n && reflector(k + 1, v2.data(), beta2, sub2);
+    if (next) {
+      for (int i = k + 2; i < n; ++i) p2[i] = 0.0;
+      for (int i = k + 2; i < n; ++i) row_pass<true, true>(&A[(size_t)i * n], i, k + 2, v.data(), p.data(), v2.data(), p2.data());
+    } else {
+      for (int i = k + 2; i < n; ++i) row_pass<true, false>(&A[(size_t)i * n], i, k + 2, v.data(), p.data(), nullptr, nullptr);
     }
-    A[(size_t)(k + 1) * n + k] = alpha * scale;
+    A[(size_t)(k + 1) * n + k] = sub;
     for (int i = k + 2; i < n; ++i) A[(size_t)i * n + k] = 0.0;
     betas[k] = beta;
     std::copy(v.begin() + k + 1, v.end(), R.begin() + (size_t)k * n + k + 1);
+    have = next;
+    if (next) {
+      std::swap(v, v2);
+      std::swap(p, p2);
+      beta = beta2;
+      sub = sub2;
+    }
   }
   std::vector<double> d(n), e(n, 0.0);
   for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];

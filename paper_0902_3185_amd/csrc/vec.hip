@@ -336,6 +336,10 @@ __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
                                                       const double* __restrict__ h2, int j,
                                                       double* __restrict__ ab, int64_t n) {
   __shared__ double beta;
+  // this thread's element of w is loaded before the norm is summed, so the
+  // two memory latencies overlap
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const double wi = (v && i < n) ? w[i] : 0.0;
   if (threadIdx.x < 64) {
     const double nrm = wave_row_sum(partial, np);
     if (threadIdx.x == 0) beta = sqrt(nrm > 0.0 ? nrm : 0.0);
@@ -348,8 +352,7 @@ __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
   }
   if (!v) return;
   const double inv = b > 0.0 ? 1.0 / b : 0.0;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i < n) v[i] = w[i] * inv;
+  if (i < n) v[i] = wi * inv;
 }
 
 // w -= sum_{i<nv} h[i] V_i, then partial[i * gridDim.x + blockIdx.x] = the
