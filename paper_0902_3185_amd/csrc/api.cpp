@@ -1013,11 +1013,16 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
       std::vector<double> A((size_t)n * n, 0.0);
       if (rho_off[sec] >= 0)
         std::copy(rho + rho_off[sec], rho + rho_off[sec] + (size_t)n * n, A.begin());
-      for (int i = 0; i < n; ++i)   // symmetrise the computed block
-        for (int j = i + 1; j < n; ++j) {
-          const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
-          A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
-        }
+      // symmetrise the computed block, in 16 x 16 tiles so that the
+      // transposed reads stay in cache
+      constexpr int kSym = 16;
+      for (int i0 = 0; i0 < n; i0 += kSym)
+        for (int j0 = i0; j0 < n; j0 += kSym)
+          for (int i = i0; i < std::min(n, i0 + kSym); ++i)
+            for (int j = std::max(i + 1, j0); j < std::min(n, j0 + kSym); ++j) {
+              const double v = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+              A[(size_t)i * n + j] = A[(size_t)j * n + i] = v;
+            }
       if (!sym_eigen_reduce(n, A.data(), eig[sec], 1)) {
         if (bad.fetch_add(1) == 0) {
           int nonfinite = 0;

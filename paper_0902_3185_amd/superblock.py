@@ -258,16 +258,23 @@ class Superblock:
         check(lib().dmrg_rho_truncate(self.handle, _ptr(psi), int(side), int(m), int(bool(no_split)),
                                       C.byref(tr)))
         kept = tr.kept
-        kps = [tr.kept_per_sec[i] for i in range(tr.nsec)]
+
+        def arr(ptr, n, dtype):   # copy of a library-owned array (ctypes indexing is slow)
+            if n == 0:
+                return np.zeros(0, dtype=dtype)
+            return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
+
+        kps = arr(tr.kept_per_sec, tr.nsec, np.int64)
         W = {}
         for s in range(tr.nsec):
-            if kps[s] > 0:
-                W[s] = np.ctypeslib.as_array(tr.W[s], shape=(self._dim(side, s) * kps[s],)).reshape(
-                    self._dim(side, s), kps[s]).copy()
+            k = int(kps[s])
+            if k > 0:
+                d = self._dim(side, s)
+                W[s] = np.ctypeslib.as_array(tr.W[s], shape=(d * k,)).reshape(d, k).copy()
         return dict(eps=tr.trunc_err, kept=kept, straddle=bool(tr.straddle),
-                    lam=np.array([tr.lambda_[i] for i in range(kept)]),
-                    lam_sec=np.array([tr.lambda_sec[i] for i in range(kept)], dtype=np.int64),
-                    kept_per_sec=np.array(kps), W=W)
+                    lam=arr(tr.lambda_, kept, np.float64),
+                    lam_sec=arr(tr.lambda_sec, kept, np.int64),
+                    kept_per_sec=kps, W=W)
 
     def _dim(self, side, s):
         return int(self._dims[side][s])
