@@ -786,19 +786,17 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
     // evaluates the check taken after step jc from h; true: the cycle stops
     double ctol = tol;                   // this cycle's stopping residual
     double est_prev = -1.0, est_last = -1.0;   // the last two evaluated estimates
-    // Gram-Schmidt against the basis runs twice in the first step of a cycle
-    // and once after it.  One pass leaves v_{j+1} orthogonal to the basis up
-    // to about eps * ||H v_j|| / beta_j; the start vector of a restarted
-    // cycle is close to an eigenvector (small beta_0), later steps have
-    // ||H v_j|| / beta_j = sqrt(alpha_j^2 + beta_{j-1}^2 + beta_j^2) / beta_j
-    // of order one.  Should that ratio exceed kOncePassMax at a check, the
-    // rest of the cycle runs both passes.  A basis that is not small against
-    // the dimension always runs both: the Krylov space may be exhausted (or
-    // confined to a small invariant subspace) within the cycle, and one pass
-    // would not leave the vanishing beta that ends the recursion there.
-    constexpr double kOncePassMax = 1e3;
+    // The first step of a cycle orthogonalises by classical Gram-Schmidt
+    // twice; later steps subtract the local three-term recurrence (alpha_j
+    // V_j + beta_{j-1} V_{j-1}) and run one Gram-Schmidt pass on the
+    // remainder, which keeps the basis orthogonal to working precision at
+    // two passes over it instead of three.  A basis that is not small
+    // against the dimension always runs two full passes: the Krylov space may
+    // be exhausted (or confined to a small invariant subspace) within the
+    // cycle, and only they leave the vanishing beta that ends the recursion
+    // there.
     constexpr int64_t kOncePassMinRatio = 32;   // D >= 32 * vectors per cycle
-    bool twice = D < kOncePassMinRatio * nvec;
+    const bool twice = D < kOncePassMinRatio * nvec;
     auto evaluate = [&](int jc, const double* h) {
       alphas.clear();
       betas.clear();
@@ -810,11 +808,6 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
         if (b <= 1e-13 * std::max(1.0, std::fabs(h[2 * m]))) break;
       }
       const int steps = (int)alphas.size();
-      for (int m = 1; m < steps && !twice; ++m) {
-        const double b = betas[m];
-        const double g = std::sqrt(alphas[m] * alphas[m] + betas[m - 1] * betas[m - 1] + b * b);
-        if (!(g <= kOncePassMax * b)) twice = true;
-      }
       if (jc == 0) {
         E = alphas[0];
         res = betas[0];
@@ -845,8 +838,10 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
       if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
       ++total;
+      const bool two = j == 0 || twice;
       HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
-                             j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, j == 0 || twice, s));
+                             j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, two,
+                             two ? nullptr : ab + 2 * (j - 1) + 1, s));
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
       HIP_TRY(hipMemcpyAsync(hbuf[nbuf], ab, 2 * (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1256,7 +1251,7 @@ dmrg_status dmrg_lanczos_tridiag(dmrg_sb sb, const double* v0_d, int32_t nsteps,
   for (int j = 0; j < nsteps; ++j) {
     if ((st = run_product(sb, sb->fwd, sb->prec, V + (size_t)j * D, w, 1.0, 0.0)) != DMRG_OK) return st;
     HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
-                           V + (size_t)(j + 1) * D, true, s));
+                           V + (size_t)(j + 1) * D, true, nullptr, s));
   }
   std::vector<double> hs(2 * nsteps + 1);
   HIP_TRY(hipMemcpyAsync(hs.data(), ab, 2 * nsteps * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -135,14 +135,23 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 }
 
 // ---------------------------------------------------------------------------
-// One step of the Lanczos recursion with classical Gram-Schmidt against the
-// whole basis, once or twice, in bandwidth-shaped launches:
+// One step of the Lanczos recursion, orthogonalised against the whole basis
+// in bandwidth-shaped launches.  Either classical Gram-Schmidt twice:
 //   dot     partial sums of V^T w
 //   reduce  h1 = sum of the partials, one wave per basis vector
-//   (twice: axpy+dot  w -= V h1, then partial sums of V^T w for the
-//    updated w; reduce  h2)
-//   axpy    w -= V h (h2 or h1) and partial sums of ||w||^2
+//   axpy+dot  w -= V h1, then partial sums of V^T w for the updated w
+//   reduce  h2
+//   axpy    w -= V h2 and partial sums of ||w||^2
 //   finish  (alpha, beta) and v_next = w / beta
+// or the local three-term recurrence followed by one Gram-Schmidt pass,
+// w' = w - alpha V_j - beta_{j-1} V_{j-1}, w -= V (V^T w'), in two passes:
+//   dot3    partial sums of V^T w, V^T V_j and V^T V_{j-1}
+//   reduce  the pass's coefficients (lz_reduce_local)
+//   axpy, finish  as above
+// One pass over a vector that is already orthogonal to V up to the
+// recurrence's small remainder keeps the basis orthogonal to working
+// precision; one pass over w itself would not (its error grows by about
+// ||H V_j|| / beta_j per step).
 // Every pass gives each thread one element of w (256 per block, a grid of
 // ceil(n / 256) blocks) and walks the basis vectors in batches whose loads
 // are all issued before the first use, so a wave keeps a batch of basis
@@ -159,7 +168,7 @@ constexpr int kFusedMaxNv = 64;   // basis size up to which axpy and dot share a
 int lz_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kLzThreads - 1) / kLzThreads); }
 
 size_t lz_partial_size(int64_t n, int nv) {
-  return (size_t)std::max(nv, 1) * (size_t)lz_blocks(n);
+  return (size_t)3 * std::max(nv, 1) * (size_t)lz_blocks(n);
 }
 
 __device__ inline double wave_sum(double v) {
@@ -269,6 +278,78 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot(const double* __restrict__ 
 #pragma unroll
     for (int b = 0; b < kTailBatch; ++b) p[b] = (ok && b < nb) ? p[b] * x : 0.0;
     block_batch_partials<kTailBatch>(p, sh, parity, i0, nb, partial);
+  }
+}
+
+// Three sets of products in one pass over the basis: for s = 0, 1, 2 and
+// i < nv, partial[(s * nv + i) * gridDim.x + blockIdx.x] = the block's part
+// of <V_i, x_s> with x_0 = w, x_1 = V_{nv-1}, x_2 = V_{nv-2} (nv >= 2).  The
+// basis elements of a batch are loaded once and used for all three.
+__global__ __launch_bounds__(kLzThreads) void lz_dot3(const double* __restrict__ V, int64_t ldv,
+                                                      int nv, const double* __restrict__ w,
+                                                      int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[2][kLzThreads / 64][kBatch];
+  const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
+  const bool ok = e < n;
+  const double* Vb = V + (ok ? e : 0);   // in-range address for the tail block
+  double x[3];
+  x[0] = ok ? w[e] : 0.0;
+  x[1] = ok ? Vb[(int64_t)(nv - 1) * ldv] : 0.0;
+  x[2] = ok ? Vb[(int64_t)(nv - 2) * ldv] : 0.0;
+  int i0 = 0, parity = 0;
+#pragma unroll 1
+  for (; i0 + kBatch <= nv; i0 += kBatch) {
+    double t[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) t[b] = Vb[(int64_t)(i0 + b) * ldv];
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q, parity ^= 1) {
+      double p[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) p[b] = ok ? t[b] * x[q] : 0.0;
+      block_batch_partials<kBatch>(p, sh, parity, q * nv + i0, kBatch, partial);
+    }
+  }
+#pragma unroll 1
+  for (; i0 < nv; i0 += kTailBatch) {
+    const int nb = min(kTailBatch, nv - i0);
+    double t[kTailBatch];
+#pragma unroll
+    for (int b = 0; b < kTailBatch; ++b) t[b] = Vb[(int64_t)(i0 + (b < nb ? b : 0)) * ldv];
+#pragma unroll 1
+    for (int q = 0; q < 3; ++q, parity ^= 1) {
+      double p[kTailBatch];
+#pragma unroll
+      for (int b = 0; b < kTailBatch; ++b) p[b] = (ok && b < nb) ? t[b] * x[q] : 0.0;
+      block_batch_partials<kTailBatch>(p, sh, parity, q * nv + i0, nb, partial);
+    }
+  }
+}
+
+// Coefficients of the single Gram-Schmidt pass that follows the local
+// three-term recurrence (see launch_lz_step): with r_i = <V_i, w>,
+// g_i = <V_i, V_j>, m_i = <V_i, V_{j-1}> (j = nv - 1, sums of lz_dot3's
+// partials), alpha = r_j and beta = *beta_prev,
+//   h[i] = r_i - alpha g_i - beta m_i + alpha [i == j] + beta [i == j-1],
+// so that w - sum_i h[i] V_i = w' - V (V^T w') for w' = w - alpha V_j -
+// beta V_{j-1}.  One block of four waves per i: the waves sum r_i, g_i, m_i
+// and r_j in parallel.
+__global__ __launch_bounds__(256) void lz_reduce_local(const double* __restrict__ partial, int nbx,
+                                                       int nv, const double* __restrict__ beta_prev,
+                                                       double* __restrict__ h) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x, j = nv - 1;
+  const int wave = threadIdx.x >> 6;
+  const int row = wave < 3 ? wave * nv + i : j;
+  const double t = wave_row_sum(partial + (int64_t)row * nbx, nbx);
+  if ((threadIdx.x & 63) == 0) sh[wave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double alpha = sh[3], beta = *beta_prev;
+    double c = sh[0] - alpha * sh[1] - beta * sh[2];
+    if (i == j) c += alpha;
+    if (i == j - 1) c += beta;
+    h[i] = c;
   }
 }
 
@@ -398,12 +479,12 @@ void launch_axpy_dot(double* w, const double* V, int64_t ldv, int nv, int64_t n,
 
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
-                          bool twice, hipStream_t stream) {
+                          bool twice, const double* beta_prev, hipStream_t stream) {
   const int nb = lz_blocks(n);
-  hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
-  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h1);
-  const double* hlast = h1;   // coefficients of the last update
+  if (!twice && (nv < 2 || !beta_prev)) return hipErrorInvalidValue;
   if (twice) {
+    hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+    hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h1);
     if (nv <= kFusedMaxNv) {
       // first update and second products in one pass over the basis
       if (nv <= 8)
@@ -420,10 +501,12 @@ hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64
       hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
     }
     hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
-    hlast = h2;
+  } else {
+    hipLaunchKernelGGL(lz_dot3, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+    hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(256), 0, stream, partial, nb, nv, beta_prev, h1);
   }
-  hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, hlast,
-                     partial);
+  hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n,
+                     twice ? h2 : h1, partial);
   const unsigned nfin = vnext ? (unsigned)((n + kThreads - 1) / kThreads) : 1u;
   hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, nb, h1,
                      twice ? h2 : nullptr, nv - 1, ab, n);
