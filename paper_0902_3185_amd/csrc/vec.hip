@@ -283,48 +283,74 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot(const double* __restrict__ 
 
 // Three sets of products in one pass over the basis: for s = 0, 1, 2 and
 // i < nv, partial[(s * nv + i) * gridDim.x + blockIdx.x] = the block's part
-// of <V_i, x_s> with x_0 = w, x_1 = V_{nv-1}, x_2 = V_{nv-2} (nv >= 2).  The
-// basis elements of a batch are loaded once and used for all three.
+// of <V_i, x_s> with x_0 = w, x_1 = V_{nv-1}, x_2 = V_{nv-2} (nv >= 2).  A
+// thread takes kE elements (256 kE per block) and the basis in batches of
+// kB vectors, loaded once and used for all three sets; the thread's
+// products are summed over its elements before the wave's butterfly.
+template <int kE, int kB>
 __global__ __launch_bounds__(kLzThreads) void lz_dot3(const double* __restrict__ V, int64_t ldv,
                                                       int nv, const double* __restrict__ w,
                                                       int64_t n, double* __restrict__ partial) {
   __shared__ double sh[2][kLzThreads / 64][kBatch];
-  const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
-  const bool ok = e < n;
-  const double* Vb = V + (ok ? e : 0);   // in-range address for the tail block
-  double x[3];
-  x[0] = ok ? w[e] : 0.0;
-  x[1] = ok ? Vb[(int64_t)(nv - 1) * ldv] : 0.0;
-  x[2] = ok ? Vb[(int64_t)(nv - 2) * ldv] : 0.0;
+  static_assert(kB <= kBatch, "batch larger than the block's staging");
+  const int64_t e0 = (int64_t)blockIdx.x * kLzThreads * kE + threadIdx.x;
+  bool ok[kE];
+  int64_t ec[kE];
+  double x[3][kE];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int64_t e = e0 + (int64_t)q * kLzThreads;
+    ok[q] = e < n;
+    ec[q] = ok[q] ? e : 0;   // in-range address for the tail block
+    x[0][q] = ok[q] ? w[e] : 0.0;
+    x[1][q] = ok[q] ? V[(int64_t)(nv - 1) * ldv + e] : 0.0;
+    x[2][q] = ok[q] ? V[(int64_t)(nv - 2) * ldv + e] : 0.0;
+  }
   int i0 = 0, parity = 0;
 #pragma unroll 1
-  for (; i0 + kBatch <= nv; i0 += kBatch) {
-    double t[kBatch];
+  for (; i0 + kB <= nv; i0 += kB) {
+    double t[kB][kE];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) t[b] = Vb[(int64_t)(i0 + b) * ldv];
+    for (int b = 0; b < kB; ++b)
+#pragma unroll
+      for (int q = 0; q < kE; ++q) t[b][q] = V[(int64_t)(i0 + b) * ldv + ec[q]];
 #pragma unroll 1
-    for (int q = 0; q < 3; ++q, parity ^= 1) {
-      double p[kBatch];
+    for (int s = 0; s < 3; ++s, parity ^= 1) {
+      double p[kB];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) p[b] = ok ? t[b] * x[q] : 0.0;
-      block_batch_partials<kBatch>(p, sh, parity, q * nv + i0, kBatch, partial);
+      for (int b = 0; b < kB; ++b) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < kE; ++q) a += ok[q] ? t[b][q] * x[s][q] : 0.0;
+        p[b] = a;
+      }
+      block_batch_partials<kB>(p, sh, parity, s * nv + i0, kB, partial);
     }
   }
 #pragma unroll 1
   for (; i0 < nv; i0 += kTailBatch) {
     const int nb = min(kTailBatch, nv - i0);
-    double t[kTailBatch];
+    double t[kTailBatch][kE];
 #pragma unroll
-    for (int b = 0; b < kTailBatch; ++b) t[b] = Vb[(int64_t)(i0 + (b < nb ? b : 0)) * ldv];
+    for (int b = 0; b < kTailBatch; ++b)
+#pragma unroll
+      for (int q = 0; q < kE; ++q) t[b][q] = V[(int64_t)(i0 + (b < nb ? b : 0)) * ldv + ec[q]];
 #pragma unroll 1
-    for (int q = 0; q < 3; ++q, parity ^= 1) {
+    for (int s = 0; s < 3; ++s, parity ^= 1) {
       double p[kTailBatch];
 #pragma unroll
-      for (int b = 0; b < kTailBatch; ++b) p[b] = (ok && b < nb) ? t[b] * x[q] : 0.0;
-      block_batch_partials<kTailBatch>(p, sh, parity, q * nv + i0, nb, partial);
+      for (int b = 0; b < kTailBatch; ++b) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < kE; ++q) a += (ok[q] && b < nb) ? t[b][q] * x[s][q] : 0.0;
+        p[b] = a;
+      }
+      block_batch_partials<kTailBatch>(p, sh, parity, s * nv + i0, nb, partial);
     }
   }
 }
+
+constexpr int kDot3E = 1, kDot3B = 32;   // the configuration the step launches
 
 // Coefficients of the single Gram-Schmidt pass that follows the local
 // three-term recurrence (see launch_lz_step): with r_i = <V_i, w>,
@@ -502,8 +528,10 @@ hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64
     }
     hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
   } else {
-    hipLaunchKernelGGL(lz_dot3, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
-    hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(256), 0, stream, partial, nb, nv, beta_prev, h1);
+    const int nb3 = (int)std::max<int64_t>(1, (n + kLzThreads * kDot3E - 1) / (kLzThreads * kDot3E));
+    hipLaunchKernelGGL((lz_dot3<kDot3E, kDot3B>), dim3(nb3), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n,
+                       partial);
+    hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(256), 0, stream, partial, nb3, nv, beta_prev, h1);
   }
   hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n,
                      twice ? h2 : h1, partial);

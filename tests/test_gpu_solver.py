@@ -77,6 +77,26 @@ def test_lanczos_full_size_headline(ctx):
     assert abs(r["energy"] - E_ref) <= 1e-9 * 64, (r["energy"], E_ref)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_lanczos_long_cycles_ladder(ctx, prec):
+    """Restart cycles that run past 64 steps on the full 2x32 ladder
+    superblock (D = 604708, single Gram-Schmidt pass after the local
+    recurrence): the result is an eigenvector of the oracle's FP64 product
+    to the requested residual.  One Gram-Schmidt pass on H v_j itself lost
+    orthogonality after about 55 steps here and never converged."""
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("ladder_2x32_m1024", seed=0)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    r = sb.lanczos(_dev(seeded_vector(sb.D, 0)), max_iter=1500, tol=1e-8)
+    assert r["converged"] and r["iters"] < 600, r["iters"]
+    psi = _host(r["psi"])
+    hp = OS.hpsi_blocks(desc, psi)
+    E = float(np.dot(psi, hp))
+    assert abs(np.linalg.norm(psi) - 1.0) <= 1e-12
+    assert np.linalg.norm(hp - E * psi) <= 2e-8
+    assert abs(E - r["energy"]) <= 1e-10 * abs(E)
+
+
 def test_lanczos_cap_reports_noconv(ctx):
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock("heisenberg_L16_m32", seed=0)
