@@ -740,8 +740,8 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   HIP_TRY(ctx->V.ensure((size_t)nvec * D * sizeof(double)));
   HIP_TRY(ctx->w.ensure((size_t)D * sizeof(double)));
   HIP_TRY(ctx->partial.ensure(npart * sizeof(double)));
-  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec]
-  const size_t nsmall = (size_t)5 * nvec + 8;
+  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec], g[2][nvec]
+  const size_t nsmall = (size_t)7 * nvec + 8;
   HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
   HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));
   if (ctx->host_small_n < nsmall) {
@@ -758,6 +758,7 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   double* ud = h2 + nvec;
   double* nrm2 = ud + nvec;
   double* ab = nrm2 + 8;
+  double* gbuf[2] = {ab + 2 * nvec, ab + 3 * nvec};
   double* hs = ctx->host_small;
 
   // v0 = psi0 / |psi0|
@@ -839,9 +840,12 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
       ++total;
       const bool two = j == 0 || twice;
+      // <V_i, V_j> of a single-pass step is kept for the next one (g[j & 1])
       HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
                              j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, two,
-                             two ? nullptr : ab + 2 * (j - 1) + 1, s));
+                             two ? nullptr : ab + 2 * (j - 1) + 1,
+                             (two || j < 2) ? nullptr : gbuf[(j - 1) & 1], two ? nullptr : gbuf[j & 1],
+                             s));
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
       HIP_TRY(hipMemcpyAsync(hbuf[nbuf], ab, 2 * (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1251,7 +1255,7 @@ dmrg_status dmrg_lanczos_tridiag(dmrg_sb sb, const double* v0_d, int32_t nsteps,
   for (int j = 0; j < nsteps; ++j) {
     if ((st = run_product(sb, sb->fwd, sb->prec, V + (size_t)j * D, w, 1.0, 0.0)) != DMRG_OK) return st;
     HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
-                           V + (size_t)(j + 1) * D, true, nullptr, s));
+                           V + (size_t)(j + 1) * D, true, nullptr, nullptr, nullptr, s));
   }
   std::vector<double> hs(2 * nsteps + 1);
   HIP_TRY(hipMemcpyAsync(hs.data(), ab, 2 * nsteps * sizeof(double), hipMemcpyDeviceToHost, s));

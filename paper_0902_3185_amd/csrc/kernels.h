@@ -68,14 +68,17 @@ hipError_t launch_normalise(double* dst, const double* src, const double* nrm2, 
 // Gram-Schmidt twice (h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2).
 // twice = false (nv >= 2): the local recurrence with alpha = <V_j, w> and
 // beta_{j-1} = *beta_prev (device), then one Gram-Schmidt pass on the
-// remainder, applied as w -= V h1 with the combined coefficients h1.
-// ab[0] = alpha_j (h1[j] + h2[j], or h1[j]), ab[1] = beta_j = ||w||;
-// vnext = w / beta_j (if vnext is not null).  partial needs
-// lz_partial_size(n, nv) doubles.
+// remainder, applied as w -= V h1 with the combined coefficients h1; it
+// needs <V_i, V_{j-1}> (i < j), either from gprev (the previous step's
+// gcur) or, with gprev null, from an extra set of products; gcur (if not
+// null) receives <V_i, V_j>, i <= j.  ab[0] = alpha_j (h1[j] + h2[j], or
+// h1[j]), ab[1] = beta_j = ||w||; vnext = w / beta_j (if vnext is not
+// null).  partial needs lz_partial_size(n, nv) doubles.
 size_t lz_partial_size(int64_t n, int nv);
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
-                          bool twice, const double* beta_prev, hipStream_t stream);
+                          bool twice, const double* beta_prev, const double* gprev, double* gcur,
+                          hipStream_t stream);
 
 // Record alpha_j = h1[j] + h2[j] and beta_j = sqrt(nrm2) into ab[2*it], ab[2*it+1].
 hipError_t launch_record(const double* h1, const double* h2, int j, const double* nrm2,

@@ -145,7 +145,8 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 //   finish  (alpha, beta) and v_next = w / beta
 // or the local three-term recurrence followed by one Gram-Schmidt pass,
 // w' = w - alpha V_j - beta_{j-1} V_{j-1}, w -= V (V^T w'), in two passes:
-//   dot3    partial sums of V^T w, V^T V_j and V^T V_{j-1}
+//   dotk    partial sums of V^T w and V^T V_j (and V^T V_{j-1} unless the
+//           previous step left it: it is that step's V^T V_j)
 //   reduce  the pass's coefficients (lz_reduce_local)
 //   axpy, finish  as above
 // One pass over a vector that is already orthogonal to V up to the
@@ -281,16 +282,17 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot(const double* __restrict__ 
   }
 }
 
-// Three sets of products in one pass over the basis: for s = 0, 1, 2 and
-// i < nv, partial[(s * nv + i) * gridDim.x + blockIdx.x] = the block's part
-// of <V_i, x_s> with x_0 = w, x_1 = V_{nv-1}, x_2 = V_{nv-2} (nv >= 2).  A
+// kS sets of products in one pass over the basis: for s < kS and i < nv,
+// partial[(s * nv + i) * gridDim.x + blockIdx.x] = the block's part of
+// <V_i, x_s> with x_0 = w, x_1 = V_{nv-1}, x_2 = V_{nv-2} (nv >= 2).  A
 // thread takes kE elements (256 kE per block) and the basis in batches of
-// kB vectors, loaded once and used for all three sets; the thread's
-// products are summed over its elements before the wave's butterfly.
-template <int kE, int kB>
-__global__ __launch_bounds__(kLzThreads) void lz_dot3(const double* __restrict__ V, int64_t ldv,
+// kB vectors, loaded once and used for every set; the thread's products are
+// summed over its elements before the wave's butterfly.
+template <int kE, int kB, int kS>
+__global__ __launch_bounds__(kLzThreads) void lz_dotk(const double* __restrict__ V, int64_t ldv,
                                                       int nv, const double* __restrict__ w,
                                                       int64_t n, double* __restrict__ partial) {
+  static_assert(kS == 2 || kS == 3, "two or three sets");
   __shared__ double sh[2][kLzThreads / 64][kBatch];
   static_assert(kB <= kBatch, "batch larger than the block's staging");
   const int64_t e0 = (int64_t)blockIdx.x * kLzThreads * kE + threadIdx.x;
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot3(const double* __restrict__
     ec[q] = ok[q] ? e : 0;   // in-range address for the tail block
     x[0][q] = ok[q] ? w[e] : 0.0;
     x[1][q] = ok[q] ? V[(int64_t)(nv - 1) * ldv + e] : 0.0;
-    x[2][q] = ok[q] ? V[(int64_t)(nv - 2) * ldv + e] : 0.0;
+    x[2][q] = (kS > 2 && ok[q]) ? V[(int64_t)(nv - 2) * ldv + e] : 0.0;
   }
   int i0 = 0, parity = 0;
 #pragma unroll 1
@@ -315,7 +317,7 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot3(const double* __restrict__
 #pragma unroll
       for (int q = 0; q < kE; ++q) t[b][q] = V[(int64_t)(i0 + b) * ldv + ec[q]];
 #pragma unroll 1
-    for (int s = 0; s < 3; ++s, parity ^= 1) {
+    for (int s = 0; s < kS; ++s, parity ^= 1) {
       double p[kB];
 #pragma unroll
       for (int b = 0; b < kB; ++b) {
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot3(const double* __restrict__
 #pragma unroll
       for (int q = 0; q < kE; ++q) t[b][q] = V[(int64_t)(i0 + (b < nb ? b : 0)) * ldv + ec[q]];
 #pragma unroll 1
-    for (int s = 0; s < 3; ++s, parity ^= 1) {
+    for (int s = 0; s < kS; ++s, parity ^= 1) {
       double p[kTailBatch];
 #pragma unroll
       for (int b = 0; b < kTailBatch; ++b) {
@@ -350,32 +352,44 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot3(const double* __restrict__
   }
 }
 
-constexpr int kDot3E = 1, kDot3B = 32;   // the configuration the step launches
+constexpr int kDotkE = 1, kDotkB = 32;   // the configuration the step launches
 
 // Coefficients of the single Gram-Schmidt pass that follows the local
 // three-term recurrence (see launch_lz_step): with r_i = <V_i, w>,
-// g_i = <V_i, V_j>, m_i = <V_i, V_{j-1}> (j = nv - 1, sums of lz_dot3's
-// partials), alpha = r_j and beta = *beta_prev,
+// g_i = <V_i, V_j>, m_i = <V_i, V_{j-1}> (j = nv - 1), alpha = r_j and
+// beta = *beta_prev,
 //   h[i] = r_i - alpha g_i - beta m_i + alpha [i == j] + beta [i == j-1],
 // so that w - sum_i h[i] V_i = w' - V (V^T w') for w' = w - alpha V_j -
-// beta V_{j-1}.  One block of four waves per i: the waves sum r_i, g_i, m_i
-// and r_j in parallel.
+// beta V_{j-1}.  r and g are sums of the sweep's partials; m is a third set
+// of partials (gprev null) or, for i < j, the previous step's g (gprev) and,
+// for i = j, g_{j-1}.  g is also written to gcur (if not null) for the next
+// step.  One block of four waves per i sums its rows in parallel.
 __global__ __launch_bounds__(256) void lz_reduce_local(const double* __restrict__ partial, int nbx,
                                                        int nv, const double* __restrict__ beta_prev,
+                                                       const double* __restrict__ gprev,
+                                                       double* __restrict__ gcur,
                                                        double* __restrict__ h) {
   __shared__ double sh[4];
   const int i = blockIdx.x, j = nv - 1;
   const int wave = threadIdx.x >> 6;
-  const int row = wave < 3 ? wave * nv + i : j;
-  const double t = wave_row_sum(partial + (int64_t)row * nbx, nbx);
+  // rows: wave 0 r_i, wave 1 g_i, wave 2 m_i (or g_{j-1} when i == j and gprev
+  // is given; nothing otherwise), wave 3 r_j = alpha
+  int row = -1;
+  if (wave == 0) row = i;
+  else if (wave == 1) row = nv + i;
+  else if (wave == 2) row = !gprev ? 2 * nv + i : (i == j ? nv + j - 1 : -1);
+  else row = j;
+  const double t = row >= 0 ? wave_row_sum(partial + (int64_t)row * nbx, nbx) : 0.0;
   if ((threadIdx.x & 63) == 0) sh[wave] = t;
   __syncthreads();
   if (threadIdx.x == 0) {
     const double alpha = sh[3], beta = *beta_prev;
-    double c = sh[0] - alpha * sh[1] - beta * sh[2];
+    const double m = (!gprev || i == j) ? sh[2] : gprev[i];
+    double c = sh[0] - alpha * sh[1] - beta * m;
     if (i == j) c += alpha;
     if (i == j - 1) c += beta;
     h[i] = c;
+    if (gcur) gcur[i] = sh[1];
   }
 }
 
@@ -505,7 +519,8 @@ void launch_axpy_dot(double* w, const double* V, int64_t ldv, int nv, int64_t n,
 
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
-                          bool twice, const double* beta_prev, hipStream_t stream) {
+                          bool twice, const double* beta_prev, const double* gprev, double* gcur,
+                          hipStream_t stream) {
   const int nb = lz_blocks(n);
   if (!twice && (nv < 2 || !beta_prev)) return hipErrorInvalidValue;
   if (twice) {
@@ -528,10 +543,15 @@ hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64
     }
     hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
   } else {
-    const int nb3 = (int)std::max<int64_t>(1, (n + kLzThreads * kDot3E - 1) / (kLzThreads * kDot3E));
-    hipLaunchKernelGGL((lz_dot3<kDot3E, kDot3B>), dim3(nb3), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n,
-                       partial);
-    hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(256), 0, stream, partial, nb3, nv, beta_prev, h1);
+    const int nbk = (int)std::max<int64_t>(1, (n + kLzThreads * kDotkE - 1) / (kLzThreads * kDotkE));
+    if (gprev)
+      hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 2>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv,
+                         nv, w, n, partial);
+    else
+      hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 3>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv,
+                         nv, w, n, partial);
+    hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(256), 0, stream, partial, nbk, nv, beta_prev,
+                       gprev, gcur, h1);
   }
   hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n,
                      twice ? h2 : h1, partial);
