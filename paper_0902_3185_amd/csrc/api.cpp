@@ -780,7 +780,9 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
     HIP_TRY(hipEventCreateWithFlags(&ctx->chk[1], hipEventDisableTiming));
   }
   double* hbuf[2] = {hs, hs + 2 * nvec};
-  while (!converged && total < max_iter) {
+  double* uh = hs + 4 * nvec;   // Ritz coefficients on their way to the device
+  double prev_ctol = tol;   // tolerance the previous cycle stopped at
+  for (int cycle = 0; !converged && total < max_iter; ++cycle) {
     double beta0 = 0.0;
     int nv = 0;      // basis vectors that enter the Ritz vector of this cycle
     u.clear();
@@ -861,7 +863,12 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       // thrown away.
       const bool likely = est_prev > 0.0 && est_last > 0.0 &&
                           est_last * (est_last / est_prev) <= 4.0 * ctol;
-      if (j == 0 || last || likely) {
+      // The first step of a cycle is checked at once when the cycle may end
+      // there: always in the first cycle (the start vector may already be an
+      // eigenvector), and after a cycle that ran to the final tolerance.
+      // After a cycle that stopped at its own looser tolerance the FP64
+      // residual cannot be met yet, so its check is pipelined like the rest.
+      if ((j == 0 && (cycle == 0 || prev_ctol <= tol)) || last || likely) {
         HIP_TRY(hipEventSynchronize(ctx->chk[nbuf]));
         if (evaluate(j, hbuf[nbuf]) || last) break;
       } else {
@@ -871,12 +878,15 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       nbuf ^= 1;
     }
     if (converged) break;
-    // Ritz vector of the cycle -> start of the next one
-    HIP_TRY(hipMemcpyAsync(ud, u.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
+    prev_ctol = ctol;
+    // Ritz vector of the cycle -> start of the next one.  The coefficients
+    // go through pinned memory that no later host work touches before the
+    // next cycle's first (synchronous) check, so the queue is not drained.
+    std::copy(u.begin(), u.begin() + nv, uh);
+    HIP_TRY(hipMemcpyAsync(ud, uh, nv * sizeof(double), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_combine(w, V, D, nv, ud, D, s));
     HIP_TRY(launch_multi_dot(w, 0, 1, w, D, part, nrm2, s));
     HIP_TRY(launch_normalise(V, w, nrm2, D, s));
-    HIP_TRY(hipStreamSynchronize(s));
   }
   HIP_TRY(hipMemcpyAsync(psi_d, V, (size_t)D * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
