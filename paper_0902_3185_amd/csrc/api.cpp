@@ -737,11 +737,12 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   const int nvec = per_cycle + 1;
   constexpr int kCheck = 4;
   const size_t npart = std::max(lz_partial_size(D, nvec), (size_t)vec_blocks(D));
+  const size_t nnorm = lz_norm_partials(D);
   HIP_TRY(ctx->V.ensure((size_t)nvec * D * sizeof(double)));
   HIP_TRY(ctx->w.ensure((size_t)D * sizeof(double)));
-  HIP_TRY(ctx->partial.ensure(npart * sizeof(double)));
-  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec], g[2][nvec]
-  const size_t nsmall = (size_t)7 * nvec + 8;
+  HIP_TRY(ctx->partial.ensure((npart + 2 * nnorm) * sizeof(double)));
+  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec], g[2][nvec], scale[8]
+  const size_t nsmall = (size_t)7 * nvec + 16;
   HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
   HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));
   if (ctx->host_small_n < nsmall) {
@@ -759,6 +760,10 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   double* nrm2 = ud + nvec;
   double* ab = nrm2 + 8;
   double* gbuf[2] = {ab + 2 * nvec, ab + 3 * nvec};
+  double* scale = ab + 4 * nvec;
+  // partial sums of the norm of a single-pass step's (unnormalised) new
+  // vector, by step parity: step j writes [j & 1], step j + 1 reads it
+  double* npb[2] = {part + npart, part + npart + nnorm};
   double* hs = ctx->host_small;
 
   // v0 = psi0 / |psi0|
@@ -842,14 +847,22 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
       ++total;
       const bool two = j == 0 || twice;
-      // <V_i, V_j> of a single-pass step is kept for the next one (g[j & 1])
-      HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
-                             j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr, two,
-                             two ? nullptr : ab + 2 * (j - 1) + 1,
-                             (two || j < 2) ? nullptr : gbuf[(j - 1) & 1], two ? nullptr : gbuf[j & 1],
-                             s));
+      double* vnext = j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr;
+      if (two) {
+        HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j, vnext, s));
+      } else {
+        // single pass; the new vector stays unnormalised until the next
+        // step, which normalises it in place (no separate finishing launch);
+        // <V_i, V_j> is kept for the next step (g[j & 1])
+        HIP_TRY(launch_lz_step_pending(w, V, D, j + 1, D, h1, part, j >= 2 ? npb[(j - 1) & 1] : nullptr,
+                                       j >= 2 ? nullptr : ab + 2 * (j - 1) + 1, npb[j & 1], scale,
+                                       ab + 2 * j, j >= 2 ? gbuf[(j - 1) & 1] : nullptr, gbuf[j & 1],
+                                       vnext, s));
+      }
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
+      // a single-pass step's beta_j is otherwise formed by the next step
+      if (!two) HIP_TRY(launch_lz_record_norm(npb[j & 1], D, ab + 2 * j + 1, s));
       HIP_TRY(hipMemcpyAsync(hbuf[nbuf], ab, 2 * (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipEventRecord(ctx->chk[nbuf], s));
       if (pend >= 0) {   // the previous check: its copy is behind older steps only
@@ -1264,8 +1277,7 @@ dmrg_status dmrg_lanczos_tridiag(dmrg_sb sb, const double* v0_d, int32_t nsteps,
   HIP_TRY(launch_normalise(V, v0_d, nrm2, D, s));
   for (int j = 0; j < nsteps; ++j) {
     if ((st = run_product(sb, sb->fwd, sb->prec, V + (size_t)j * D, w, 1.0, 0.0)) != DMRG_OK) return st;
-    HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j,
-                           V + (size_t)(j + 1) * D, true, nullptr, nullptr, nullptr, s));
+    HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j, V + (size_t)(j + 1) * D, s));
   }
   std::vector<double> hs(2 * nsteps + 1);
   HIP_TRY(hipMemcpyAsync(hs.data(), ab, 2 * nsteps * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -64,21 +64,38 @@ hipError_t launch_normalise(double* dst, const double* src, const double* nrm2, 
                             hipStream_t stream);
 
 // One step of the Lanczos recursion against the nv basis vectors
-// V_0..V_{nv-1} (V_j = V_{nv-1} the current one).  twice = true: classical
-// Gram-Schmidt twice (h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2).
-// twice = false (nv >= 2): the local recurrence with alpha = <V_j, w> and
-// beta_{j-1} = *beta_prev (device), then one Gram-Schmidt pass on the
-// remainder, applied as w -= V h1 with the combined coefficients h1; it
-// needs <V_i, V_{j-1}> (i < j), either from gprev (the previous step's
-// gcur) or, with gprev null, from an extra set of products; gcur (if not
-// null) receives <V_i, V_j>, i <= j.  ab[0] = alpha_j (h1[j] + h2[j], or
-// h1[j]), ab[1] = beta_j = ||w||; vnext = w / beta_j (if vnext is not
+// V_0..V_{nv-1} (V_j = V_{nv-1} the current one), by classical Gram-Schmidt
+// twice: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2.  ab[0] = alpha_j =
+// h1[j] + h2[j], ab[1] = beta_j = ||w||; vnext = w / beta_j (if vnext is not
 // null).  partial needs lz_partial_size(n, nv) doubles.
 size_t lz_partial_size(int64_t n, int nv);
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
-                          bool twice, const double* beta_prev, const double* gprev, double* gcur,
                           hipStream_t stream);
+
+// A single-pass step (nv >= 2): the local three-term recurrence (alpha_j =
+// <v_j, H v_j>, beta_{j-1}) followed by one Gram-Schmidt pass on the
+// remainder, applied as one combined update; the pass needs <V_i, V_{j-1}>
+// (i < j), either from gprev (the previous step's gcur) or, with gprev
+// null, from an extra set of products.  It leaves its new vector
+// unnormalised: out (if not null) receives x = H v_j - (recurrence and pass
+// terms), nout its partial sums of ||x||^2 (lz_norm_partials(n) of them);
+// the next step normalises it.  The current vector V_j is either stored
+// normalised (npend null, beta_{j-1} = *beta_prev) or stored unnormalised
+// by the previous such step (npend = that step's nout): then w = H u for
+// the stored u, the step normalises V_j in place and writes ab[-1] =
+// beta_{j-1} = ||u||.  ab[0] = alpha_j, *scale = 1/||u|| (or 1), h the
+// coefficients, gcur (if not null) <V_i, V_j>, i <= j.  w is not
+// modified.
+size_t lz_norm_partials(int64_t n);
+hipError_t launch_lz_step_pending(double* w, double* V, int64_t ldv, int nv, int64_t n, double* h,
+                                  double* partial, const double* npend, const double* beta_prev,
+                                  double* nout, double* scale, double* ab, const double* gprev,
+                                  double* gcur, double* out, hipStream_t stream);
+
+// *out = sqrt(sum of the lz_norm_partials(n) partial sums at npart), in the
+// order launch_lz_step_pending adds them.
+hipError_t launch_lz_record_norm(const double* npart, int64_t n, double* out, hipStream_t stream);
 
 // Record alpha_j = h1[j] + h2[j] and beta_j = sqrt(nrm2) into ab[2*it], ab[2*it+1].
 hipError_t launch_record(const double* h1, const double* h2, int j, const double* nrm2,

@@ -148,7 +148,10 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 //   dotk    partial sums of V^T w and V^T V_j (and V^T V_{j-1} unless the
 //           previous step left it: it is that step's V^T V_j)
 //   reduce  the pass's coefficients (lz_reduce_local)
-//   axpy, finish  as above
+//   axpy    the combined update and partial sums of ||w||^2 (lz_axpy_local)
+// where the new vector is left unnormalised: the next step's reduce sums its
+// norm and that step's passes scale it on the fly (and write it back
+// normalised), so a single-pass step needs no finishing launch.
 // One pass over a vector that is already orthogonal to V up to the
 // recurrence's small remainder keeps the basis orthogonal to working
 // precision; one pass over w itself would not (its error grows by about
@@ -171,6 +174,8 @@ int lz_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kLzThreads - 1)
 size_t lz_partial_size(int64_t n, int nv) {
   return (size_t)3 * std::max(nv, 1) * (size_t)lz_blocks(n);
 }
+
+size_t lz_norm_partials(int64_t n) { return (size_t)lz_blocks(n); }
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -355,41 +360,71 @@ __global__ __launch_bounds__(kLzThreads) void lz_dotk(const double* __restrict__
 constexpr int kDotkE = 1, kDotkB = 32;   // the configuration the step launches
 
 // Coefficients of the single Gram-Schmidt pass that follows the local
-// three-term recurrence (see launch_lz_step): with r_i = <V_i, w>,
-// g_i = <V_i, V_j>, m_i = <V_i, V_{j-1}> (j = nv - 1), alpha = r_j and
-// beta = *beta_prev,
+// three-term recurrence (see launch_lz_step).  With j = nv - 1, the true
+// current vector v_j = s u where u is the stored V_j and s = 1 / ||u|| when
+// u was left unnormalised (npend: the previous step's partial sums of
+// ||u||^2) or s = 1 otherwise; w = H u.  Then r_i = <V_i, H v_j> and
+// g_i = <V_i, v_j> come from the sweep's partial sums times s (times s
+// again for i = j), alpha = r_j, beta = ||u|| when pending or *beta_prev,
+// m_i = <V_i, V_{j-1}> is a third set of partials (gprev null) or, for
+// i < j, the previous step's g (gprev) and, for i = j, g_{j-1}, and
 //   h[i] = r_i - alpha g_i - beta m_i + alpha [i == j] + beta [i == j-1],
-// so that w - sum_i h[i] V_i = w' - V (V^T w') for w' = w - alpha V_j -
-// beta V_{j-1}.  r and g are sums of the sweep's partials; m is a third set
-// of partials (gprev null) or, for i < j, the previous step's g (gprev) and,
-// for i = j, g_{j-1}.  g is also written to gcur (if not null) for the next
-// step.  One block of four waves per i sums its rows in parallel.
-__global__ __launch_bounds__(256) void lz_reduce_local(const double* __restrict__ partial, int nbx,
+// so that s w - sum_i h[i] v_i = w' - V (V^T w') for w' = H v_j - alpha v_j
+// - beta V_{j-1}.  g goes to gcur (if not null) for the next step; block j
+// writes s to *scale, beta to *beta_out (when pending) and alpha_j = h[j]
+// to *alpha_out (scale and alpha_out may be null).  One block of five waves
+// per i sums its rows in parallel.
+__global__ __launch_bounds__(320) void lz_reduce_local(const double* __restrict__ partial, int nbx,
                                                        int nv, const double* __restrict__ beta_prev,
                                                        const double* __restrict__ gprev,
                                                        double* __restrict__ gcur,
-                                                       double* __restrict__ h) {
-  __shared__ double sh[4];
+                                                       double* __restrict__ h,
+                                                       const double* __restrict__ npend, int nnp,
+                                                       double* __restrict__ scale,
+                                                       double* __restrict__ beta_out,
+                                                       double* __restrict__ alpha_out) {
+  __shared__ double sh[5];
   const int i = blockIdx.x, j = nv - 1;
   const int wave = threadIdx.x >> 6;
-  // rows: wave 0 r_i, wave 1 g_i, wave 2 m_i (or g_{j-1} when i == j and gprev
-  // is given; nothing otherwise), wave 3 r_j = alpha
-  int row = -1;
-  if (wave == 0) row = i;
-  else if (wave == 1) row = nv + i;
-  else if (wave == 2) row = !gprev ? 2 * nv + i : (i == j ? nv + j - 1 : -1);
-  else row = j;
-  const double t = row >= 0 ? wave_row_sum(partial + (int64_t)row * nbx, nbx) : 0.0;
+  // rows: wave 0 R_i, wave 1 G_i, wave 2 m_i (or G_{j-1} when i == j and gprev
+  // is given; nothing otherwise), wave 3 R_j, wave 4 ||u||^2 (pending only)
+  const double* row = nullptr;
+  int cnt = nbx;
+  if (wave == 0) row = partial + (int64_t)i * nbx;
+  else if (wave == 1) row = partial + (int64_t)(nv + i) * nbx;
+  else if (wave == 2) {
+    if (!gprev) row = partial + (int64_t)(2 * nv + i) * nbx;
+    else if (i == j) row = partial + (int64_t)(nv + j - 1) * nbx;
+  } else if (wave == 3) row = partial + (int64_t)j * nbx;
+  else if (npend) {
+    row = npend;
+    cnt = nnp;
+  }
+  const double t = row ? wave_row_sum(row, cnt) : 0.0;
   if ((threadIdx.x & 63) == 0) sh[wave] = t;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double alpha = sh[3], beta = *beta_prev;
-    const double m = (!gprev || i == j) ? sh[2] : gprev[i];
-    double c = sh[0] - alpha * sh[1] - beta * m;
+    double s = 1.0, beta = 0.0;
+    if (npend) {
+      beta = sqrt(sh[4] > 0.0 ? sh[4] : 0.0);
+      s = beta > 0.0 ? 1.0 / beta : 0.0;
+    } else {
+      beta = *beta_prev;
+    }
+    const double alpha = s * s * sh[3];
+    const double r = (i == j ? s * s : s) * sh[0];
+    const double g = (i == j ? s * s : s) * sh[1];
+    const double m = !gprev ? sh[2] : (i == j ? s * sh[2] : gprev[i]);
+    double c = r - alpha * g - beta * m;
     if (i == j) c += alpha;
     if (i == j - 1) c += beta;
     h[i] = c;
-    if (gcur) gcur[i] = sh[1];
+    if (gcur) gcur[i] = g;
+    if (i == j) {
+      if (scale) *scale = s;
+      if (npend) *beta_out = beta;
+      if (alpha_out) *alpha_out = c;
+    }
   }
 }
 
@@ -447,9 +482,49 @@ __global__ __launch_bounds__(kLzThreads) void lz_axpy(double* __restrict__ w,
   if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
+// The update of a single-pass step: x = s w - sum_{i<j} h[i] V_i - h[j] s u
+// (j = nv - 1, u the stored V_j, s = *scale); with pending, V_j is replaced
+// by s u in place.  x goes to out (if not null) unnormalised, and
+// partial[blockIdx.x] = the block's part of ||x||^2.
+__global__ __launch_bounds__(kLzThreads) void lz_axpy_local(const double* __restrict__ w,
+                                                            double* __restrict__ V, int64_t ldv,
+                                                            int nv, int64_t n,
+                                                            const double* __restrict__ h,
+                                                            const double* __restrict__ scale,
+                                                            bool pending, double* __restrict__ out,
+                                                            double* __restrict__ partial) {
+  const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
+  const bool ok = e < n;
+  const int64_t ec = ok ? e : 0;
+  const int j = nv - 1;
+  const double sc = *scale;
+  const double u = V[(int64_t)j * ldv + ec];
+  double x = ok ? sc * w[ec] : 0.0;
+  x = axpy_walk(x, V + ec, ldv, j, h);
+  const double vj = pending ? sc * u : u;
+  x -= h[j] * vj;
+  if (ok) {
+    if (pending) V[(int64_t)j * ldv + e] = vj;
+    if (out) out[e] = x;
+  }
+  __shared__ double sh[kLzThreads / 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double q = wave_sum(ok ? x * x : 0.0);
+  if (lane == 0) sh[wave] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// *out = sqrt(sum of partial[0..np)), summed as lz_reduce_local sums them.
+__global__ __launch_bounds__(64) void lz_record_norm(const double* __restrict__ partial, int np,
+                                                     double* __restrict__ out) {
+  const double t = wave_row_sum(partial, np);
+  if (threadIdx.x == 0) *out = sqrt(t > 0.0 ? t : 0.0);
+}
+
 // beta = sqrt(sum of partial[0..np)) (every block adds the same partials in
-// the same order); block 0 writes ab[0] = h1[j] (+ h2[j] when h2 is given)
-// and ab[1] = beta; v_next = w / beta where v_next is given.
+// the same order); block 0 writes ab[0] = h1[j] + h2[j] and ab[1] = beta;
+// v_next = w / beta where v_next is given.
 __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
                                                       const double* __restrict__ w,
                                                       const double* __restrict__ partial, int np,
@@ -468,7 +543,7 @@ __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
   __syncthreads();
   const double b = beta;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ab[0] = h2 ? h1[j] + h2[j] : h1[j];
+    ab[0] = h1[j] + h2[j];
     ab[1] = b;
   }
   if (!v) return;
@@ -519,45 +594,58 @@ void launch_axpy_dot(double* w, const double* V, int64_t ldv, int nv, int64_t n,
 
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
-                          bool twice, const double* beta_prev, const double* gprev, double* gcur,
                           hipStream_t stream) {
+  if (nv < 1) return hipErrorInvalidValue;
   const int nb = lz_blocks(n);
-  if (!twice && (nv < 2 || !beta_prev)) return hipErrorInvalidValue;
-  if (twice) {
-    hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
-    hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h1);
-    if (nv <= kFusedMaxNv) {
-      // first update and second products in one pass over the basis
-      if (nv <= 8)
-        launch_axpy_dot<8>(w, V, ldv, nv, n, h1, partial, nb, stream);
-      else if (nv <= 16)
-        launch_axpy_dot<16>(w, V, ldv, nv, n, h1, partial, nb, stream);
-      else if (nv <= 32)
-        launch_axpy_dot<32>(w, V, ldv, nv, n, h1, partial, nb, stream);
-      else
-        launch_axpy_dot<64>(w, V, ldv, nv, n, h1, partial, nb, stream);
-    } else {
-      hipLaunchKernelGGL(lz_axpy<false>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
-                         partial);
-      hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
-    }
-    hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
-  } else {
-    const int nbk = (int)std::max<int64_t>(1, (n + kLzThreads * kDotkE - 1) / (kLzThreads * kDotkE));
-    if (gprev)
-      hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 2>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv,
-                         nv, w, n, partial);
+  hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
+  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h1);
+  if (nv <= kFusedMaxNv) {
+    // first update and second products in one pass over the basis
+    if (nv <= 8)
+      launch_axpy_dot<8>(w, V, ldv, nv, n, h1, partial, nb, stream);
+    else if (nv <= 16)
+      launch_axpy_dot<16>(w, V, ldv, nv, n, h1, partial, nb, stream);
+    else if (nv <= 32)
+      launch_axpy_dot<32>(w, V, ldv, nv, n, h1, partial, nb, stream);
     else
-      hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 3>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv,
-                         nv, w, n, partial);
-    hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(256), 0, stream, partial, nbk, nv, beta_prev,
-                       gprev, gcur, h1);
+      launch_axpy_dot<64>(w, V, ldv, nv, n, h1, partial, nb, stream);
+  } else {
+    hipLaunchKernelGGL(lz_axpy<false>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h1,
+                       partial);
+    hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
   }
-  hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n,
-                     twice ? h2 : h1, partial);
+  hipLaunchKernelGGL(lz_reduce, dim3(nv), dim3(64), 0, stream, partial, nb, h2);
+  hipLaunchKernelGGL(lz_axpy<true>, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h2,
+                     partial);
   const unsigned nfin = vnext ? (unsigned)((n + kThreads - 1) / kThreads) : 1u;
-  hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, nb, h1,
-                     twice ? h2 : nullptr, nv - 1, ab, n);
+  hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, nb, h1, h2,
+                     nv - 1, ab, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_lz_step_pending(double* w, double* V, int64_t ldv, int nv, int64_t n, double* h,
+                                  double* partial, const double* npend, const double* beta_prev,
+                                  double* nout, double* scale, double* ab, const double* gprev,
+                                  double* gcur, double* out, hipStream_t stream) {
+  if (nv < 2 || !nout || !scale || (!npend && !beta_prev)) return hipErrorInvalidValue;
+  const int nb = lz_blocks(n);
+  const int nbk = (int)std::max<int64_t>(1, (n + kLzThreads * kDotkE - 1) / (kLzThreads * kDotkE));
+  if (gprev)
+    hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 2>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv,
+                       nv, w, n, partial);
+  else
+    hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 3>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv,
+                       nv, w, n, partial);
+  // beta_{j-1} into ab[-1] (when pending), alpha_j into ab[0]
+  hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(320), 0, stream, partial, nbk, nv, beta_prev,
+                     gprev, gcur, h, npend, nb, scale, ab - 1, ab);
+  hipLaunchKernelGGL(lz_axpy_local, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h, scale,
+                     npend != nullptr, out, nout);
+  return hipGetLastError();
+}
+
+hipError_t launch_lz_record_norm(const double* npart, int64_t n, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(lz_record_norm, dim3(1), dim3(64), 0, stream, npart, lz_blocks(n), out);
   return hipGetLastError();
 }
 
