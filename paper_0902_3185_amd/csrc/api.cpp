@@ -741,8 +741,8 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   HIP_TRY(ctx->V.ensure((size_t)nvec * D * sizeof(double)));
   HIP_TRY(ctx->w.ensure((size_t)D * sizeof(double)));
   HIP_TRY(ctx->partial.ensure((npart + 2 * nnorm) * sizeof(double)));
-  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec], g[2][nvec], scale[8]
-  const size_t nsmall = (size_t)7 * nvec + 16;
+  // small: h1[nvec], h2[nvec], u[nvec], nrm2[8], ab[2*nvec], scale[8]
+  const size_t nsmall = (size_t)5 * nvec + 16;
   HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
   HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));
   if (ctx->host_small_n < nsmall) {
@@ -759,8 +759,7 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   double* ud = h2 + nvec;
   double* nrm2 = ud + nvec;
   double* ab = nrm2 + 8;
-  double* gbuf[2] = {ab + 2 * nvec, ab + 3 * nvec};
-  double* scale = ab + 4 * nvec;
+  double* scale = ab + 2 * nvec;
   // partial sums of the norm of a single-pass step's (unnormalised) new
   // vector, by step parity: step j writes [j & 1], step j + 1 reads it
   double* npb[2] = {part + npart, part + npart + nnorm};
@@ -795,10 +794,18 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
     double ctol = tol;                   // this cycle's stopping residual
     double est_prev = -1.0, est_last = -1.0;   // the last two evaluated estimates
     // The first step of a cycle orthogonalises by classical Gram-Schmidt
-    // twice; later steps subtract the local three-term recurrence (alpha_j
-    // V_j + beta_{j-1} V_{j-1}) and run one Gram-Schmidt pass on the
-    // remainder, which keeps the basis orthogonal to working precision at
-    // two passes over it instead of three.  A basis that is not small
+    // twice.  After it, odd steps subtract the local three-term recurrence
+    // (alpha_j V_j + beta_{j-1} V_{j-1}) and run one Gram-Schmidt pass on
+    // the remainder (two passes over the basis instead of three); even steps
+    // subtract the recurrence alone and do not touch the rest of the basis.
+    // A pass on every other step keeps the basis semi-orthogonal (periodic
+    // reorthogonalisation in the sense of Grcar and of Simon's analysis of
+    // semi-orthogonal Lanczos bases): the loss of orthogonality that one
+    // recurrence-only step lets grow is removed by the next pass before it
+    // is amplified again, so the overlaps stay near 1e-7 with reduced
+    // precision products (two recurrence-only steps in a row let them grow
+    // geometrically).  Every cycle's result is certified by the FP64
+    // residual of the next cycle's first step.  A basis that is not small
     // against the dimension always runs two full passes: the Krylov space may
     // be exhausted (or confined to a small invariant subspace) within the
     // cycle, and only they leave the vanishing beta that ends the recursion
@@ -850,14 +857,17 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       double* vnext = j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr;
       if (two) {
         HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j, vnext, s));
-      } else {
-        // single pass; the new vector stays unnormalised until the next
-        // step, which normalises it in place (no separate finishing launch);
-        // <V_i, V_j> is kept for the next step (g[j & 1])
-        HIP_TRY(launch_lz_step_pending(w, V, D, j + 1, D, h1, part, j >= 2 ? npb[(j - 1) & 1] : nullptr,
+      } else if (j & 1) {
+        // the recurrence and one pass against the basis; the new vector
+        // stays unnormalised until the next step, which normalises it in
+        // place (no separate finishing launch)
+        HIP_TRY(launch_lz_step_onepass(w, V, D, j + 1, D, h1, part, j >= 2 ? npb[(j - 1) & 1] : nullptr,
                                        j >= 2 ? nullptr : ab + 2 * (j - 1) + 1, npb[j & 1], scale,
-                                       ab + 2 * j, j >= 2 ? gbuf[(j - 1) & 1] : nullptr, gbuf[j & 1],
-                                       vnext, s));
+                                       ab + 2 * j, vnext, s));
+      } else {
+        // the recurrence alone
+        HIP_TRY(launch_lz_step_recurrence(w, V, D, j + 1, D, part, npb[(j - 1) & 1], npb[j & 1],
+                                          ab + 2 * j, vnext, s));
       }
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;

@@ -75,26 +75,37 @@ hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64
 
 // A single-pass step (nv >= 2): the local three-term recurrence (alpha_j =
 // <v_j, H v_j>, beta_{j-1}) followed by one Gram-Schmidt pass on the
-// remainder, applied as one combined update; the pass needs <V_i, V_{j-1}>
-// (i < j), either from gprev (the previous step's gcur) or, with gprev
-// null, from an extra set of products.  It leaves its new vector
+// remainder, applied as one combined update whose coefficients come from one
+// sweep for V^T w and V^T V_j; V_{j-1} must have left such a step (or a
+// two-pass one) as its new vector.  It leaves its new vector
 // unnormalised: out (if not null) receives x = H v_j - (recurrence and pass
 // terms), nout its partial sums of ||x||^2 (lz_norm_partials(n) of them);
 // the next step normalises it.  The current vector V_j is either stored
 // normalised (npend null, beta_{j-1} = *beta_prev) or stored unnormalised
-// by the previous such step (npend = that step's nout): then w = H u for
-// the stored u, the step normalises V_j in place and writes ab[-1] =
+// by the previous step (npend = that step's nout): then w = H u for the
+// stored u, the step normalises V_j in place and writes ab[-1] =
 // beta_{j-1} = ||u||.  ab[0] = alpha_j, *scale = 1/||u|| (or 1), h the
-// coefficients, gcur (if not null) <V_i, V_j>, i <= j.  w is not
+// coefficients.  partial needs lz_partial_size(n, nv) doubles.  w is not
 // modified.
 size_t lz_norm_partials(int64_t n);
-hipError_t launch_lz_step_pending(double* w, double* V, int64_t ldv, int nv, int64_t n, double* h,
+hipError_t launch_lz_step_onepass(double* w, double* V, int64_t ldv, int nv, int64_t n, double* h,
                                   double* partial, const double* npend, const double* beta_prev,
-                                  double* nout, double* scale, double* ab, const double* gprev,
-                                  double* gcur, double* out, hipStream_t stream);
+                                  double* nout, double* scale, double* ab, double* out,
+                                  hipStream_t stream);
+
+// A recurrence-only step (nv >= 2, j = nv - 1): no pass over the basis.
+// V_j is stored unnormalised by the previous step (npend = that step's
+// nout) and w = H u for the stored u; the step normalises V_j in place and
+// forms x = H v_j - alpha_j v_j - beta_{j-1} V_{j-1}, unnormalised, into out
+// (if not null) with its partial sums of ||x||^2 in nout; ab[-1] =
+// beta_{j-1} = ||u||, ab[0] = alpha_j = <v_j, H v_j>.  partial needs
+// lz_norm_partials(n) doubles.  w is not modified.
+hipError_t launch_lz_step_recurrence(const double* w, double* V, int64_t ldv, int nv, int64_t n,
+                                     double* partial, const double* npend, double* nout,
+                                     double* ab, double* out, hipStream_t stream);
 
 // *out = sqrt(sum of the lz_norm_partials(n) partial sums at npart), in the
-// order launch_lz_step_pending adds them.
+// order launch_lz_step_onepass and launch_lz_step_recurrence add them.
 hipError_t launch_lz_record_norm(const double* npart, int64_t n, double* out, hipStream_t stream);
 
 // Record alpha_j = h1[j] + h2[j] and beta_j = sqrt(nrm2) into ab[2*it], ab[2*it+1].

@@ -145,17 +145,21 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 //   finish  (alpha, beta) and v_next = w / beta
 // or the local three-term recurrence followed by one Gram-Schmidt pass,
 // w' = w - alpha V_j - beta_{j-1} V_{j-1}, w -= V (V^T w'), in two passes:
-//   dotk    partial sums of V^T w and V^T V_j (and V^T V_{j-1} unless the
-//           previous step left it: it is that step's V^T V_j)
+//   dotk    partial sums of V^T w and V^T V_j in one sweep
 //   reduce  the pass's coefficients (lz_reduce_local)
 //   axpy    the combined update and partial sums of ||w||^2 (lz_axpy_local)
-// where the new vector is left unnormalised: the next step's reduce sums its
-// norm and that step's passes scale it on the fly (and write it back
-// normalised), so a single-pass step needs no finishing launch.
+// or the recurrence alone, w' = w - alpha V_j - beta_{j-1} V_{j-1}, which
+// reads three vectors and not the basis:
+//   dot     partial sums of <V_j, w> (lz_dot_uw)
+//   update  alpha, w' and partial sums of ||w'||^2 (lz_local_update).
+// In the last two forms the new vector is left unnormalised: the next
+// step sums its norm and scales it on the fly (and writes it back
+// normalised), so neither needs a finishing launch.
 // One pass over a vector that is already orthogonal to V up to the
 // recurrence's small remainder keeps the basis orthogonal to working
 // precision; one pass over w itself would not (its error grows by about
-// ||H V_j|| / beta_j per step).
+// ||H V_j|| / beta_j per step).  The solver alternates the pass and the
+// recurrence alone, which keeps the basis semi-orthogonal.
 // Every pass gives each thread one element of w (256 per block, a grid of
 // ceil(n / 256) blocks) and walks the basis vectors in batches whose loads
 // are all issued before the first use, so a wave keeps a batch of basis
@@ -172,7 +176,7 @@ constexpr int kFusedMaxNv = 64;   // basis size up to which axpy and dot share a
 int lz_blocks(int64_t n) { return (int)std::max<int64_t>(1, (n + kLzThreads - 1) / kLzThreads); }
 
 size_t lz_partial_size(int64_t n, int nv) {
-  return (size_t)3 * std::max(nv, 1) * (size_t)lz_blocks(n);
+  return (size_t)2 * std::max(nv, 1) * (size_t)lz_blocks(n);
 }
 
 size_t lz_norm_partials(int64_t n) { return (size_t)lz_blocks(n); }
@@ -360,24 +364,23 @@ __global__ __launch_bounds__(kLzThreads) void lz_dotk(const double* __restrict__
 constexpr int kDotkE = 1, kDotkB = 32;   // the configuration the step launches
 
 // Coefficients of the single Gram-Schmidt pass that follows the local
-// three-term recurrence (see launch_lz_step).  With j = nv - 1, the true
-// current vector v_j = s u where u is the stored V_j and s = 1 / ||u|| when
-// u was left unnormalised (npend: the previous step's partial sums of
-// ||u||^2) or s = 1 otherwise; w = H u.  Then r_i = <V_i, H v_j> and
-// g_i = <V_i, v_j> come from the sweep's partial sums times s (times s
-// again for i = j), alpha = r_j, beta = ||u|| when pending or *beta_prev,
-// m_i = <V_i, V_{j-1}> is a third set of partials (gprev null) or, for
-// i < j, the previous step's g (gprev) and, for i = j, g_{j-1}, and
+// three-term recurrence (see launch_lz_step_onepass).  With j = nv - 1, the
+// true current vector v_j = s u where u is the stored V_j and s = 1 / ||u||
+// when u was left unnormalised (npend: the previous step's partial sums of
+// ||u||^2) or s = 1 otherwise; w = H u.  The sweep's two sets of partial
+// sums give r_i = <V_i, H v_j> and g_i = <V_i, v_j> (times s, and times s
+// again for i = j); alpha = r_j, beta = ||u|| when pending or *beta_prev.
+// m_i = <V_i, V_{j-1}> is 1 for i = j - 1, g_{j-1} for i = j and 0 below:
+// V_{j-1} left the previous pass orthogonal to V_0..V_{j-2} up to second
+// order (the products of the pass's small coefficients and the basis'
+// small overlaps), which this pass need not see.  Then
 //   h[i] = r_i - alpha g_i - beta m_i + alpha [i == j] + beta [i == j-1],
 // so that s w - sum_i h[i] v_i = w' - V (V^T w') for w' = H v_j - alpha v_j
-// - beta V_{j-1}.  g goes to gcur (if not null) for the next step; block j
-// writes s to *scale, beta to *beta_out (when pending) and alpha_j = h[j]
-// to *alpha_out (scale and alpha_out may be null).  One block of five waves
-// per i sums its rows in parallel.
+// - beta V_{j-1}.  Block j writes s to *scale, beta to *beta_out (when
+// pending) and alpha_j = h[j] to *alpha_out.  One block of five waves per i
+// sums its rows in parallel.
 __global__ __launch_bounds__(320) void lz_reduce_local(const double* __restrict__ partial, int nbx,
                                                        int nv, const double* __restrict__ beta_prev,
-                                                       const double* __restrict__ gprev,
-                                                       double* __restrict__ gcur,
                                                        double* __restrict__ h,
                                                        const double* __restrict__ npend, int nnp,
                                                        double* __restrict__ scale,
@@ -386,16 +389,13 @@ __global__ __launch_bounds__(320) void lz_reduce_local(const double* __restrict_
   __shared__ double sh[5];
   const int i = blockIdx.x, j = nv - 1;
   const int wave = threadIdx.x >> 6;
-  // rows: wave 0 R_i, wave 1 G_i, wave 2 m_i (or G_{j-1} when i == j and gprev
-  // is given; nothing otherwise), wave 3 R_j, wave 4 ||u||^2 (pending only)
+  // rows: wave 0 R_i, wave 1 G_i, wave 2 G_{j-1} (block j only), wave 3
+  // R_j, wave 4 ||u||^2 (pending only)
   const double* row = nullptr;
   int cnt = nbx;
-  if (wave == 0) row = partial + (int64_t)i * nbx;
-  else if (wave == 1) row = partial + (int64_t)(nv + i) * nbx;
-  else if (wave == 2) {
-    if (!gprev) row = partial + (int64_t)(2 * nv + i) * nbx;
-    else if (i == j) row = partial + (int64_t)(nv + j - 1) * nbx;
-  } else if (wave == 3) row = partial + (int64_t)j * nbx;
+  if (wave < 2) row = partial + (int64_t)(wave * nv + i) * nbx;
+  else if (wave == 2) row = i == j ? partial + (int64_t)(nv + j - 1) * nbx : nullptr;
+  else if (wave == 3) row = partial + (int64_t)j * nbx;
   else if (npend) {
     row = npend;
     cnt = nnp;
@@ -414,16 +414,15 @@ __global__ __launch_bounds__(320) void lz_reduce_local(const double* __restrict_
     const double alpha = s * s * sh[3];
     const double r = (i == j ? s * s : s) * sh[0];
     const double g = (i == j ? s * s : s) * sh[1];
-    const double m = !gprev ? sh[2] : (i == j ? s * sh[2] : gprev[i]);
+    const double m = i == j ? s * sh[2] : (i == j - 1 ? 1.0 : 0.0);
     double c = r - alpha * g - beta * m;
     if (i == j) c += alpha;
     if (i == j - 1) c += beta;
     h[i] = c;
-    if (gcur) gcur[i] = g;
     if (i == j) {
-      if (scale) *scale = s;
+      *scale = s;
       if (npend) *beta_out = beta;
-      if (alpha_out) *alpha_out = c;
+      *alpha_out = c;
     }
   }
 }
@@ -513,6 +512,67 @@ __global__ __launch_bounds__(kLzThreads) void lz_axpy_local(const double* __rest
   if (lane == 0) sh[wave] = q;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// partial[blockIdx.x] = the block's part of <u, w>.
+__global__ __launch_bounds__(kLzThreads) void lz_dot_uw(const double* __restrict__ u,
+                                                        const double* __restrict__ w, int64_t n,
+                                                        double* __restrict__ partial) {
+  const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
+  __shared__ double sh[kLzThreads / 64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const double t = wave_sum(e < n ? u[e] * w[e] : 0.0);
+  if (lane == 0) sh[wave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// The update of a recurrence-only step (j >= 1): V_j is stored unnormalised
+// as u, npend holds the partial sums of ||u||^2 and dpart those of <u, w>
+// for w = H u (np of each).  With beta_{j-1} = ||u||, s = 1 / ||u|| and
+// alpha_j = s^2 <u, w>:  x = s w - alpha_j s u - beta_{j-1} V_{j-1}; V_j is
+// replaced by s u in place, x goes to out (if not null) unnormalised and
+// nout[blockIdx.x] = the block's part of ||x||^2; block 0 writes ab[-1] =
+// beta_{j-1} and ab[0] = alpha_j.  Every block adds the same partials in
+// the same order, so all of them use the same s and alpha_j.
+__global__ __launch_bounds__(kLzThreads) void lz_local_update(
+    const double* __restrict__ w, double* __restrict__ V, int64_t ldv, int j, int64_t n,
+    const double* __restrict__ dpart, const double* __restrict__ npend, int np,
+    double* __restrict__ out, double* __restrict__ nout, double* __restrict__ ab) {
+  __shared__ double sums[2];
+  __shared__ double sh[kLzThreads / 64];
+  const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
+  const bool ok = e < n;
+  const int64_t ec = ok ? e : 0;
+  // the thread's elements are loaded before the sums, so the latencies overlap
+  const double wi = w[ec];
+  const double ui = V[(int64_t)j * ldv + ec];
+  const double pi = V[(int64_t)(j - 1) * ldv + ec];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < 2) {
+    const double t = wave_row_sum(wave == 0 ? npend : dpart, np);
+    if (lane == 0) sums[wave] = t;
+  }
+  __syncthreads();
+  const double beta = sqrt(sums[0] > 0.0 ? sums[0] : 0.0);
+  const double sc = beta > 0.0 ? 1.0 / beta : 0.0;
+  const double alpha = sc * sc * sums[1];
+  const double vj = sc * ui;
+  const double x = ok ? sc * wi - alpha * vj - beta * pi : 0.0;
+  if (ok) {
+    V[(int64_t)j * ldv + e] = vj;
+    if (out) out[e] = x;
+  }
+  const double q = wave_sum(x * x);
+  if (lane == 0) sh[wave] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    nout[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    if (blockIdx.x == 0) {
+      ab[-1] = beta;
+      ab[0] = alpha;
+    }
+  }
 }
 
 // *out = sqrt(sum of partial[0..np)), summed as lz_reduce_local sums them.
@@ -623,24 +683,33 @@ hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64
   return hipGetLastError();
 }
 
-hipError_t launch_lz_step_pending(double* w, double* V, int64_t ldv, int nv, int64_t n, double* h,
+hipError_t launch_lz_step_onepass(double* w, double* V, int64_t ldv, int nv, int64_t n, double* h,
                                   double* partial, const double* npend, const double* beta_prev,
-                                  double* nout, double* scale, double* ab, const double* gprev,
-                                  double* gcur, double* out, hipStream_t stream) {
+                                  double* nout, double* scale, double* ab, double* out,
+                                  hipStream_t stream) {
   if (nv < 2 || !nout || !scale || (!npend && !beta_prev)) return hipErrorInvalidValue;
   const int nb = lz_blocks(n);
   const int nbk = (int)std::max<int64_t>(1, (n + kLzThreads * kDotkE - 1) / (kLzThreads * kDotkE));
-  if (gprev)
-    hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 2>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv,
-                       nv, w, n, partial);
-  else
-    hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 3>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv,
-                       nv, w, n, partial);
+  hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 2>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv, nv,
+                     w, n, partial);
   // beta_{j-1} into ab[-1] (when pending), alpha_j into ab[0]
-  hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(320), 0, stream, partial, nbk, nv, beta_prev,
-                     gprev, gcur, h, npend, nb, scale, ab - 1, ab);
+  hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(320), 0, stream, partial, nbk, nv, beta_prev, h,
+                     npend, nb, scale, ab - 1, ab);
   hipLaunchKernelGGL(lz_axpy_local, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h, scale,
                      npend != nullptr, out, nout);
+  return hipGetLastError();
+}
+
+hipError_t launch_lz_step_recurrence(const double* w, double* V, int64_t ldv, int nv, int64_t n,
+                                     double* partial, const double* npend, double* nout,
+                                     double* ab, double* out, hipStream_t stream) {
+  if (nv < 2 || !npend || !nout) return hipErrorInvalidValue;
+  const int nb = lz_blocks(n);
+  const int j = nv - 1;
+  hipLaunchKernelGGL(lz_dot_uw, dim3(nb), dim3(kLzThreads), 0, stream, V + (int64_t)j * ldv, w, n,
+                     partial);
+  hipLaunchKernelGGL(lz_local_update, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, j, n,
+                     partial, npend, nb, out, nout, ab);
   return hipGetLastError();
 }
 
