@@ -851,13 +851,14 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
     for (int j = 0;; ++j) {
       double* vj = V + (size_t)j * D;
       const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
+      const bool two = j == 0 || twice;
+      const bool recurrence = !two && !(j & 1);
       if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
       ++total;
-      const bool two = j == 0 || twice;
       double* vnext = j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr;
       if (two) {
         HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j, vnext, s));
-      } else if (j & 1) {
+      } else if (!recurrence) {
         // the recurrence and one pass against the basis; the new vector
         // stays unnormalised until the next step, which normalises it in
         // place (no separate finishing launch)
@@ -1142,6 +1143,11 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     for (int c = 0; c < k; ++c) cols[sec][c] = n - 1 - idx[c];
     for (int q0 = 0; q0 < k; q0 += 4) items.push_back({sec, q0});
   }
+  // largest sectors first, so that their (longest) items do not start last
+  std::stable_sort(items.begin(), items.end(), [&](const std::pair<int, int>& x,
+                                                   const std::pair<int, int>& y) {
+    return ds[x.first] > ds[y.first];
+  });
   {
     std::atomic<int> it(0);
     auto vecs = [&](int) {
