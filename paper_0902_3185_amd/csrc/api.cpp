@@ -232,6 +232,9 @@ struct dmrg_sb_s {
     DevBuf images;
   };
   RhoPlan rho_plan[2];
+  // per-sector eigen-solve workspaces of the last truncation on each side,
+  // kept so that their pages are reused by the next call
+  std::vector<SymEig> rho_eig[2];
   DevBuf rho_out;
   std::vector<double> tr_lambda;
   std::vector<int32_t> tr_sec, tr_kps;
@@ -1026,7 +1029,8 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     int32_t sec;
   };
   std::vector<Ent> ents;
-  std::vector<SymEig> eig(nsec);
+  std::vector<SymEig>& eig = sb->rho_eig[side];
+  eig.resize(nsec);
   const double floor_ = 1e-13, rel_tie = 1e-6;
   // Sectors are independent: all eigenvalues (and the data for the
   // eigenvectors) on host threads, largest sector first; the eigenvectors
@@ -1043,7 +1047,9 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
       if (w >= nsec) return;
       const int sec = work[w];
       const int n = ds[sec];
-      std::vector<double> A((size_t)n * n, 0.0);
+      // the symmetrised block, in a buffer each host thread keeps
+      thread_local std::vector<double> A;
+      A.assign((size_t)n * n, 0.0);
       if (rho_off[sec] >= 0)
         std::copy(rho + rho_off[sec], rho + rho_off[sec] + (size_t)n * n, A.begin());
       // symmetrise the computed block, in 16 x 16 tiles so that the
@@ -1125,7 +1131,8 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     per[e.sec].push_back(e.idx);
   }
   sb->tr_kps.assign(nsec, 0);
-  sb->tr_W.assign(nsec, std::vector<double>());
+  sb->tr_W.resize(nsec);   // the vectors keep their buffers from the last call
+  for (std::vector<double>& v : sb->tr_W) v.clear();
   sb->tr_Wp.assign(nsec, nullptr);
   // eigenvectors of the kept states: work items of up to four vectors of one
   // sector, shared by the host threads

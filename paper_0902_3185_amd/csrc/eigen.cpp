@@ -237,7 +237,8 @@ bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
   out.beta.assign(n, 0.0);
   if (n <= 0) return true;
   nthreads = std::max(1, std::min(nthreads, (n + 31) / 32));
-  std::vector<double> A(Ain, Ain + (size_t)n * n);
+  std::vector<double>& A = out.work;
+  A.assign(Ain, Ain + (size_t)n * n);
   std::vector<double>& R = out.R;
   std::vector<double>& betas = out.beta;
   // 1. Householder reduction to tridiagonal form on the lower triangle.
@@ -316,8 +317,12 @@ bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
   //    acts on rows k and k+1 of Z^T (columns of the tridiagonal's
   //    eigenvector matrix Z); it is recorded as (k, c, s) and applied in
   //    step 3.
-  std::vector<int32_t> rk;
-  std::vector<double> rc, rs;
+  std::vector<int32_t>& rk = out.rk;
+  std::vector<double>& rc = out.rc;
+  std::vector<double>& rs = out.rs;
+  rk.clear();
+  rc.clear();
+  rs.clear();
   rk.reserve((size_t)4 * n * n / 2 + 16);
   rc.reserve(rk.capacity());
   rs.reserve(rk.capacity());

@@ -31,6 +31,11 @@ struct SymEig {
   std::vector<double> R, beta;    // reflector k: beta[k], v_k[k+1..n) in R[k * n + ...]
   std::vector<double> zbuf;       // Z^T, n rows of stride ld from zbuf.data() + zoff
   size_t zoff = 0;
+  // scratch of sym_eigen_reduce (the working copy of A, the QR rotations);
+  // an object reused for later solves keeps its buffers, so the pages are
+  // not faulted in again on every call
+  std::vector<double> work, rc, rs;
+  std::vector<int32_t> rk;
 };
 bool sym_eigen_reduce(int n, const double* A, SymEig& out, int nthreads = 1);
 

@@ -44,8 +44,13 @@ def _oracle_ground(desc, seed):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp64_plain"])
 @pytest.mark.parametrize("name,m", [("heisenberg_L16_m32", None), ("hubbard_L64_U4_m512", 64),
-                                    ("j1j2_L64_m256", 48)])
+                                    ("j1j2_L64_m256", 48), ("heisenberg_L100_m256", None)])
 def test_lanczos_energy(ctx, name, m, prec):
+    """Ground state against the oracle's Lanczos.  The last superblock (D =
+    52564) is large against the vectors per cycle, so after each cycle's
+    first step the library alternates a Gram-Schmidt pass step with a
+    recurrence-only step; the smaller ones run two full passes at every
+    step."""
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock(name, m=m, seed=5)
     L = desc["meta"]["L"]
@@ -80,10 +85,11 @@ def test_lanczos_full_size_headline(ctx):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_lanczos_long_cycles_ladder(ctx, prec):
     """Restart cycles that run past 64 steps on the full 2x32 ladder
-    superblock (D = 604708, single Gram-Schmidt pass after the local
-    recurrence): the result is an eigenvector of the oracle's FP64 product
-    to the requested residual.  One Gram-Schmidt pass on H v_j itself lost
-    orthogonality after about 55 steps here and never converged."""
+    superblock (D = 604708; the local recurrence at every step, a single
+    Gram-Schmidt pass on every other step): the result is an eigenvector of
+    the oracle's FP64 product to the requested residual.  One Gram-Schmidt
+    pass on H v_j itself lost orthogonality after about 55 steps here and
+    never converged."""
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock("ladder_2x32_m1024", seed=0)
     sb = Superblock(desc, prec=prec, ctx=ctx)
