@@ -123,7 +123,8 @@ def test_lanczos_exact_eigenvector_stops_at_once(ctx):
 @pytest.mark.parametrize("no_split", [False, True])
 @pytest.mark.parametrize("name,m,keep", [("hubbard_L64_U4_m512", 64, 100),
                                          ("heisenberg_L100_m256", 64, 40),
-                                         ("heisenberg_L16_m32", None, 1000)])
+                                         ("heisenberg_L16_m32", None, 1000),
+                                         ("hubbard_L64_U4_m512", None, 512)])
 def test_rho_truncate_parity(ctx, name, m, keep, no_split):
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock(name, m=m, seed=6)
