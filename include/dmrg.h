@@ -115,7 +115,9 @@ typedef struct {
  *   nsec        sectors of the truncated side's basis
  *   kept_per_sec[nsec] kept states per sector
  *   W           [nsec] row-major dim[s] x kept_per_sec[s] eigenvector blocks,
- *               columns in decreasing eigenvalue order (NULL if none kept)  */
+ *               columns in decreasing eigenvalue order (NULL if none kept)
+ *   W_all       the same blocks back to back in sector order (W[s] points
+ *               into it), W_total doubles, so a caller can copy them at once */
 typedef struct {
   double trunc_err;
   int32_t kept;
@@ -125,6 +127,8 @@ typedef struct {
   int32_t nsec;
   const int32_t* kept_per_sec;
   const double* const* W;
+  const double* W_all;
+  int64_t W_total;
 } dmrg_trunc;
 
 /* ---------------------------------------------------------------------- */

@@ -49,7 +49,8 @@ class dmrg_trunc(C.Structure):
     _fields_ = [("trunc_err", C.c_double), ("kept", C.c_int32), ("straddle", C.c_int32),
                 ("lambda_", C.POINTER(C.c_double)), ("lambda_sec", C.POINTER(C.c_int32)),
                 ("nsec", C.c_int32), ("kept_per_sec", C.POINTER(C.c_int32)),
-                ("W", C.POINTER(C.POINTER(C.c_double)))]
+                ("W", C.POINTER(C.POINTER(C.c_double))),
+                ("W_all", C.POINTER(C.c_double)), ("W_total", C.c_int64)]
 
 
 _P = C.c_void_p

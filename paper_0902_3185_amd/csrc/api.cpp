@@ -238,7 +238,7 @@ struct dmrg_sb_s {
   DevBuf rho_out;
   std::vector<double> tr_lambda;
   std::vector<int32_t> tr_sec, tr_kps;
-  std::vector<std::vector<double>> tr_W;
+  std::vector<double> tr_W;          // the kept vectors of all sectors, back to back
   std::vector<const double*> tr_Wp;
 };
 
@@ -1131,21 +1131,27 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     per[e.sec].push_back(e.idx);
   }
   sb->tr_kps.assign(nsec, 0);
-  sb->tr_W.resize(nsec);   // the vectors keep their buffers from the last call
-  for (std::vector<double>& v : sb->tr_W) v.clear();
   sb->tr_Wp.assign(nsec, nullptr);
+  std::vector<int64_t> woff(nsec, 0);
   // eigenvectors of the kept states: work items of up to four vectors of one
   // sector, shared by the host threads
   std::vector<std::vector<int>> cols(nsec);
   std::vector<std::pair<int, int>> items;
+  int64_t wtot = 0;
   for (int sec = 0; sec < nsec; ++sec) {
     std::vector<int>& idx = per[sec];
     std::sort(idx.begin(), idx.end());
     const int n = ds[sec], k = (int)idx.size();
     sb->tr_kps[sec] = k;
+    woff[sec] = wtot;
+    wtot += (int64_t)n * k;
+  }
+  sb->tr_W.resize((size_t)wtot);   // every entry is written below
+  for (int sec = 0; sec < nsec; ++sec) {
+    const int n = ds[sec], k = sb->tr_kps[sec];
     if (k == 0) continue;
-    sb->tr_W[sec].assign((size_t)n * k, 0.0);
-    sb->tr_Wp[sec] = sb->tr_W[sec].data();
+    const std::vector<int>& idx = per[sec];
+    sb->tr_Wp[sec] = sb->tr_W.data() + woff[sec];
     cols[sec].resize(k);
     for (int c = 0; c < k; ++c) cols[sec][c] = n - 1 - idx[c];
     for (int q0 = 0; q0 < k; q0 += 4) items.push_back({sec, q0});
@@ -1164,7 +1170,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
         const int sec = items[w].first, q0 = items[w].second;
         const int k = (int)cols[sec].size();
         sym_eigen_vectors(eig[sec], std::min(4, k - q0), cols[sec].data() + q0,
-                          sb->tr_W[sec].data() + q0, k, 1);
+                          sb->tr_W.data() + woff[sec] + q0, k, 1);
       }
     };
     HostPool::get().run(std::min(hw, (int)items.size()), vecs);
@@ -1177,6 +1183,8 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   out->nsec = nsec;
   out->kept_per_sec = sb->tr_kps.data();
   out->W = sb->tr_Wp.data();
+  out->W_all = sb->tr_W.data();
+  out->W_total = wtot;
   return DMRG_OK;
 }
 

@@ -265,12 +265,15 @@ class Superblock:
             return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
 
         kps = arr(tr.kept_per_sec, tr.nsec, np.int64)
+        # one copy of all kept vectors; each sector's block is a view into it
+        wall = arr(tr.W_all, int(tr.W_total), np.float64)
         W = {}
-        for s in range(tr.nsec):
+        off = 0
+        for s in np.flatnonzero(kps):
             k = int(kps[s])
-            if k > 0:
-                d = self._dim(side, s)
-                W[s] = np.ctypeslib.as_array(tr.W[s], shape=(d * k,)).reshape(d, k).copy()
+            d = self._dim(side, int(s))
+            W[int(s)] = wall[off:off + d * k].reshape(d, k)
+            off += d * k
         return dict(eps=tr.trunc_err, kept=kept, straddle=bool(tr.straddle),
                     lam=arr(tr.lambda_, kept, np.float64),
                     lam_sec=arr(tr.lambda_sec, kept, np.int64),
