@@ -35,7 +35,7 @@ if ROOT not in sys.path:
 METRIC = ("H·ψ TFLOP/s + frac. of peak, FP32-MFMA vs FP64 at |ΔE|≤1e-9, "
           "Hubbard m=512")
 PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X dense matrix-core TFLOP/s
-TIMING_STRIDE = 4   # in the timed steps, every 4th product launch carries HIP events
+TIMING_STRIDE = 16  # in the timed steps, every 16th product launch carries HIP events
 
 
 def log(*a):
