@@ -239,6 +239,7 @@ struct dmrg_sb_s {
   std::vector<double> tr_lambda;
   std::vector<int32_t> tr_sec, tr_kps;
   std::vector<double> tr_W;          // the kept vectors of all sectors, back to back
+  std::vector<double> spec_W;        // eigenvectors formed ahead of the selection
   std::vector<const double*> tr_Wp;
 };
 
@@ -1041,10 +1042,71 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
   std::atomic<int> next(0), bad(0);
   std::string bad_what;
   const int hw = host_threads();
+  // While the last sector is still being reduced, the idle threads form the
+  // eigenvectors of the leading m entries of the finished sectors (the only
+  // ones of theirs that can be kept); the selection below takes those it
+  // keeps from there and forms only the rest.  Every vector is formed by the
+  // same routine either way, so the result does not depend on the timing.
+  struct SpecItem {
+    int sec, p0, np;   // positions p0 .. p0 + np - 1 in decreasing order
+  };
+  std::vector<SpecItem> spec;
+  std::vector<int> kspec(nsec, 0), spec_first(nsec, 0);
+  std::vector<int64_t> spec_off(nsec, 0);
+  std::vector<std::vector<int>> spec_cols(nsec);
+  std::unique_ptr<std::atomic<char>[]> spec_done;
+  std::unique_ptr<std::atomic<char>[]> finished(new std::atomic<char>[std::max(nsec, 1)]);
+  std::unique_ptr<std::atomic<char>[]> failed(new std::atomic<char>[std::max(nsec, 1)]);
+  for (int i = 0; i < nsec; ++i) {
+    finished[i].store(0, std::memory_order_relaxed);
+    failed[i].store(0, std::memory_order_relaxed);
+  }
+  std::atomic<int> done(0), spec_next(0), spec_ready(0);
+  auto publish = [&]() {
+    struct FE {
+      double lam;
+      int64_t q;
+      int sec, pos;
+    };
+    std::vector<FE> fe;
+    for (int s = 0; s < nsec; ++s) {
+      if (!finished[s].load(std::memory_order_acquire) || failed[s].load(std::memory_order_relaxed))
+        continue;
+      const int n = ds[s];
+      for (int c = 0; c < n; ++c) {
+        const double raw = eig[s].w[n - 1 - c];
+        fe.push_back({raw >= floor_ ? raw : 0.0, qs[s], s, c});
+      }
+    }
+    const int top = std::min<int>(std::max(m, 0), (int)fe.size());
+    std::nth_element(fe.begin(), fe.begin() + std::max(top - 1, 0), fe.end(),
+                     [](const FE& x, const FE& y) {
+                       if (x.lam != y.lam) return x.lam > y.lam;
+                       if (x.q != y.q) return x.q < y.q;
+                       return x.pos < y.pos;
+                     });
+    for (int i = 0; i < top; ++i) kspec[fe[i].sec] = std::max(kspec[fe[i].sec], fe[i].pos + 1);
+    int64_t tot = 0;
+    for (int s = 0; s < nsec; ++s) {
+      spec_off[s] = tot;
+      tot += (int64_t)ds[s] * kspec[s];
+      spec_cols[s].resize(kspec[s]);
+      for (int c = 0; c < kspec[s]; ++c) spec_cols[s][c] = ds[s] - 1 - c;
+    }
+    sb->spec_W.resize((size_t)tot);
+    for (int w = 0; w < nsec; ++w) {   // largest sectors first
+      const int s = work[w];
+      spec_first[s] = (int)spec.size();
+      for (int p0 = 0; p0 < kspec[s]; p0 += 4) spec.push_back({s, p0, std::min(4, kspec[s] - p0)});
+    }
+    spec_done.reset(new std::atomic<char>[std::max<size_t>(spec.size(), 1)]);
+    for (size_t i = 0; i < spec.size(); ++i) spec_done[i].store(0, std::memory_order_relaxed);
+    spec_ready.store(1, std::memory_order_release);
+  };
   auto solve = [&](int) {
     for (;;) {
       const int w = next.fetch_add(1);
-      if (w >= nsec) return;
+      if (w >= nsec) break;
       const int sec = work[w];
       const int n = ds[sec];
       // the symmetrised block, in a buffer each host thread keeps
@@ -1076,7 +1138,24 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
              << " non-finite entries, max |rho| " << amax << ")";
           bad_what = os.str();
         }
+        failed[sec].store(1, std::memory_order_relaxed);
       }
+      finished[sec].store(1, std::memory_order_release);
+      if (done.fetch_add(1, std::memory_order_acq_rel) + 1 == nsec - 1) publish();
+    }
+    // speculative eigenvectors until the last sector is done
+    for (;;) {
+      if (done.load(std::memory_order_acquire) >= nsec) return;
+      if (!spec_ready.load(std::memory_order_acquire)) {
+        std::this_thread::yield();
+        continue;
+      }
+      const int i = spec_next.fetch_add(1);
+      if (i >= (int)spec.size()) return;
+      const SpecItem& it = spec[i];
+      sym_eigen_vectors(eig[it.sec], it.np, spec_cols[it.sec].data() + it.p0,
+                        sb->spec_W.data() + spec_off[it.sec] + it.p0, kspec[it.sec], 1);
+      spec_done[i].store(1, std::memory_order_release);
     }
   };
   HostPool::get().run(std::min(hw, nsec), solve);
@@ -1147,6 +1226,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     wtot += (int64_t)n * k;
   }
   sb->tr_W.resize((size_t)wtot);   // every entry is written below
+  const bool have_spec = spec_ready.load(std::memory_order_acquire) != 0;
   for (int sec = 0; sec < nsec; ++sec) {
     const int n = ds[sec], k = sb->tr_kps[sec];
     if (k == 0) continue;
@@ -1154,7 +1234,25 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     sb->tr_Wp[sec] = sb->tr_W.data() + woff[sec];
     cols[sec].resize(k);
     for (int c = 0; c < k; ++c) cols[sec][c] = n - 1 - idx[c];
-    for (int q0 = 0; q0 < k; q0 += 4) items.push_back({sec, q0});
+    // the leading kept columns formed while the last sector was reduced
+    // (kept positions are 0..k-1 of the sector's decreasing order; the
+    // formed ones a prefix of them)
+    int avail = 0;
+    if (have_spec && kspec[sec] > 0) {
+      bool prefix = true;
+      for (int c = 0; c < k; ++c) prefix = prefix && idx[c] == c;
+      while (prefix && avail < std::min(k, kspec[sec]) &&
+             spec_done[spec_first[sec] + avail / 4].load(std::memory_order_acquire))
+        avail = std::min(std::min(k, kspec[sec]), avail / 4 * 4 + 4);
+      double* dst = sb->tr_W.data() + woff[sec];
+      const double* src = sb->spec_W.data() + spec_off[sec];
+      for (int r = 0; r < n; ++r)
+        std::copy(src + (size_t)r * kspec[sec], src + (size_t)r * kspec[sec] + avail, dst + (size_t)r * k);
+    }
+    // the rest in work items (two vectors each in large sectors, whose items
+    // are the longest)
+    const int per_item = n >= 128 ? 2 : 4;
+    for (int q0 = avail; q0 < k; q0 += per_item) items.push_back({sec, q0});
   }
   // largest sectors first, so that their (longest) items do not start last
   std::stable_sort(items.begin(), items.end(), [&](const std::pair<int, int>& x,
@@ -1169,7 +1267,8 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
         if (w >= (int)items.size()) return;
         const int sec = items[w].first, q0 = items[w].second;
         const int k = (int)cols[sec].size();
-        sym_eigen_vectors(eig[sec], std::min(4, k - q0), cols[sec].data() + q0,
+        const int per_item = ds[sec] >= 128 ? 2 : 4;
+        sym_eigen_vectors(eig[sec], std::min(per_item, k - q0), cols[sec].data() + q0,
                           sb->tr_W.data() + woff[sec] + q0, k, 1);
       }
     };
