@@ -229,6 +229,17 @@ dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant);
  * dmrg_sb_autotune reports it); DMRG_E_ARG for an unknown variant.         */
 dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant);
 
+/* Reorthogonalisation of dmrg_lanczos_ground's basis (paper Sec. 3.3 gives
+ * the recursion, not a scheme).  mode 0 (the default): after each restart
+ * cycle's first step, the local three-term recurrence at every step and one
+ * Gram-Schmidt pass against the whole basis on every other step, which keeps
+ * the basis semi-orthogonal (overlaps of order 1e-7 with reduced-precision
+ * products); small dimensions always take mode 1.  mode 1: classical
+ * Gram-Schmidt twice against the whole basis at every step (orthogonal to
+ * working precision, about twice the passes over the basis).  DMRG_E_ARG
+ * for another mode.                                                          */
+dmrg_status dmrg_sb_set_reorth(dmrg_sb sb, int32_t mode);
+
 /* y_d = alpha * H psi_d + beta * y_d (paper Sec. 3.3: the Lanczos solver's
  * only need, x += H y, with alpha = beta = 1).  psi_d and y_d are device FP64
  * arrays of length D in the dmrg_sb_layout order and must not overlap.

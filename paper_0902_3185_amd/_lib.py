@@ -89,6 +89,7 @@ _SIGS = {
     "dmrg_host_sym_eigen": (C.c_int, [C.c_int32, _D, _D]),
     "dmrg_sb_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32)]),
     "dmrg_sb_set_variant": (C.c_int, [_P, C.c_int32]),
+    "dmrg_sb_set_reorth": (C.c_int, [_P, C.c_int32]),
     "dmrg_host_tridiag_lowest": (C.c_int, [C.c_int32, _D, _D, _D, _D]),
 }
 

@@ -222,6 +222,7 @@ struct dmrg_sb_s {
   Staged fwd;
   std::unique_ptr<Staged> adj;
   int variant[3] = {0, 0, 0};   // fused-kernel variant per kernel precision (autotuner)
+  int reorth = 0;               // Lanczos reorthogonalisation (dmrg_sb_set_reorth)
   // density-matrix blocks: tile images per side (built on first use), output
   struct RhoPlan {
     bool built = false;
@@ -668,6 +669,13 @@ dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant) {
   return DMRG_OK;
 }
 
+dmrg_status dmrg_sb_set_reorth(dmrg_sb sb, int32_t mode) {
+  if (!sb) return fail(DMRG_E_ARG, "null superblock");
+  if (mode != 0 && mode != 1) return fail(DMRG_E_ARG, "reorthogonalisation mode must be 0 or 1");
+  sb->reorth = mode;
+  return DMRG_OK;
+}
+
 dmrg_status dmrg_hpsi(dmrg_sb sb, const double* psi_d, double* y_d, double alpha, double beta) {
   dmrg_status st = need_device(sb);
   if (st != DMRG_OK) return st;
@@ -815,7 +823,7 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
     // cycle, and only they leave the vanishing beta that ends the recursion
     // there.
     constexpr int64_t kOncePassMinRatio = 32;   // D >= 32 * vectors per cycle
-    const bool twice = D < kOncePassMinRatio * nvec;
+    const bool twice = sb->reorth == 1 || D < kOncePassMinRatio * nvec;
     auto evaluate = [&](int jc, const double* h) {
       alphas.clear();
       betas.clear();

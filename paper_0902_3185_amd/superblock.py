@@ -190,6 +190,12 @@ class Superblock:
         """dmrg_sb_set_variant: pin the fused kernel's variant."""
         check(lib().dmrg_sb_set_variant(self.handle, int(variant)))
 
+    def set_reorth(self, mode):
+        """dmrg_sb_set_reorth: 0 = Gram-Schmidt pass on every other Lanczos
+        step after the local recurrence (default), 1 = classical
+        Gram-Schmidt twice at every step."""
+        check(lib().dmrg_sb_set_reorth(self.handle, int(mode)))
+
     def set_prec(self, prec):
         check(lib().dmrg_sb_set_prec(self.handle, PREC[prec]))
         self.prec = prec

@@ -103,6 +103,30 @@ def test_lanczos_long_cycles_ladder(ctx, prec):
     assert abs(E - r["energy"]) <= 1e-10 * abs(E)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_lanczos_reorth_modes(ctx, prec):
+    """dmrg_sb_set_reorth: the Gram-Schmidt pass on every other step (the
+    default) and classical Gram-Schmidt twice at every step reach the same
+    certified ground state of the full headline superblock."""
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("hubbard_L64_U4_m512", seed=0)
+    energies = []
+    for mode in (0, 1):
+        sb = Superblock(desc, prec=prec, ctx=ctx)
+        sb.set_reorth(mode)
+        r = sb.lanczos(_dev(seeded_vector(sb.D, 3)), max_iter=2000, tol=1e-8)
+        assert r["converged"], mode
+        psi = _host(r["psi"])
+        hp = OS.hpsi_blocks(desc, psi)
+        E = float(np.dot(psi, hp))
+        assert np.linalg.norm(hp - E * psi) <= 2e-8, mode
+        assert abs(E - r["energy"]) <= 1e-10 * abs(E), mode
+        energies.append(r["energy"])
+    assert abs(energies[0] - energies[1]) <= 1e-10 * abs(energies[0])
+    with pytest.raises(Exception):
+        sb.set_reorth(2)
+
+
 def test_lanczos_cap_reports_noconv(ctx):
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock("heisenberg_L16_m32", seed=0)
