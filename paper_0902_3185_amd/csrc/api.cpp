@@ -839,7 +839,12 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
         E = alphas[0];
         res = betas[0];
         beta0 = betas[0];
-        ctol = reduced ? std::max(tol, 1e-4 * beta0) : tol;
+        // a reduced-precision cycle stops at a fraction of its starting
+        // (FP64) residual that its products can still resolve: FP32 products
+        // carry about 1e-7 relative error, the BF16 split about 1e-5
+        // (measured: 1e-5 for FP32 takes 81 products to the headline ground
+        // state where 1e-4 takes 85 and 1e-6 85)
+        ctol = reduced ? std::max(tol, (sb->prec == DMRG_FP32 ? 1e-5 : 1e-4) * beta0) : tol;
         if (res <= tol) {
           converged = true;
           nv = 1;
