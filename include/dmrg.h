@@ -254,7 +254,9 @@ dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d
                               double* gpsi_d, double* gc_h);
 
 /* Lowest eigenpair of H in the target sector by Lanczos (Sec. 3.3), with
- * FP64 vectors and full (twice-applied) reorthogonalisation.  When the
+ * FP64 vectors reorthogonalised as dmrg_sb_set_reorth selects (by default
+ * semi-orthogonally: the local recurrence at every step, one Gram-Schmidt
+ * pass against the whole basis on every other step).  When the
  * superblock computes in reduced precision, each restart cycle begins with
  * one FP64 product (Rayleigh quotient and residual in FP64) and continues in
  * the reduced precision; cycles repeat until the FP64 residual

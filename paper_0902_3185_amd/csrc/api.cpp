@@ -166,6 +166,7 @@ struct Staged {
   Plan plan;
   DevBuf tiles, segs, gsrc, gscale, dense64, dense32;
   DevBuf images;            // one tile image per workgroup slot of the fused kernel
+  DevBuf psi32;             // FP32 copy of the input vector (products that read one)
   int32_t img_stride = 0;   // words per image
   int32_t nslots = 0;
   bool has32 = false;
@@ -277,8 +278,8 @@ dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
   if ((r = upload(st.gscale, p.gscale.data(), p.gscale.size() * sizeof(double), s)) != DMRG_OK) return r;
   if ((r = upload(st.dense64, p.dense.data(), p.dense.size() * sizeof(double), s)) != DMRG_OK) return r;
   if (want32) {
-    std::vector<float> f(p.dense.size());
-    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)p.dense[i];
+    std::vector<float> f;
+    dense_f32(p, f);
     if ((r = upload(st.dense32, f.data(), f.size() * sizeof(float), s)) != DMRG_OK) return r;
     HIP_TRY(hipStreamSynchronize(s));   // the host staging vector dies here
     st.has32 = true;
@@ -311,6 +312,31 @@ hipError_t take_event(dmrg_ctx c, hipEvent_t* e) {
     return hipSuccess;
   }
   return hipEventCreate(e);
+}
+
+// The fused product in kernel precision kp.  The FP32 and BF16 kernels read
+// psi as an FP32 copy in the plan's staging buffer (kPoolPad elements of
+// room past the end, so that their vector loads stay inside it): psi32, if
+// given, already holds it; otherwise psi is converted into it first.  The
+// event pair, if any, brackets the product alone.
+dmrg_status launch_fused(Staged& st, int kp, int variant, const void* dense, const double* psi,
+                         double* y, double alpha, double beta, hipStream_t s, hipEvent_t t0,
+                         hipEvent_t t1, const float* psi32 = nullptr) {
+  if (kp == kPrecF64) {
+    HIP_TRY(launch_hpsi(kp, variant, st.nslots, st.images.as<uint32_t>(), st.img_stride, dense, psi, y,
+                        alpha, beta, s, t0, t1));
+    return DMRG_OK;
+  }
+  const int64_t n = st.plan.D_in + kPoolPad;
+  if (!psi32) {
+    HIP_TRY(st.psi32.ensure((size_t)n * sizeof(float)));
+    HIP_TRY(launch_psi_to_f32(psi, st.psi32.as<float>(), st.plan.D_in, s));
+    psi32 = st.psi32.as<float>();
+  }
+  const int64_t ndense = (int64_t)st.plan.dense.size() + kPoolPad;
+  HIP_TRY(launch_hpsi(kp, variant, st.nslots, st.images.as<uint32_t>(), st.img_stride, dense, psi, y,
+                      alpha, beta, s, t0, t1, psi32, ndense, n));
+  return DMRG_OK;
 }
 
 dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
@@ -350,9 +376,7 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
     dense = st.dense32.p;
   }
   const int kp = kernel_prec(prec);
-  HIP_TRY(launch_hpsi(kp, sb->variant[kp], st.nslots, st.images.as<uint32_t>(), st.img_stride, dense,
-                      psi, y, alpha, beta, s, t0, t1));
-  return DMRG_OK;
+  return launch_fused(st, kp, sb->variant[kp], dense, psi, y, alpha, beta, s, t0, t1);
 }
 
 dmrg_status need_device(dmrg_sb sb) {
@@ -603,8 +627,8 @@ dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec) {
   if (prec < DMRG_FP64 || prec > DMRG_FP64_PLAIN) return fail(DMRG_E_ARG, "unknown precision");
   if (uses32(prec) && sb->ctx && !sb->fwd.has32) {
     DeviceGuard g(sb->ctx->device);
-    std::vector<float> f(sb->fwd.plan.dense.size());
-    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)sb->fwd.plan.dense[i];
+    std::vector<float> f;
+    dense_f32(sb->fwd.plan, f);
     dmrg_status r = upload(sb->fwd.dense32, f.data(), f.size() * sizeof(float), sb->ctx->stream);
     if (r != DMRG_OK) return r;
     HIP_TRY(hipStreamSynchronize(sb->ctx->stream));
@@ -626,7 +650,7 @@ dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant) {
   if (!sb->fwd.has32) return fail(DMRG_E_ARG, "FP32 operators not staged (use dmrg_sb_set_prec)");
   DeviceGuard g(sb->ctx->device);
   hipStream_t s = sb->ctx->stream;
-  const Staged& stg = sb->fwd;
+  Staged& stg = sb->fwd;
   DevBuf x, y;
   HIP_TRY(x.ensure((size_t)std::max<int64_t>(stg.plan.D_in, 1) * sizeof(double)));
   HIP_TRY(y.ensure((size_t)std::max<int64_t>(stg.plan.D, 1) * sizeof(double)));
@@ -639,8 +663,10 @@ dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant) {
   hipError_t err = hipSuccess;
   for (int v = 0; v < kVariants && err == hipSuccess; ++v) {
     auto go = [&]() {
-      return launch_hpsi(kp, v, stg.nslots, stg.images.as<uint32_t>(), stg.img_stride, stg.dense32.p,
-                         x.as<double>(), y.as<double>(), 1.0, 0.0, s);
+      return launch_fused(sb->fwd, kp, v, stg.dense32.p, x.as<double>(), y.as<double>(), 1.0, 0.0, s,
+                          nullptr, nullptr) == DMRG_OK
+                 ? hipSuccess
+                 : hipErrorUnknown;
     };
     for (int w = 0; w < 2 && err == hipSuccess; ++w) err = go();
     if (err == hipSuccess) err = hipEventRecord(e0, s);

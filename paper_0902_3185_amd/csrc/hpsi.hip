@@ -1,13 +1,14 @@
 // Superblock product kernels for gfx950 (CDNA4).
 //
-// One workgroup of 4 wave64s owns one 32 x 32 output tile of one target
-// block Y_q and reduces every term that writes it (Y_q += c A Psi_q' B^T;
-// paper Sec. 3.3, blocking by effective symmetry).  The dense products run on
-// the matrix cores; the four waves split the contraction chunks of all of the
-// tile's terms and their partial tiles are summed in LDS in a fixed order, so
-// the result does not depend on scheduling.  Terms with identity or gather
-// operators on both sides are elementwise and are added in FP64 afterwards.
-// No atomics are used on y.
+// One workgroup owns one 32 x 32 output tile of one target block Y_q and
+// reduces every term that writes it (Y_q += c A Psi_q' B^T; paper Sec. 3.3,
+// blocking by effective symmetry).  The dense products run on the matrix
+// cores: the workgroup's waves (16 for FP32 and the BF16 split, 8 for FP64)
+// split the contraction chunks of all of the tile's terms, and their
+// partial tiles are summed in LDS in a fixed order, so the result does not
+// depend on scheduling.  Terms with identity or gather operators on both
+// sides are elementwise and are added in FP64 afterwards.  No atomics are
+// used on y.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
@@ -16,6 +17,7 @@
 namespace dmrg {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef double d2 __attribute__((ext_vector_type(2)));
@@ -71,8 +73,8 @@ struct CfgF32 {
     const int64_t ldp = sg.psi_ld;
     const int nch = (sg.K + kChunk - 1) / kChunk;
     if (sg.kind == SEG_KN) {
-      const op_t* At = dense + sg.op_off;
-      const int64_t lda = sg.op_ld;
+      // the FP32 pool holds A-side blocks row-major (a x K)
+      const op_t* A = dense + sg.op_off;
       const int m = t.m0 + i;
       const bool mok = m < t.a;
       GatherLane gb = gather_at(gsrc, gscale, sg.gB, t.n0 + i, t.b);
@@ -84,7 +86,7 @@ struct CfgF32 {
         for (int s = 0; s < 8; ++s) {
           const int k = k0 + 2 * s + kh;
           const bool kok = k < sg.K;
-          av[s] = (mok && kok) ? cs * At[k * lda + m] : 0.f;
+          av[s] = (mok && kok) ? cs * A[(int64_t)m * sg.K + k] : 0.f;
           bv[s] = (gb.ok && kok) ? sb * (float)P[k * ldp + gb.src] : 0.f;
         }
 #pragma unroll
@@ -240,7 +242,6 @@ __device__ inline double gg_term(const SegDesc& sg, const TileDesc& t, int m, in
 // BF16 k = 8*(lane/32) + s, FP64 k = 4*(lane/16) + s (A and B agree, so the
 // order inside a chunk is immaterial).
 // ---------------------------------------------------------------------------
-constexpr int kMaxGG = 8;     // elementwise segments whose operands are loaded early
 
 __device__ inline int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -259,236 +260,292 @@ struct TileGeo {
   int a, b, m0, n0;
 };
 
-// FP32 matrix cores, v_mfma_f32_32x32x2f32: A[i][k] from lane i + 32k,
-// B[k][j] from lane j + 32k; D[i][j] in lane j + 32*((i/4)%2), register
-// (i%4) + 4*(i/8).  One chunk is 8 instructions; element s of lane half h
-// carries k = 8h + s.
-struct F32Tile {
+// FP32 and BF16 products with each wave's contraction chunk staged in LDS.
+//
+// A chunk is 16 positions of one segment's contraction.  Its two operand
+// panels -- A (32 output rows x 16 k) and B (16 k x 32 output columns) --
+// are read with 16-byte buffer loads along the direction the data is
+// contiguous in (rows of psi and of the row-major operator blocks along k;
+// rows of Psi' along the output columns for SEG_KN, over a 32-column window
+// that holds every gathered column of the tile), scaled, and written to the
+// wave's own LDS area: A as [m][k], B as [k][w] (the window) for SEG_KN and
+// as [n][k] for SEG_MK.  The matrix-core operands are then read from LDS in
+// the layout of v_mfma_f32_16x16x4f32 on the tile's four 16 x 16 quarters:
+// A[i][k] from lane i + 16k, B[k][j] from lane j + 16k, D[i][j] in lane
+// j + 16*(i/4), register i%4; lane group kk = lane/16 takes chunk positions
+// 4kk .. 4kk + 3, instruction s position 4kk + s.  The BF16 form splits each
+// FP32 operand x into hi = bf16(x) and lo = bf16(x - hi) and issues
+// hi*hi + hi*lo + lo*hi with v_mfma_f32_16x16x16bf16_1k (A[i][k] from lane
+// i + 16*(k/4), element k%4: the same four positions per lane), FP32
+// accumulate.
+//
+// Each lane's byte offsets and scales depend only on the segment, so they
+// are formed once per segment; a chunk then costs four loads (one add each)
+// and a few multiplies.  Loads past a block's rows or columns read
+// neighbouring data (zeroed by the scales) or, past the buffer, zeros: the
+// buffer resources carry each buffer's size, which the hardware checks.  A
+// chunk that ends past the contraction length is masked element by element.
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 buf16(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
+}
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr uint32_t kNoRead = 0x80000000u;   // an offset past every buffer: reads zeros, no traffic
+
+template <bool kBF16>
+struct F32S {
   using op_t = float;
+  using psi_t = float;
   using red_t = float;
   static constexpr int kWaves = 16;
+  static constexpr int kLdn = 36;                      // [k][w] window row stride (floats)
+  static constexpr int kAFloats = kTile * kChunk;      // A panel [m][k]
+  static constexpr int kBFloats = kChunk * kLdn;       // B panel ([k][w]; [n][k] uses 512)
+  static constexpr int kStageFloats = kAFloats + kBFloats;
   struct Acc {
-    f32x16 d;
+    f32x4 d[4];   // quarter (qi, qj) at d[2*qi + qj]
   };
+  // one chunk in registers: operator panel (rows lane/4 + 16j, positions
+  // 4*(lane%4) .. +3) and psi panel (SEG_KN: window row lane/8 + 8j,
+  // columns 4*(lane%8) .. +3; SEG_MK: gathered row lane/4 + 16j, positions
+  // 4*(lane%4) .. +3)
   struct Raw {
-    float f[8];    // SEG_KN: A;  SEG_MK: B
-    double d[8];   // SEG_KN: B;  SEG_MK: A  (psi)
+    f4 o[2], p[2];
+  };
+  // a segment's per-lane byte offsets of its chunk 0 and bytes per chunk
+  struct Fetch {
+    int seg;
+    uint32_t op[2], ps[2];
+    uint32_t dop, dps;
+  };
+  // a segment's per-lane scales: sa (A panel rows), sb (SEG_KN: column
+  // scale at use, w the column's place in the window; SEG_MK: B rows)
+  struct Use {
+    int seg;
+    float sa[2], sb[2];
+    int w[2];
   };
   __device__ static void zero(Acc& a) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) a.d[r] = 0.f;
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a.d[q][r] = 0.f;
   }
-  template <bool kStage>
-  __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
-                              const op_t* dense, const double* psi, int lane) {
-    const int i = lane & 31, kb = ch * kChunk + 8 * (lane >> 5);
+  __device__ static void setup_fetch(Fetch& f, int s, const ImgSeg& sg, int kind, int K, const TileGeo& g,
+                                     int lane) {
+    f.seg = s;
+    const int64_t ldp = sg.psi_ld;
     if (kind == SEG_KN) {
-      const op_t* At = dense + sg.op_off + min(g.m0 + i, g.a - 1);
-      const int64_t lda = sg.op_ld;
-      const double* P = psi + sg.psi_off + max(sg.src[i], 0);
-      const int64_t ldp = sg.psi_ld;
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int64_t k = min(kb + s, K - 1);
-        R.f[s] = At[k * lda];
-        R.d[s] = P[k * ldp];
+      for (int j = 0; j < 2; ++j) {
+        f.op[j] = (uint32_t)(4 * (sg.op_off + (int64_t)(g.m0 + lane / 4 + 16 * j) * K + (lane & 3) * 4));
+        f.ps[j] = (uint32_t)(4 * (sg.psi_off + (int64_t)(lane / 8 + 8 * j) * ldp + sg.pad + (lane & 7) * 4));
       }
-    } else if (!kStage) {
-      // each lane walks its own row along k with 16-byte loads (rows are
-      // only element-aligned, which the memory system takes for vector loads)
-      const double* Arow = psi + sg.psi_off + (int64_t)max(sg.src[i], 0) * sg.psi_ld;
-      const op_t* Brow = dense + sg.op_off + (int64_t)min(g.n0 + i, g.b - 1) * sg.op_ld;
-      if (K - (ch + 1) * kChunk >= 0) {   // whole chunk in range (uniform)
+      f.dop = 4 * kChunk;
+      f.dps = (uint32_t)(4 * kChunk * ldp);
+    } else {
 #pragma unroll
-        for (int s = 0; s < 8; s += 2) {
-          d2 t;
-          __builtin_memcpy(&t, Arow + kb + s, sizeof(t));
-          R.d[s] = t.x;
-          R.d[s + 1] = t.y;
-        }
+      for (int j = 0; j < 2; ++j) {
+        const int r = max(sg.src[lane / 4 + 16 * j], 0);
+        f.op[j] = (uint32_t)(4 * (sg.op_off + (int64_t)(g.n0 + lane / 4 + 16 * j) * sg.op_ld + (lane & 3) * 4));
+        f.ps[j] = (uint32_t)(4 * (sg.psi_off + (int64_t)r * ldp + (lane & 3) * 4));
+      }
+      f.dop = 4 * kChunk;
+      f.dps = 4 * kChunk;
+    }
+  }
+  __device__ static void setup_use(Use& u, int s, const ImgSeg& sg, int kind, const TileGeo& g, int lane) {
+    u.seg = s;
+    const int i = lane & 15;
+    if (kind == SEG_KN) {
 #pragma unroll
-        for (int s = 0; s < 8; s += 4) {
-          f4 t;
-          __builtin_memcpy(&t, Brow + kb + s, sizeof(t));
-          R.f[s] = t.x;
-          R.f[s + 1] = t.y;
-          R.f[s + 2] = t.z;
-          R.f[s + 3] = t.w;
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int k = min(kb + s, K - 1);
-          R.d[s] = Arow[k];
-          R.f[s] = Brow[k];
-        }
+      for (int j = 0; j < 2; ++j) {
+        u.sa[j] = g.m0 + lane / 4 + 16 * j < g.a ? (float)sg.c : 0.f;
+        const int src = sg.src[16 * j + i];
+        u.w[j] = src >= 0 ? src - sg.pad : 0;
+        u.sb[j] = src >= 0 ? (float)sg.scl[16 * j + i] : 0.f;
       }
     } else {
-      // whole rows per group of lanes, so that each load instruction covers
-      // few cache lines: A rows are 16 doubles, 8 lanes x 16 bytes per row,
-      // 8 rows per instruction; B rows are 16 floats, 4 lanes x 16 bytes, 16
-      // rows per instruction.  operands() transposes them through LDS.
-      const int q8 = lane & 7, r8 = lane >> 3, q4 = lane & 3, r4 = lane >> 2;
-      const int kc = ch * kChunk;
-      const bool full = K - (ch + 1) * kChunk >= 0;   // whole chunk in range (uniform)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double* Arow = psi + sg.psi_off + (int64_t)max(sg.src[8 * j + r8], 0) * sg.psi_ld;
-        if (full) {
-          d2 t;
-          __builtin_memcpy(&t, Arow + kc + 2 * q8, sizeof(t));
-          R.d[2 * j] = t.x;
-          R.d[2 * j + 1] = t.y;
-        } else {
-          R.d[2 * j] = Arow[min(kc + 2 * q8, K - 1)];
-          R.d[2 * j + 1] = Arow[min(kc + 2 * q8 + 1, K - 1)];
+      for (int j = 0; j < 2; ++j) {
+        const int r = lane / 4 + 16 * j;
+        u.sa[j] = sg.src[r] >= 0 ? (float)(sg.c * sg.scl[r]) : 0.f;
+        u.sb[j] = g.n0 + r < g.b ? 1.f : 0.f;
+        u.w[j] = 0;
+      }
+    }
+  }
+  __device__ static void load(Raw& R, const Fetch& f, int ch, bool live, __amdgpu_buffer_rsrc_t rd,
+                              __amdgpu_buffer_rsrc_t rp) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      R.o[j] = buf16(rd, live ? f.op[j] + ch * f.dop : kNoRead);
+      R.p[j] = buf16(rp, live ? f.ps[j] + ch * f.dps : kNoRead);
+    }
+  }
+  // raw registers -> scaled FP32 panels in the wave's LDS area
+  __device__ static void stage(const Raw& R, const Use& u, int kind, int K, int ch, int lane, float* As,
+                               float* Bs) {
+    const int kc = ch * kChunk;
+    const bool full = kc + kChunk <= K;   // uniform
+    f4 v[4];
+    if (kind == SEG_KN) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        v[j] = u.sa[j] * R.o[j];   // A[m][k] = c op[m][k]
+        v[2 + j] = R.p[j];         // window rows
+      }
+      if (!full) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (kc + (lane & 3) * 4 + e >= K) v[j][e] = 0.f;
+          if (kc + lane / 8 + 8 * j >= K) v[2 + j] = f4{0.f, 0.f, 0.f, 0.f};
         }
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const op_t* Brow = dense + sg.op_off + (int64_t)min(g.n0 + 16 * j + r4, g.b - 1) * sg.op_ld;
-        if (full) {
-          f4 t;
-          __builtin_memcpy(&t, Brow + kc + 4 * q4, sizeof(t));
-          R.f[4 * j] = t.x;
-          R.f[4 * j + 1] = t.y;
-          R.f[4 * j + 2] = t.z;
-          R.f[4 * j + 3] = t.w;
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) R.f[4 * j + t] = Brow[min(kc + 4 * q4 + t, K - 1)];
-        }
-      }
-    }
-  }
-  // LDS staging of one wave's row-walking chunk: A and B as [row][k] floats,
-  // rows padded to kStageLd (16-byte aligned rows).
-  static constexpr int kStageLd = 20;
-  static constexpr int kStageFloats = 2 * kTile * kStageLd;   // per wave
-  // operands of one chunk in FP32, scaled and masked
-  template <bool kStage>
-  __device__ static void operands(const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
-                                  const TileGeo& g, int lane, float* stage, float (&a)[8],
-                                  float (&b)[8]) {
-    const int i = lane & 31, kh = lane >> 5, kv = K - ch * kChunk - 8 * kh;
-    const int src = sg.src[i];
-    if (kind == SEG_KN) {
-      const float cA = g.m0 + i < g.a ? (float)sg.c : 0.f;
-      const float sB = src >= 0 ? (float)sg.scl[i] : 0.f;
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        a[s] = s < kv ? cA * R.f[s] : 0.f;
-        b[s] = s < kv ? sB * (float)R.d[s] : 0.f;
-      }
-    } else if (!kStage) {
-      const float cA = src >= 0 ? (float)(sg.c * sg.scl[i]) : 0.f;
-      const float sB = g.n0 + i < g.b ? 1.f : 0.f;
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        a[s] = s < kv ? cA * (float)R.d[s] : 0.f;
-        b[s] = s < kv ? sB * R.f[s] : 0.f;
+        *reinterpret_cast<f4*>(As + (lane / 4 + 16 * j) * kChunk + (lane & 3) * 4) = v[j];
+        *reinterpret_cast<f4*>(Bs + (lane / 8 + 8 * j) * kLdn + (lane & 7) * 4) = v[2 + j];
       }
     } else {
-      // transpose through the wave's LDS stage: rows as loaded, then each
-      // lane reads its own row's 8 contraction elements (the wave's LDS
-      // operations complete in order)
-      float* As = stage;
-      float* Bs = stage + kTile * kStageLd;
-      const int q8 = lane & 7, r8 = lane >> 3, q4 = lane & 3, r4 = lane >> 2;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float2 t;
-        t.x = (float)R.d[2 * j];
-        t.y = (float)R.d[2 * j + 1];
-        *reinterpret_cast<float2*>(As + (8 * j + r8) * kStageLd + 2 * q8) = t;
+      for (int j = 0; j < 2; ++j) {
+        v[j] = u.sa[j] * R.p[j];       // A[m][k] = c scl[m] Psi'[src m][k]
+        v[2 + j] = u.sb[j] * R.o[j];   // B^T[n][k] = op[n][k]
+      }
+      if (!full) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (kc + (lane & 3) * 4 + e >= K) v[j][e] = 0.f;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        float4 t;
-        t.x = R.f[4 * j];
-        t.y = R.f[4 * j + 1];
-        t.z = R.f[4 * j + 2];
-        t.w = R.f[4 * j + 3];
-        *reinterpret_cast<float4*>(Bs + (16 * j + r4) * kStageLd + 4 * q4) = t;
+        *reinterpret_cast<f4*>(As + (lane / 4 + 16 * j) * kChunk + (lane & 3) * 4) = v[j];
+        *reinterpret_cast<f4*>(Bs + (lane / 4 + 16 * j) * kChunk + (lane & 3) * 4) = v[2 + j];
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const float4 a0 = *reinterpret_cast<const float4*>(As + i * kStageLd + 8 * kh);
-      const float4 a1 = *reinterpret_cast<const float4*>(As + i * kStageLd + 8 * kh + 4);
-      const float4 b0 = *reinterpret_cast<const float4*>(Bs + i * kStageLd + 8 * kh);
-      const float4 b1 = *reinterpret_cast<const float4*>(Bs + i * kStageLd + 8 * kh + 4);
-      const float ar[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-      const float br[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-      const float cA = src >= 0 ? (float)(sg.c * sg.scl[i]) : 0.f;
-      const float sB = g.n0 + i < g.b ? 1.f : 0.f;
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        a[s] = s < kv ? cA * ar[s] : 0.f;
-        b[s] = s < kv ? sB * br[s] : 0.f;
-      }
-      // the stage is rewritten by the wave's next chunk only after these reads
-      __builtin_amdgcn_wave_barrier();
     }
   }
-  template <bool kStage>
-  __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
-                             const TileGeo& g, int lane, float* stage) {
-    float a[8], b[8];
-    operands<kStage>(R, sg, kind, K, ch, g, lane, stage, a, b);
+  __device__ static void split(const f4& x, s16x4& hi, s16x4& lo) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc.d = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s], b[s], acc.d, 0, 0, 0);
-  }
-  static constexpr int kRegs = 16;
-  __device__ static float value(const Acc& a, int r) { return a.d[r]; }
-  __device__ static void coords(int lane, int r, int& row, int& col) {
-    row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    col = lane & 31;
-  }
-};
-
-// BF16 hi/lo split on the matrix cores: v_mfma_f32_32x32x16_bf16, A[i][k]
-// from lane i + 32*(k/8), element k%8 (B likewise with column j); D as in the
-// FP32 32x32 layout.  Every FP32 operand x is split into hi = bf16(x) and
-// lo = bf16(x - hi); a product is hi*hi + hi*lo + lo*hi (the lo*lo term and
-// the rounding of lo leave a relative error of about 2^-16), accumulated in
-// FP32.  Raw loads and masking are those of the FP32 tile.
-struct BF16Tile {
-  using op_t = float;
-  using red_t = float;
-  static constexpr int kWaves = 16;
-  using Acc = F32Tile::Acc;
-  using Raw = F32Tile::Raw;
-  __device__ static void zero(Acc& a) { F32Tile::zero(a); }
-  template <bool kStage>
-  __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
-                              const op_t* dense, const double* psi, int lane) {
-    F32Tile::load<kStage>(R, sg, kind, K, ch, g, dense, psi, lane);
-  }
-  __device__ static void split(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < 4; ++j) {
       const __bf16 h = (__bf16)x[j];
-      hi[j] = h;
-      lo[j] = (__bf16)(x[j] - (float)h);
+      const __bf16 l = (__bf16)(x[j] - (float)h);
+      hi[j] = __builtin_bit_cast(short, h);
+      lo[j] = __builtin_bit_cast(short, l);
     }
   }
-  static constexpr int kStageFloats = F32Tile::kStageFloats;
-  template <bool kStage>
-  __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
-                             const TileGeo& g, int lane, float* stage) {
-    float a[8], b[8];
-    F32Tile::operands<kStage>(R, sg, kind, K, ch, g, lane, stage, a, b);
-    bf16x8 ah, al, bh, bl;
-    split(a, ah, al);
-    split(b, bh, bl);
-    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc.d, 0, 0, 0);
-    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc.d, 0, 0, 0);
-    acc.d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc.d, 0, 0, 0);
+  __device__ static void mma(Acc& acc, const Raw& R, const Use& u, int kind, int K, int ch, int lane,
+                             float* stage_area) {
+    float* As = stage_area;
+    float* Bs = stage_area + kAFloats;
+    // the previous chunk's reads of this area were issued before this point
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    stage(R, u, kind, K, ch, lane, As, Bs);
+    // the wave's LDS operations complete in order: its reads below see the
+    // writes above
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int i = lane & 15, kk = lane >> 4;
+    f4 a[2], b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) a[h] = *reinterpret_cast<const f4*>(As + (16 * h + i) * kChunk + 4 * kk);
+    if (kind == SEG_KN) {   // B[k][n] = scl[n] W[k][src n - base]
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) b[h][s] = u.sb[h] * Bs[(4 * kk + s) * kLdn + u.w[h]];
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) b[h] = *reinterpret_cast<const f4*>(Bs + (16 * h + i) * kChunk + 4 * kk);
+    }
+    if constexpr (kBF16) {
+      s16x4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        split(a[h], ah[h], al[h]);
+        split(b[h], bh[h], bl[h]);
+      }
+#pragma unroll
+      for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+        for (int qj = 0; qj < 2; ++qj) {
+          f32x4& d = acc.d[2 * qi + qj];
+          d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[qi], bh[qj], d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[qi], bl[qj], d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[qi], bh[qj], d, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+          for (int qj = 0; qj < 2; ++qj)
+            acc.d[2 * qi + qj] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(a[qi][s], b[qj][s], acc.d[2 * qi + qj], 0, 0, 0);
+    }
+  }
+  // The wave's chunks are wave, wave + kW, ... of the tile's chunk
+  // sequence; two are in flight ahead of the one on the matrix cores.
+  // Fetches are unconditional (one past the wave's last chunk reads
+  // nothing), so that every step issues the same loads and the compiler
+  // keeps them ahead of the work.
+  __device__ static void contract(Acc& acc, const uint32_t* img, int ngemm, int nchunk, const TileGeo& g,
+                                  int wave, int lane, const float* dense, const float* psi, int64_t ndense,
+                                  int64_t npsi, float* stage_area) {
+    const __amdgpu_buffer_rsrc_t rd = buf_rsrc(dense, 4 * ndense), rp = buf_rsrc(psi, 4 * npsi);
+    const int nmy = (nchunk - wave + kWaves - 1) / kWaves;
+    int si = 0;   // segment of the latest chunk fetched (chunks come in increasing order)
+    Fetch f;
+    f.seg = -1;
+    Use u;
+    u.seg = -1;
+    auto fetch = [&](Raw& R, int i, int& gc, int& s) {
+      const bool live = i < nmy;
+      gc = wave + kWaves * (live ? i : nmy - 1);
+      while (si + 1 < ngemm && gc >= rfl(img_seg(img, si + 1).ch0)) ++si;
+      s = si;
+      const ImgSeg& sg = img_seg(img, s);
+      if (s != f.seg) setup_fetch(f, s, sg, rfl(sg.kind), rfl(sg.K), g, lane);
+      load(R, f, gc - rfl(sg.ch0), live, rd, rp);
+    };
+    auto run = [&](const Raw& R, int gc, int s) {
+      const ImgSeg& sg = img_seg(img, s);
+      const int kind = rfl(sg.kind);
+      if (s != u.seg) setup_use(u, s, sg, kind, g, lane);
+      mma(acc, R, u, kind, rfl(sg.K), gc - rfl(sg.ch0), lane, stage_area);
+    };
+    Raw ra, rb;
+    int gA, sA, gB, sB;
+    fetch(ra, 0, gA, sA);
+    fetch(rb, 1, gB, sB);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int i = 0; i < nmy; i += 2) {
+      run(ra, gA, sA);
+      fetch(ra, i + 2, gA, sA);
+      __builtin_amdgcn_sched_barrier(0);
+      if (i + 1 < nmy) run(rb, gB, sB);
+      fetch(rb, i + 3, gB, sB);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   static constexpr int kRegs = 16;
-  __device__ static float value(const Acc& a, int r) { return a.d[r]; }
-  __device__ static void coords(int lane, int r, int& row, int& col) { F32Tile::coords(lane, r, row, col); }
+  __device__ static float value(const Acc& a, int r) { return a.d[r >> 2][r & 3]; }
+  __device__ static void coords(int lane, int r, int& row, int& col) {
+    const int q = r >> 2;
+    row = 16 * (q >> 1) + 4 * (lane >> 4) + (r & 3);
+    col = 16 * (q & 1) + (lane & 15);
+  }
 };
 
 // FP64 matrix cores, v_mfma_f64_16x16x4f64 on the four 16x16 quarters of the
@@ -497,6 +554,7 @@ struct BF16Tile {
 // carries k = 4q + s.
 struct F64Tile {
   using op_t = double;
+  using psi_t = double;
   using red_t = double;
   static constexpr int kWaves = 8;
   struct Acc {
@@ -513,7 +571,8 @@ struct F64Tile {
   }
   template <bool kStage>
   __device__ static void load(Raw& R, const ImgSeg& sg, int kind, int K, int ch, const TileGeo& g,
-                              const op_t* dense, const double* psi, int lane) {
+                              const op_t* dense, const double* psi, int lane, int64_t /*ndense*/,
+                              int64_t /*npsi*/, bool /*live*/ = true) {
     const int i = lane & 15, kb = ch * kChunk + 4 * (lane >> 4);
     if (kind == SEG_KN) {
       const op_t* A0 = dense + sg.op_off + min(g.m0 + i, g.a - 1);
@@ -567,7 +626,7 @@ struct F64Tile {
   static constexpr int kStageFloats = 0;   // rows are read per lane, no LDS stage
   template <bool kStage>
   __device__ static void mma(Acc& acc, const Raw& R, const ImgSeg& sg, int kind, int K, int ch,
-                             const TileGeo& g, int lane, float* /*stage*/) {
+                             const TileGeo& g, int lane, float* /*stage*/, const double* /*psi*/) {
     const int i = lane & 15, kv = K - ch * kChunk - 4 * (lane >> 4);
     const int src0 = sg.src[i], src1 = sg.src[16 + i];
     double cA0, cA1, sB0, sB1;
@@ -600,30 +659,79 @@ struct F64Tile {
     row = 16 * qi + 4 * (r & 3) + (lane >> 4);
     col = 16 * qj + (lane & 15);
   }
+  // The wave's chunks are wave, wave + kW, ...; their operands are loaded
+  // two chunks ahead of the matrix cores.
+  __device__ static void contract(Acc& acc, const uint32_t* img, int ngemm, int nchunk, const TileGeo& g,
+                                  int wave, int lane, const double* dense, const double* psi,
+                                  int64_t /*ndense*/, int64_t /*npsi*/, float* /*stage_area*/) {
+    Raw ra, rb;
+    int si = 0;   // segment of the latest chunk handed out (chunks come in increasing order)
+    auto seg_for = [&](int gc) {
+      while (si + 1 < ngemm && gc >= rfl(img_seg(img, si + 1).ch0)) ++si;
+      return si;
+    };
+    auto fetch = [&](Raw& R, int gc, int s) {
+      const ImgSeg& sg = img_seg(img, s);
+      load<false>(R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, dense, psi, lane, 0, 0);
+    };
+    auto run = [&](const Raw& R, int gc, int s) {
+      const ImgSeg& sg = img_seg(img, s);
+      mma<false>(acc, R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, lane, nullptr, psi);
+    };
+    int gA = wave, sA = seg_for(gA);
+    fetch(ra, gA, sA);
+    int gB = gA + kWaves, sB = 0;
+    if (gB < nchunk) {
+      sB = seg_for(gB);
+      fetch(rb, gB, sB);
+    }
+    for (;;) {
+      run(ra, gA, sA);
+      if (gB >= nchunk) break;
+      gA = gB + kWaves;
+      if (gA < nchunk) {
+        sA = seg_for(gA);
+        fetch(ra, gA, sA);
+      }
+      run(rb, gB, sB);
+      if (gA >= nchunk) break;
+      gB = gA + kWaves;
+      if (gB < nchunk) {
+        sB = seg_for(gB);
+        fetch(rb, gB, sB);
+      }
+    }
+  }
 };
 
-// Elementwise term at local element (mi, nj): c * rs * cs * psi[row + col].
-// A zero row or column has scale 0 in the image; its load is clamped to
-// psi[0] and dropped by that scale, so loads need no branch and the loads
-// of several terms go out together.
-__device__ inline double img_gg_load(const ImgGG& G, int mi, int nj, const double* psi) {
-  const int64_t row = G.row[mi];
-  const int32_t col = G.col[nj];
-  return psi[(row < 0 ? 0 : row) + (col < 0 ? 0 : col)];
+// Elementwise terms, c * rs[mi] * cs[nj] * psi[row(mi) + col(nj)].  Threads
+// 0 .. 255 take four consecutive columns of one tile row each; the loads of
+// the first kGGEarly terms go out before the contraction chunks' and are
+// summed after them (terms beyond re-read term 0's entries, dropped at the
+// sum).  A zero row or column has scale 0 in the image and reads psi[0], so
+// the loads need no branch.
+constexpr int kGGEarly = 4;
+constexpr int kGGThreads = kTile * kTile / 4;
+
+template <class PsiT>
+__device__ inline void gg_load4(const ImgGG& G, int mi, int nj4, const PsiT* psi, PsiT (&v)[4]) {
+  const int64_t row = G.row[mi] < 0 ? 0 : G.row[mi];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int32_t col = G.col[nj4 + e];
+    v[e] = psi[row + (col < 0 ? 0 : col)];
+  }
 }
 __device__ inline double img_gg_coef(const ImgGG& G, int mi, int nj) {
   return G.c * G.rs[mi] * G.cs[nj];
-}
-__device__ inline double img_gg_term(const ImgGG& G, int mi, int nj, const double* psi) {
-  const double v = img_gg_load(G, mi, nj, psi);
-  return img_gg_coef(G, mi, nj) * v;
 }
 
 template <class Cfg, bool kStage>
 __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
     const uint32_t* __restrict__ images, int32_t stride,
-    const typename Cfg::op_t* __restrict__ dense, const double* __restrict__ psi,
-    double* __restrict__ y, double alpha, double beta) {
+    const typename Cfg::op_t* __restrict__ dense, const typename Cfg::psi_t* __restrict__ psi,
+    double* __restrict__ y, double alpha, double beta, int64_t ndense, int64_t npsi) {
+  using psi_t = typename Cfg::psi_t;
   constexpr int kW = Cfg::kWaves;
   constexpr int kT = kW * 64;
   constexpr int kPer = kTile * kTile / kT;   // output elements per thread
@@ -633,6 +741,7 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
   constexpr size_t kRedBytes = sizeof(red_t) * kW * kTile * kTile;
   constexpr size_t kStageBytes = kStage ? sizeof(float) * kW * Cfg::kStageFloats : 0;
   __shared__ __align__(16) char pool[kRedBytes > kStageBytes ? kRedBytes : kStageBytes];
+  __shared__ double ggs[kTile * kTile];   // elementwise terms' sum per tile element
   auto red = reinterpret_cast<red_t(*)[kTile * kTile]>(pool);
 
   // phase 0: the slot's image into LDS
@@ -655,81 +764,42 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
   const int wave = rfl(threadIdx.x >> 6), lane = threadIdx.x & 63;
 
   // phase 1
+  const bool gg_thread = ngg > 0 && wave < kGGThreads / 64;   // uniform per wave
+  const int gmi = threadIdx.x >> 3, gnj = (threadIdx.x & 7) * 4;
+  psi_t gr[kGGEarly][4];
+  if (gg_thread) {
+#pragma unroll
+    for (int q = 0; q < kGGEarly; ++q) gg_load4(img_gg(img, ngemm, q < ngg ? q : 0), gmi, gnj, psi, gr[q]);
+  }
   typename Cfg::Acc acc;
   Cfg::zero(acc);
-  double ggv[kPer];
+  if (wave < nchunk)
+    Cfg::contract(acc, img, ngemm, nchunk, g, wave, lane, dense, psi, ndense, npsi,
+                  reinterpret_cast<float*>(pool) + wave * Cfg::kStageFloats);
+  if (gg_thread) {   // FP64 sum over the terms in order
+    // the raw values stay as loaded until here (the compiler would otherwise
+    // widen them next to their loads: an early wait and twice the registers)
 #pragma unroll
-  for (int e = 0; e < kPer; ++e) ggv[e] = 0.0;
-  // elementwise terms: their loads go out before the first chunks' (terms
-  // beyond ngg re-read term 0's), the FP64 sum in term order comes after
-  double ggt[kPer][kMaxGG];
-  auto gg_issue = [&]() {
-    if (ngg == 0) return;
+    for (int q = 0; q < kGGEarly; ++q)
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int el = threadIdx.x + e * kT;
+      for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(gr[q][e]));
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < kMaxGG; ++q)
-        ggt[e][q] = img_gg_load(img_gg(img, ngemm, q < ngg ? q : 0), el / kTile, el % kTile, psi);
-    }
-  };
-  auto gg_sum = [&]() {
-    if (ngg == 0) return;
+    for (int q = 0; q < kGGEarly; ++q)
+      if (q < ngg) {
+        const ImgGG& G = img_gg(img, ngemm, q);
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) {
-      const int el = threadIdx.x + e * kT;
-#pragma unroll
-      for (int q = 0; q < kMaxGG; ++q)
-        if (q < ngg) ggv[e] += img_gg_coef(img_gg(img, ngemm, q), el / kTile, el % kTile) * ggt[e][q];
-    }
-  };
-  if (wave < nchunk) {
-    typename Cfg::Raw ra, rb;
-    int si = 0;   // segment of the latest chunk handed out (chunks come in increasing order)
-    auto seg_for = [&](int gc) {
-      while (si + 1 < ngemm && gc >= rfl(img_seg(img, si + 1).ch0)) ++si;
-      return si;
-    };
-    auto fetch = [&](typename Cfg::Raw& R, int gc, int s) {
-      const ImgSeg& sg = img_seg(img, s);
-      Cfg::template load<kStage>(R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, dense, psi, lane);
-    };
-    float* stage = reinterpret_cast<float*>(pool) + wave * Cfg::kStageFloats;
-    auto run = [&](const typename Cfg::Raw& R, int gc, int s) {
-      const ImgSeg& sg = img_seg(img, s);
-      Cfg::template mma<kStage>(acc, R, sg, rfl(sg.kind), rfl(sg.K), gc - rfl(sg.ch0), g, lane, stage);
-    };
-    int gA = wave, sA = seg_for(gA);
-    gg_issue();
-    fetch(ra, gA, sA);
-    int gB = gA + kW, sB = 0;
-    if (gB < nchunk) {
-      sB = seg_for(gB);
-      fetch(rb, gB, sB);
-    }
-    // keep the scheduler from hoisting the sum (and its wait) above the
-    // second chunk's loads
-    __builtin_amdgcn_sched_barrier(0);
-    gg_sum();
-    for (;;) {
-      run(ra, gA, sA);
-      if (gB >= nchunk) break;
-      gA = gB + kW;
-      if (gA < nchunk) {
-        sA = seg_for(gA);
-        fetch(ra, gA, sA);
+        for (int e = 0; e < 4; ++e) v[e] += img_gg_coef(G, gmi, gnj + e) * (double)gr[q][e];
       }
-      run(rb, gB, sB);
-      if (gA >= nchunk) break;
-      gB = gA + kW;
-      if (gB < nchunk) {
-        sB = seg_for(gB);
-        fetch(rb, gB, sB);
-      }
+    for (int q = kGGEarly; q < ngg; ++q) {
+      const ImgGG& G = img_gg(img, ngemm, q);
+      psi_t t[4];
+      gg_load4(G, gmi, gnj, psi, t);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] += img_gg_coef(G, gmi, gnj + e) * (double)t[e];
     }
-  } else {
-    gg_issue();
-    gg_sum();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ggs[gmi * kTile + gnj + e] = v[e];
   }
   __syncthreads();   // every wave is done with its chunk stage
   if (wave < nchunk) {
@@ -752,8 +822,7 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
     const int mi = el / kTile, nj = el % kTile;
     double v = 0.0;
     for (int w = 0; w < nw; ++w) v += (double)red[w][el];
-    v += ggv[e];
-    for (int q = kMaxGG; q < ngg; ++q) v += img_gg_term(img_gg(img, ngemm, q), mi, nj, psi);
+    if (ngg > 0) v += ggs[el];
     const int m = g.m0 + mi, n = g.n0 + nj;
     if (m < g.a && n < g.b) {
       const int64_t idx = y_off + (int64_t)m * ldy + n;
@@ -867,34 +936,47 @@ __global__ __launch_bounds__(256) void plain_segment(SegDesc sg, TileDesc t,
   if (m < t.a && n < t.b) y[t.y_off + (int64_t)m * t.b + n] += alpha * acc;
 }
 
+// psi in FP32 for the products that read an FP32 copy (one pass).
+__global__ __launch_bounds__(256) void psi_to_f32(const double* __restrict__ x, float* __restrict__ out,
+                                                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = (float)x[i];
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <class Cfg, bool kStage>
 void launch_tiles(int nslots, const uint32_t* images, int32_t stride, const void* dense,
-                  const double* psi, double* y, double alpha, double beta, hipStream_t stream,
-                  hipEvent_t t0, hipEvent_t t1) {
+                  const void* psi, double* y, double alpha, double beta, hipStream_t stream,
+                  hipEvent_t t0, hipEvent_t t1, int64_t ndense = 0, int64_t npsi = 0) {
   // hipExtLaunchKernelGGL records t0/t1 (when given) at the dispatch's own
   // start and end, so the interval is the kernel alone
   hipExtLaunchKernelGGL(hpsi_tiles<Cfg, kStage>, dim3(nslots), dim3(Cfg::kWaves * 64), 0, stream, t0,
-                        t1, 0, images, stride, (const typename Cfg::op_t*)dense, psi, y, alpha, beta);
+                        t1, 0, images, stride, (const typename Cfg::op_t*)dense,
+                        (const typename Cfg::psi_t*)psi, y, alpha, beta, ndense, npsi);
+}
+
+hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psi_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, psi, out, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
-                       hipStream_t stream, hipEvent_t t0, hipEvent_t t1) {
+                       hipStream_t stream, hipEvent_t t0, hipEvent_t t1, const float* psi32,
+                       int64_t ndense, int64_t npsi) {
   if (nslots <= 0) return hipSuccess;
-  const bool stage = variant == kVariantStagedRows;
-  if (prec == kPrecF32) {
-    if (stage)
-      launch_tiles<F32Tile, true>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
+  (void)variant;
+  if (prec == kPrecF32 || prec == kPrecBF16X3) {
+    if (!psi32 || npsi < 4 || ndense < 4) return hipErrorInvalidValue;
+    if (prec == kPrecF32)
+      launch_tiles<F32S<false>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0,
+                                             t1, ndense, npsi);
     else
-      launch_tiles<F32Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
-  } else if (prec == kPrecBF16X3) {
-    if (stage)
-      launch_tiles<BF16Tile, true>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
-    else
-      launch_tiles<BF16Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
+      launch_tiles<F32S<true>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0,
+                                            t1, ndense, npsi);
   } else {
     launch_tiles<F64Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
   }

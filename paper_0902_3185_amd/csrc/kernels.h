@@ -17,17 +17,20 @@ constexpr int kMaxSegPerBlock = 32;
 
 // y = alpha * H psi + beta * y with the fused kernel: nslots workgroups, slot
 // b working from the tile image at images + b * stride (words; see
-// build_images).  `dense` holds the operator pool in the kernel's precision
-// (double for F64, float for F32 and BF16X3).  `variant` selects how the
-// FP32 / BF16 kernel reads row-walking operands (kVariant*; results are
-// identical); the FP64 kernel has one.  Events t0/t1, when not null, are
-// recorded at the start and end of the kernel itself.
-constexpr int kVariantRowPerLane = 0;   // each lane reads its own row
-constexpr int kVariantStagedRows = 1;   // groups of lanes read whole rows, transposed through LDS
-constexpr int kVariants = 2;
+// build_images).  FP64: `dense` is the FP64 operator pool (A-side blocks
+// k-major) and psi the FP64 vector.  FP32 and BF16X3: `dense` is the FP32
+// pool (A-side blocks row-major, ndense elements) and psi32 an FP32 copy of
+// psi (npsi elements); both buffers must hold at least 4 elements (vector
+// loads are clamped inside them).  Events t0/t1, when not null, are recorded
+// at the start and end of the kernel itself.
+constexpr int kVariants = 1;
 hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
-                       hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                       hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
+                       const float* psi32 = nullptr, int64_t ndense = 0, int64_t npsi = 0);
+
+// out = (float) psi, n elements
+hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream);
 
 // partial[tile * stride + s] = < G tile, segment s of the tile with c = 1 >
 hipError_t launch_term_dots(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,

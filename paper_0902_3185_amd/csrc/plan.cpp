@@ -3,6 +3,7 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -126,6 +127,9 @@ dmrg_status stage_side(const dmrg_op* op, const dmrg_basis* b, bool a_side, bool
       if (a_side) {
         // k-major: element (m, kk) of the block at [kk * rows + m]
         sb.op_ld = rows;
+        plan.kmajor_off.push_back(sb.op_off);
+        plan.kmajor_rows.push_back(rows);
+        plan.kmajor_cols.push_back(cols);
         plan.dense.resize(plan.dense.size() + (size_t)rows * cols);
         double* dst = plan.dense.data() + sb.op_off;
         for (int32_t i = 0; i < rows; ++i)
@@ -357,7 +361,7 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
   // of the launch runs on XCD b % kXcds and takes the (b / kXcds)-th tile of
   // that XCD's list, most expensive first; the hardware starts each slot as
   // a compute unit frees up.
-  {
+  if (!std::getenv("DMRG_SCHED_BLOCKS")) {
     std::vector<int32_t> tidx(plan.tiles.size());
     for (size_t t = 0; t < tidx.size(); ++t) tidx[t] = (int32_t)t;
     std::stable_sort(tidx.begin(), tidx.end(),
@@ -375,6 +379,79 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
       load[best] += tile_cost[t];
       last_xcd[tile_pair[t]] = best;
     }
+    size_t rows = 0;
+    for (auto& l : lists) rows = std::max(rows, l.size());
+    plan.order.assign(rows * kXcds, -1);
+    for (int x = 0; x < kXcds; ++x)
+      for (size_t r = 0; r < lists[x].size(); ++r) plan.order[r * kXcds + x] = lists[x][r];
+  }
+  else {
+    // Block-grouped order: whole blocks go to the least loaded XCD (LPT on
+    // block cost); a block costing more than a share of its own is cut into
+    // rectangles of tiles, one per share, so that an XCD holds few row and
+    // column stripes of it.  Each XCD's list runs most expensive first.
+    int64_t total = 0;
+    std::vector<int64_t> bcost(npairs, 0);
+    std::vector<std::vector<int32_t>> btiles(npairs);
+    for (size_t t = 0; t < plan.tiles.size(); ++t) {
+      btiles[tile_pair[t]].push_back((int32_t)t);
+      bcost[tile_pair[t]] += tile_cost[t];
+      total += tile_cost[t];
+    }
+    const int64_t share = std::max<int64_t>(1, (total + kXcds - 1) / kXcds);
+    // work units: (cost, tiles)
+    std::vector<std::pair<int64_t, std::vector<int32_t>>> units;
+    for (int32_t p = 0; p < npairs; ++p) {
+      if (btiles[p].empty()) continue;
+      const int32_t a = plan.dS[plan.pair_s[p]], b = plan.dE[plan.pair_e[p]];
+      const int32_t tr = (a + kTile - 1) / kTile, tc = (b + kTile - 1) / kTile;
+      int parts = (int)std::min<int64_t>(kXcds, (bcost[p] + share - 1) / share);
+      parts = std::max(1, std::min(parts, tr * tc));
+      if (parts == 1) {
+        units.push_back({bcost[p], btiles[p]});
+        continue;
+      }
+      // a pr x pc grid of rectangles, pr * pc >= parts, as square as possible
+      int pr = 1, pc = parts;
+      for (int r = 1; r <= parts; ++r) {
+        const int c = (parts + r - 1) / r;
+        if (r > tr || c > tc) continue;
+        if (std::abs(r * (double)tc / tr - c) < std::abs(pr * (double)tc / tr - pc)) {
+          pr = r;
+          pc = c;
+        }
+      }
+      pr = std::min(pr, tr);
+      pc = std::min(pc, tc);
+      for (int ri = 0; ri < pr; ++ri)
+        for (int ci = 0; ci < pc; ++ci) {
+          const int r0 = ri * tr / pr, r1 = (ri + 1) * tr / pr;
+          const int c0 = ci * tc / pc, c1 = (ci + 1) * tc / pc;
+          std::vector<int32_t> u;
+          int64_t cst = 0;
+          for (int32_t t : btiles[p]) {
+            const int r = plan.tiles[t].m0 / kTile, c = plan.tiles[t].n0 / kTile;
+            if (r >= r0 && r < r1 && c >= c0 && c < c1) {
+              u.push_back(t);
+              cst += tile_cost[t];
+            }
+          }
+          if (!u.empty()) units.push_back({cst, u});
+        }
+    }
+    std::stable_sort(units.begin(), units.end(),
+                     [](const auto& x, const auto& y) { return x.first > y.first; });
+    std::vector<int64_t> load(kXcds, 0);
+    std::vector<std::vector<int32_t>> lists(kXcds);
+    for (auto& u : units) {
+      int best = 0;
+      for (int x = 1; x < kXcds; ++x)
+        if (load[x] < load[best]) best = x;
+      for (int32_t t : u.second) lists[best].push_back(t);
+      load[best] += u.first;
+    }
+    for (auto& l : lists)
+      std::stable_sort(l.begin(), l.end(), [&](int32_t x, int32_t y) { return tile_cost[x] > tile_cost[y]; });
     size_t rows = 0;
     for (auto& l : lists) rows = std::max(rows, l.size());
     plan.order.assign(rows * kXcds, -1);
@@ -404,12 +481,40 @@ bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>
       scl = src >= 0 ? gscale[g + idx] : 0.0;
     }
   };
+  // A SEG_KN segment reads Psi' through a window of 32 consecutive source
+  // columns; a tile whose gathered columns span more is given one image
+  // segment per window (each keeps only its own columns), all with the
+  // segment's coefficient and contraction.
+  auto windows = [&](const SegDesc& sg, const TileDesc& t) {
+    std::vector<std::pair<int32_t, std::vector<int32_t>>> w;   // (base column, tile columns)
+    std::vector<std::pair<int32_t, int32_t>> cols;             // (source column, tile column)
+    for (int32_t i = 0; i < kTile; ++i) {
+      int32_t src;
+      double scl;
+      gather(sg.gB, t.n0 + i, t.b, src, scl);
+      if (src >= 0) cols.push_back({src, i});
+    }
+    std::sort(cols.begin(), cols.end());
+    for (const auto& c : cols) {
+      if (w.empty() || c.first >= w.back().first + kTile) w.push_back({c.first, {}});
+      w.back().second.push_back(c.second);
+    }
+    return w;
+  };
+  auto image_segs = [&](const TileDesc& t) {
+    int32_t n = 0;
+    for (int32_t s = 0; s < t.ngemm; ++s) {
+      const SegDesc& sg = segs[t.seg0 + s];
+      n += sg.kind == SEG_KN ? (int32_t)windows(sg, t).size() : 1;
+    }
+    return n;
+  };
   int32_t words = kHdrWords;
   for (size_t slot = 0; slot < nslots; ++slot) {
     const int32_t ti = tile_of(slot);
     if (ti < 0) continue;
     const TileDesc& t = tiles[ti];
-    words = std::max(words, kHdrWords + t.ngemm * kSegWords + (t.nseg - t.ngemm) * kGGWords);
+    words = std::max(words, kHdrWords + image_segs(t) * kSegWords + (t.nseg - t.ngemm) * kGGWords);
   }
   if (words > kImgWords) {
     std::ostringstream os;
@@ -432,9 +537,8 @@ bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>
       h.m0 = t.m0;
       h.n0 = t.n0;
       h.ldy = t.ldy;
-      h.ngemm = t.ngemm;
       h.ngg = t.nseg - t.ngemm;
-      h.nchunk = t.nchunk;
+      int32_t nrec = 0, nch = 0;
       for (int32_t s = 0; s < t.ngemm; ++s) {
         const SegDesc& sg = segs[t.seg0 + s];
         ImgSeg r{};
@@ -445,15 +549,29 @@ bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>
         r.psi_off = sg.psi_off;
         r.op_off = sg.op_off;
         r.c = sg.c;
-        r.ch0 = sg.ch0;
-        for (int32_t i = 0; i < kTile; ++i) {
-          if (sg.kind == SEG_KN)
-            gather(sg.gB, t.n0 + i, t.b, r.src[i], r.scl[i]);
-          else
-            gather(sg.gA, t.m0 + i, t.a, r.src[i], r.scl[i]);
+        const int32_t c = (sg.K + kChunk - 1) / kChunk;
+        if (sg.kind == SEG_KN) {
+          for (const auto& win : windows(sg, t)) {
+            ImgSeg w = r;
+            for (int32_t i = 0; i < kTile; ++i) {
+              w.src[i] = -1;
+              w.scl[i] = 0.0;
+            }
+            for (int32_t i : win.second) gather(sg.gB, t.n0 + i, t.b, w.src[i], w.scl[i]);
+            w.pad = win.first;
+            w.ch0 = nch;
+            nch += c;
+            std::memcpy(img + kHdrWords + nrec++ * kSegWords, &w, sizeof(w));
+          }
+        } else {
+          for (int32_t i = 0; i < kTile; ++i) gather(sg.gA, t.m0 + i, t.a, r.src[i], r.scl[i]);
+          r.ch0 = nch;
+          nch += c;
+          std::memcpy(img + kHdrWords + nrec++ * kSegWords, &r, sizeof(r));
         }
-        std::memcpy(img + kHdrWords + s * kSegWords, &r, sizeof(r));
       }
+      h.ngemm = nrec;
+      h.nchunk = nch;
       for (int32_t q = 0; q < t.nseg - t.ngemm; ++q) {
         const SegDesc& sg = segs[t.seg0 + t.ngemm + q];
         ImgGG r{};
@@ -468,12 +586,24 @@ bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>
           r.col[i] = src;
           r.cs[i] = scl;
         }
-        std::memcpy(img + kHdrWords + t.ngemm * kSegWords + q * kGGWords, &r, sizeof(r));
+        std::memcpy(img + kHdrWords + nrec * kSegWords + q * kGGWords, &r, sizeof(r));
       }
     }
     std::memcpy(img, &h, sizeof(h));
   }
   return true;
+}
+
+void dense_f32(const Plan& p, std::vector<float>& out) {
+  out.assign(p.dense.size() + kPoolPad, 0.f);
+  for (size_t i = 0; i < p.dense.size(); ++i) out[i] = (float)p.dense[i];
+  for (size_t b = 0; b < p.kmajor_off.size(); ++b) {
+    const int64_t off = p.kmajor_off[b];
+    const int32_t rows = p.kmajor_rows[b], cols = p.kmajor_cols[b];
+    for (int32_t m = 0; m < rows; ++m)
+      for (int32_t k = 0; k < cols; ++k)
+        out[off + (int64_t)m * cols + k] = (float)p.dense[off + (int64_t)k * rows + m];
+  }
 }
 
 double plan_bytes_alg(const Plan& p, int elem_bytes) {

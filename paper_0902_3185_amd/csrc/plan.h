@@ -76,7 +76,7 @@ struct ImgSeg {
   int32_t kind, K, psi_ld, op_ld;
   int64_t psi_off, op_off;
   double c;
-  int32_t ch0, pad;
+  int32_t ch0, pad;   // SEG_KN: first source column of the segment's 32-column window
   int32_t src[kTile];   // gathered side (SEG_KN: columns, SEG_MK: rows): source index, -1 = zero
   double scl[kTile];    // and its scale
 };
@@ -122,6 +122,10 @@ struct Plan {
   std::vector<int32_t> order;     // workgroup slot -> tile (-1: idle), XCD-aware
   // staged operator data (FP64; converted at upload)
   std::vector<double> dense;      // dense pool
+  // A-side blocks of the pool, stored k-major (element (m, k) at off + k * rows + m);
+  // the FP32 pool holds them row-major (off + m * cols + k)
+  std::vector<int64_t> kmajor_off;
+  std::vector<int32_t> kmajor_rows, kmajor_cols;
   std::vector<int32_t> gsrc;      // gather pool: source index (-1: zero row)
   std::vector<double> gscale;     // gather pool: scale
   // statistics of one product
@@ -143,5 +147,10 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
 
 // Recomputes statistics for an element size of the staged operators.
 double plan_bytes_alg(const Plan& p, int elem_bytes);
+
+// The FP32 operator pool of a plan: the FP64 pool rounded, with the A-side
+// blocks row-major, plus kPoolPad zero elements at the end.
+constexpr int kPoolPad = 16;
+void dense_f32(const Plan& p, std::vector<float>& out);
 
 }  // namespace dmrg
