@@ -246,6 +246,18 @@ dmrg_status dmrg_sb_set_reorth(dmrg_sb sb, int32_t mode);
  * Asynchronous on the context's stream.                                    */
 dmrg_status dmrg_hpsi(dmrg_sb sb, const double* psi_d, double* y_d, double alpha, double beta);
 
+/* The product of dmrg_hpsi for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments and result, but every temporary (the
+ * FP32 copy of psi that the FP32 and BF16 products read) lives in a fixed
+ * device scratch array of 2^24 floats (64 MiB) that the library holds on
+ * each device from the first dmrg_ctx_create there until the process ends;
+ * the call makes no allocation and takes no timing events.  DMRG_E_NOMEM if
+ * D_in + 16 exceeds 2^24.  Calls on one device share the scratch: calls that
+ * overlap on one GPU (other host threads, other streams) race; calls queued
+ * on one stream do not.  Asynchronous on the context's stream.            */
+dmrg_status dmrg_hpsi_noalloc(dmrg_sb sb, const double* psi_d, double* y_d, double alpha, double beta);
+
 /* Adjoint of the product, for differentiation:
  *   gpsi_d = H^T g_d                 (device, length D, overwritten)
  *   gc_h[k] = < g, (A_k (x) B_k) psi >  (host, nterms values; may be NULL)

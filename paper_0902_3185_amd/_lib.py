@@ -81,6 +81,7 @@ _SIGS = {
     "dmrg_sb_set_coeffs": (C.c_int, [_P, _D]),
     "dmrg_sb_set_prec": (C.c_int, [_P, C.c_int]),
     "dmrg_hpsi": (C.c_int, [_P, _P, _P, C.c_double, C.c_double]),
+    "dmrg_hpsi_noalloc": (C.c_int, [_P, _P, _P, C.c_double, C.c_double]),
     "dmrg_hpsi_adjoint": (C.c_int, [_P, _P, _P, _P, _D]),
     "dmrg_lanczos_ground": (C.c_int, [_P, _P, C.c_int32, C.c_double, _D, _P,
                                       C.POINTER(C.c_int32), _D]),

@@ -448,6 +448,12 @@ dmrg_status dmrg_ctx_create(int device, void* hip_stream, dmrg_ctx* out) {
   HIP_TRY(hipGetDeviceProperties(&prop, device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(DMRG_E_DEVICE, std::string("libdmrg is built for gfx950, device is ") + prop.gcnArchName);
+  {
+    // the fixed scratch of dmrg_hpsi_noalloc on this device
+    DeviceGuard g(device);
+    if (!g.ok) return fail(DMRG_E_DEVICE, "hipSetDevice failed");
+    HIP_TRY(scratch_setup(device));
+  }
   auto* c = new dmrg_ctx_s();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -709,6 +715,37 @@ dmrg_status dmrg_hpsi(dmrg_sb sb, const double* psi_d, double* y_d, double alpha
   if (psi_d == y_d) return fail(DMRG_E_ARG, "psi and y must not overlap");
   DeviceGuard g(sb->ctx->device);
   return run_product(sb, sb->fwd, sb->prec, psi_d, y_d, alpha, beta);
+}
+
+dmrg_status dmrg_hpsi_noalloc(dmrg_sb sb, const double* psi_d, double* y_d, double alpha, double beta) {
+  dmrg_status st = need_device(sb);
+  if (st != DMRG_OK) return st;
+  if (!psi_d || !y_d) return fail(DMRG_E_ARG, "null vector");
+  if (psi_d == y_d) return fail(DMRG_E_ARG, "psi and y must not overlap");
+  DeviceGuard g(sb->ctx->device);
+  hipStream_t s = sb->ctx->stream;
+  Staged& f = sb->fwd;
+  const Plan& p = f.plan;
+  if (sb->prec == DMRG_FP64_PLAIN) {
+    HIP_TRY(launch_plain(f.plain, p.D, f.dense64.as<double>(), f.gsrc.as<int32_t>(), f.gscale.as<double>(),
+                         psi_d, y_d, alpha, beta, s));
+    return DMRG_OK;
+  }
+  const int kp = kernel_prec(sb->prec);
+  if (kp == kPrecF64)
+    return launch_fused(f, kp, sb->variant[kp], f.dense64.p, psi_d, y_d, alpha, beta, s, nullptr, nullptr);
+  if (!f.has32) return fail(DMRG_E_ARG, "FP32 operators not staged (use dmrg_sb_set_prec)");
+  float* buf = scratch_ptr(sb->ctx->device);
+  if (!buf) return fail(DMRG_E_DEVICE, "the fixed scratch was not set up on this device");
+  if (p.D_in + kPoolPad > kScratchFloats) {
+    std::ostringstream os;
+    os << "dmrg_hpsi_noalloc: the input vector (" << p.D_in << " elements, plus " << kPoolPad
+       << " of padding) exceeds the fixed scratch of " << kScratchFloats << " floats";
+    return fail(DMRG_E_NOMEM, os.str());
+  }
+  HIP_TRY(launch_psi_to_f32(psi_d, buf, p.D_in, s));
+  return launch_fused(f, kp, sb->variant[kp], f.dense32.p, psi_d, y_d, alpha, beta, s, nullptr, nullptr,
+                      buf);
 }
 
 dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d, double* gpsi_d,

@@ -936,11 +936,14 @@ __global__ __launch_bounds__(256) void plain_segment(SegDesc sg, TileDesc t,
   if (m < t.a && n < t.b) y[t.y_off + (int64_t)m * t.b + n] += alpha * acc;
 }
 
-// psi in FP32 for the products that read an FP32 copy (one pass).
+// psi in FP32 for the products that read an FP32 copy (one pass), and
+// kPoolPad zeros after it: the products' masked vector loads may reach
+// them, and a zero scale must not meet a NaN left in the buffer.
 __global__ __launch_bounds__(256) void psi_to_f32(const double* __restrict__ x, float* __restrict__ out,
                                                   int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) out[i] = (float)x[i];
+  else if (i < n + kPoolPad) out[i] = 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -958,8 +961,9 @@ void launch_tiles(int nslots, const uint32_t* images, int32_t stride, const void
 }
 
 hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psi_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, psi, out, n);
+  if (n < 0) return hipErrorInvalidValue;
+  const int64_t m = n + kPoolPad;
+  hipLaunchKernelGGL(psi_to_f32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, psi, out, n);
   return hipGetLastError();
 }
 

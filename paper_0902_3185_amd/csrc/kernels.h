@@ -29,8 +29,16 @@ hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images
                        hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
                        const float* psi32 = nullptr, int64_t ndense = 0, int64_t npsi = 0);
 
-// out = (float) psi, n elements
+// out[0 .. n) = (float) psi, out[n .. n + kPoolPad) = 0
 hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream);
+
+// The fixed device scratch of dmrg_hpsi_noalloc (noalloc.hip): kScratchFloats
+// floats per device.  scratch_setup(device) looks up the device's copy once
+// (hipGetSymbolAddress with that device current); scratch_ptr(device) returns
+// it afterwards, or null if it was never set up.
+constexpr int64_t kScratchFloats = (int64_t)1 << 24;   // 64 MiB
+hipError_t scratch_setup(int device);
+float* scratch_ptr(int device);
 
 // partial[tile * stride + s] = < G tile, segment s of the tile with c = 1 >
 hipError_t launch_term_dots(int prec, int ntiles, const TileDesc* tiles, const SegDesc* segs,
