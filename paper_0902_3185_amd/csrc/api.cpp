@@ -167,6 +167,8 @@ struct Staged {
   DevBuf tiles, segs, gsrc, gscale, dense64, dense32;
   DevBuf images;            // one tile image per workgroup slot of the fused kernel
   DevBuf psi32;             // FP32 copy of the input vector (products that read one)
+  DevBuf wg_start;          // persistent launch: each workgroup's slots
+  int32_t nwg = 0;
   int32_t img_stride = 0;   // words per image
   int32_t nslots = 0;
   bool has32 = false;
@@ -202,6 +204,8 @@ struct dmrg_ctx_s {
   std::vector<hipEvent_t> spare;
   // Lanczos workspace (grow-only)
   DevBuf V, w, partial, small;
+  DevBuf v32;          // FP32 copy of the next product's input (reduced-precision cycles)
+  size_t v32_n = 0;    // its padded length (the padding is zero)
   double* host_small = nullptr;   // pinned, for per-iteration scalars
   size_t host_small_n = 0;
   double* host_rho = nullptr;     // pinned, density-matrix blocks on their way to the host
@@ -263,6 +267,11 @@ dmrg_status stage_images(Staged& st, hipStream_t s) {
   st.nslots = (int32_t)st.plan.order.size();
   dmrg_status r = upload(st.images, img.data(), img.size() * sizeof(uint32_t), s);
   if (r != DMRG_OK) return r;
+  st.nwg = (int32_t)st.plan.wg_start.size() - 1;
+  if (st.nwg > 0 &&
+      (r = upload(st.wg_start, st.plan.wg_start.data(), st.plan.wg_start.size() * sizeof(int32_t), s)) !=
+          DMRG_OK)
+    return r;
   HIP_TRY(hipStreamSynchronize(s));   // the host image vector dies here
   return DMRG_OK;
 }
@@ -322,9 +331,10 @@ hipError_t take_event(dmrg_ctx c, hipEvent_t* e) {
 dmrg_status launch_fused(Staged& st, int kp, int variant, const void* dense, const double* psi,
                          double* y, double alpha, double beta, hipStream_t s, hipEvent_t t0,
                          hipEvent_t t1, const float* psi32 = nullptr) {
+  const int32_t* wgs = st.nwg > 0 ? st.wg_start.as<int32_t>() : nullptr;
   if (kp == kPrecF64) {
     HIP_TRY(launch_hpsi(kp, variant, st.nslots, st.images.as<uint32_t>(), st.img_stride, dense, psi, y,
-                        alpha, beta, s, t0, t1));
+                        alpha, beta, s, t0, t1, nullptr, 0, 0, wgs, st.nwg));
     return DMRG_OK;
   }
   const int64_t n = st.plan.D_in + kPoolPad;
@@ -335,32 +345,36 @@ dmrg_status launch_fused(Staged& st, int kp, int variant, const void* dense, con
   }
   const int64_t ndense = (int64_t)st.plan.dense.size() + kPoolPad;
   HIP_TRY(launch_hpsi(kp, variant, st.nslots, st.images.as<uint32_t>(), st.img_stride, dense, psi, y,
-                      alpha, beta, s, t0, t1, psi32, ndense, n));
+                      alpha, beta, s, t0, t1, psi32, ndense, n, wgs, st.nwg));
   return DMRG_OK;
 }
 
 dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
-                              double alpha, double beta, hipEvent_t t0, hipEvent_t t1);
+                              double alpha, double beta, hipEvent_t t0, hipEvent_t t1,
+                              const float* psi32);
 
 // y = alpha H psi + beta y with a given plan and precision (timed if asked).
+// psi32, if given, already holds psi in FP32 with the padding the FP32 and
+// BF16 products read (used by those precisions only).
 dmrg_status run_product(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
-                        double alpha, double beta) {
+                        double alpha, double beta, const float* psi32 = nullptr) {
   dmrg_ctx c = sb->ctx;
-  if (c->timing <= 0) return run_product_inner(sb, st, prec, psi, y, alpha, beta, nullptr, nullptr);
+  if (c->timing <= 0) return run_product_inner(sb, st, prec, psi, y, alpha, beta, nullptr, nullptr, psi32);
   if ((int)prec >= 0 && (int)prec < 4) ++c->products[(int)prec];
   if (c->tick++ % c->timing != 0)
-    return run_product_inner(sb, st, prec, psi, y, alpha, beta, nullptr, nullptr);
+    return run_product_inner(sb, st, prec, psi, y, alpha, beta, nullptr, nullptr, psi32);
   dmrg_ctx_s::Mark mk;
   HIP_TRY(take_event(c, &mk.a));
   HIP_TRY(take_event(c, &mk.b));
   mk.prec = (int)prec;
-  dmrg_status st2 = run_product_inner(sb, st, prec, psi, y, alpha, beta, mk.a, mk.b);
+  dmrg_status st2 = run_product_inner(sb, st, prec, psi, y, alpha, beta, mk.a, mk.b, psi32);
   c->marks.push_back(mk);
   return st2;
 }
 
 dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const double* psi, double* y,
-                              double alpha, double beta, hipEvent_t t0, hipEvent_t t1) {
+                              double alpha, double beta, hipEvent_t t0, hipEvent_t t1,
+                              const float* psi32) {
   hipStream_t s = sb->ctx->stream;
   const Plan& p = st.plan;
   if (prec == DMRG_FP64_PLAIN) {
@@ -376,7 +390,7 @@ dmrg_status run_product_inner(dmrg_sb sb, Staged& st, dmrg_prec prec, const doub
     dense = st.dense32.p;
   }
   const int kp = kernel_prec(prec);
-  return launch_fused(st, kp, sb->variant[kp], dense, psi, y, alpha, beta, s, t0, t1);
+  return launch_fused(st, kp, sb->variant[kp], dense, psi, y, alpha, beta, s, t0, t1, psi32);
 }
 
 dmrg_status need_device(dmrg_sb sb) {
@@ -826,6 +840,18 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
     HIP_TRY(hipHostMalloc((void**)&ctx->host_small, nsmall * sizeof(double), hipHostMallocDefault));
     ctx->host_small_n = nsmall;
   }
+  // reduced precision: the FP32 copy of the next product's input, with the
+  // zero padding past its end that the products' masked loads may reach
+  float* v32 = nullptr;
+  if (reduced) {
+    const size_t n32 = (size_t)D + kPoolPad;
+    if (ctx->v32_n < n32 || !ctx->v32.p) {
+      HIP_TRY(ctx->v32.ensure(n32 * sizeof(float)));
+      ctx->v32_n = n32;
+    }
+    v32 = ctx->v32.as<float>();
+    HIP_TRY(hipMemsetAsync(v32 + D, 0, kPoolPad * sizeof(float), s));
+  }
   double* V = ctx->V.as<double>();
   double* w = ctx->w.as<double>();
   double* part = ctx->partial.as<double>();
@@ -933,22 +959,25 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
       const bool two = j == 0 || twice;
       const bool recurrence = !two && !(j & 1);
-      if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0)) != DMRG_OK) return st;
+      // a reduced-precision product reads the FP32 copy of its input that the
+      // previous step wrote beside it (no conversion pass)
+      if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0, p == sb->prec ? v32 : nullptr)) != DMRG_OK)
+        return st;
       ++total;
       double* vnext = j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr;
       if (two) {
-        HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j, vnext, s));
+        HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j, vnext, s, v32));
       } else if (!recurrence) {
         // the recurrence and one pass against the basis; the new vector
         // stays unnormalised until the next step, which normalises it in
         // place (no separate finishing launch)
         HIP_TRY(launch_lz_step_onepass(w, V, D, j + 1, D, h1, part, j >= 2 ? npb[(j - 1) & 1] : nullptr,
                                        j >= 2 ? nullptr : ab + 2 * (j - 1) + 1, npb[j & 1], scale,
-                                       ab + 2 * j, vnext, s));
+                                       ab + 2 * j, vnext, s, v32));
       } else {
         // the recurrence alone
         HIP_TRY(launch_lz_step_recurrence(w, V, D, j + 1, D, part, npb[(j - 1) & 1], npb[j & 1],
-                                          ab + 2 * j, vnext, s));
+                                          ab + 2 * j, vnext, s, v32));
       }
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;

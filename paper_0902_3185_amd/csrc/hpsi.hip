@@ -730,7 +730,8 @@ template <class Cfg, bool kStage>
 __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
     const uint32_t* __restrict__ images, int32_t stride,
     const typename Cfg::op_t* __restrict__ dense, const typename Cfg::psi_t* __restrict__ psi,
-    double* __restrict__ y, double alpha, double beta, int64_t ndense, int64_t npsi) {
+    double* __restrict__ y, double alpha, double beta, int64_t ndense, int64_t npsi,
+    const int32_t* __restrict__ wg_start) {
   using psi_t = typename Cfg::psi_t;
   constexpr int kW = Cfg::kWaves;
   constexpr int kT = kW * 64;
@@ -744,9 +745,14 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
   __shared__ double ggs[kTile * kTile];   // elementwise terms' sum per tile element
   auto red = reinterpret_cast<red_t(*)[kTile * kTile]>(pool);
 
+  // the workgroup's slots: a list (persistent launch) or its own index
+  const int slot0 = wg_start ? wg_start[blockIdx.x] : (int)blockIdx.x;
+  const int slot1 = wg_start ? wg_start[blockIdx.x + 1] : (int)blockIdx.x + 1;
+  for (int slot = slot0; slot < slot1; ++slot) {
   // phase 0: the slot's image into LDS
+  if (slot > slot0) __syncthreads();   // the previous tile is done with LDS
   {
-    const uint4* src = reinterpret_cast<const uint4*>(images + (int64_t)blockIdx.x * stride);
+    const uint4* src = reinterpret_cast<const uint4*>(images + (int64_t)slot * stride);
     uint4* dst = reinterpret_cast<uint4*>(img);
     for (int x = threadIdx.x; x < stride / 4; x += kT) dst[x] = src[x];
   }
@@ -754,7 +760,7 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
   const ImgHeader& H = img_header(img);
   TileGeo g;
   g.a = rfl(H.a);
-  if (g.a == 0) return;   // idle slot
+  if (g.a == 0) continue;   // idle slot
   g.b = rfl(H.b);
   g.m0 = rfl(H.m0);
   g.n0 = rfl(H.n0);
@@ -766,16 +772,27 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
   // phase 1
   const bool gg_thread = ngg > 0 && wave < kGGThreads / 64;   // uniform per wave
   const int gmi = threadIdx.x >> 3, gnj = (threadIdx.x & 7) * 4;
-  psi_t gr[kGGEarly][4];
-  if (gg_thread) {
-#pragma unroll
-    for (int q = 0; q < kGGEarly; ++q) gg_load4(img_gg(img, ngemm, q < ngg ? q : 0), gmi, gnj, psi, gr[q]);
-  }
   typename Cfg::Acc acc;
   Cfg::zero(acc);
   if (wave < nchunk)
     Cfg::contract(acc, img, ngemm, nchunk, g, wave, lane, dense, psi, ndense, npsi,
                   reinterpret_cast<float*>(pool) + wave * Cfg::kStageFloats);
+  // the elementwise terms' loads go out now (their latency overlaps the
+  // wait for the other waves and the partial tiles' store)
+  psi_t gr[kGGEarly][4];
+  if (gg_thread) {
+#pragma unroll
+    for (int q = 0; q < kGGEarly; ++q) gg_load4(img_gg(img, ngemm, q < ngg ? q : 0), gmi, gnj, psi, gr[q]);
+  }
+  __syncthreads();   // every wave is done with its chunk stage
+  if (wave < nchunk) {
+#pragma unroll
+    for (int r = 0; r < Cfg::kRegs; ++r) {
+      int row, col;
+      Cfg::coords(lane, r, row, col);
+      red[wave][row * kTile + col] = Cfg::value(acc, r);
+    }
+  }
   if (gg_thread) {   // FP64 sum over the terms in order
     // the raw values stay as loaded until here (the compiler would otherwise
     // widen them next to their loads: an early wait and twice the registers)
@@ -801,15 +818,6 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
 #pragma unroll
     for (int e = 0; e < 4; ++e) ggs[gmi * kTile + gnj + e] = v[e];
   }
-  __syncthreads();   // every wave is done with its chunk stage
-  if (wave < nchunk) {
-#pragma unroll
-    for (int r = 0; r < Cfg::kRegs; ++r) {
-      int row, col;
-      Cfg::coords(lane, r, row, col);
-      red[wave][row * kTile + col] = Cfg::value(acc, r);
-    }
-  }
   __syncthreads();
 
   // phase 2: fixed-order sum, elementwise terms, y
@@ -829,6 +837,7 @@ __global__ __launch_bounds__(Cfg::kWaves * 64) void hpsi_tiles(
       y[idx] = beta == 0.0 ? alpha * v : alpha * v + beta * y[idx];
     }
   }
+  }   // slots
 }
 
 // ---------------------------------------------------------------------------
@@ -952,12 +961,13 @@ __global__ __launch_bounds__(256) void psi_to_f32(const double* __restrict__ x, 
 template <class Cfg, bool kStage>
 void launch_tiles(int nslots, const uint32_t* images, int32_t stride, const void* dense,
                   const void* psi, double* y, double alpha, double beta, hipStream_t stream,
-                  hipEvent_t t0, hipEvent_t t1, int64_t ndense = 0, int64_t npsi = 0) {
+                  hipEvent_t t0, hipEvent_t t1, int64_t ndense, int64_t npsi, const int32_t* wg_start,
+                  int nwg) {
   // hipExtLaunchKernelGGL records t0/t1 (when given) at the dispatch's own
   // start and end, so the interval is the kernel alone
-  hipExtLaunchKernelGGL(hpsi_tiles<Cfg, kStage>, dim3(nslots), dim3(Cfg::kWaves * 64), 0, stream, t0,
-                        t1, 0, images, stride, (const typename Cfg::op_t*)dense,
-                        (const typename Cfg::psi_t*)psi, y, alpha, beta, ndense, npsi);
+  hipExtLaunchKernelGGL(hpsi_tiles<Cfg, kStage>, dim3(wg_start ? nwg : nslots), dim3(Cfg::kWaves * 64), 0,
+                        stream, t0, t1, 0, images, stride, (const typename Cfg::op_t*)dense,
+                        (const typename Cfg::psi_t*)psi, y, alpha, beta, ndense, npsi, wg_start);
 }
 
 hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream) {
@@ -970,19 +980,21 @@ hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream
 hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
                        hipStream_t stream, hipEvent_t t0, hipEvent_t t1, const float* psi32,
-                       int64_t ndense, int64_t npsi) {
+                       int64_t ndense, int64_t npsi, const int32_t* wg_start, int nwg) {
   if (nslots <= 0) return hipSuccess;
+  if (wg_start && nwg <= 0) return hipErrorInvalidValue;
   (void)variant;
   if (prec == kPrecF32 || prec == kPrecBF16X3) {
     if (!psi32 || npsi < 4 || ndense < 4) return hipErrorInvalidValue;
     if (prec == kPrecF32)
-      launch_tiles<F32S<false>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0,
-                                             t1, ndense, npsi);
+      launch_tiles<F32S<false>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0, t1,
+                                      ndense, npsi, wg_start, nwg);
     else
-      launch_tiles<F32S<true>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0,
-                                            t1, ndense, npsi);
+      launch_tiles<F32S<true>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0, t1,
+                                     ndense, npsi, wg_start, nwg);
   } else {
-    launch_tiles<F64Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1);
+    launch_tiles<F64Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1, 0, 0,
+                                 wg_start, nwg);
   }
   return hipGetLastError();
 }

@@ -15,9 +15,11 @@ constexpr int kPrecF32 = 1;
 constexpr int kPrecBF16X3 = 2;
 constexpr int kMaxSegPerBlock = 32;
 
-// y = alpha * H psi + beta * y with the fused kernel: nslots workgroups, slot
-// b working from the tile image at images + b * stride (words; see
-// build_images).  FP64: `dense` is the FP64 operator pool (A-side blocks
+// y = alpha * H psi + beta * y with the fused kernel, from the tile images
+// at images + slot * stride (words; see build_images): with wg_start null,
+// nslots workgroups, workgroup b taking slot b; else nwg workgroups (a
+// persistent launch), workgroup w taking slots wg_start[w] ..
+// wg_start[w + 1] - 1 (a device array of nwg + 1 entries).  FP64: `dense` is the FP64 operator pool (A-side blocks
 // k-major) and psi the FP64 vector.  FP32 and BF16X3: `dense` is the FP32
 // pool (A-side blocks row-major, ndense elements) and psi32 an FP32 copy of
 // psi (npsi elements); both buffers must hold at least 4 elements (vector
@@ -27,7 +29,8 @@ constexpr int kVariants = 1;
 hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
                        hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
-                       const float* psi32 = nullptr, int64_t ndense = 0, int64_t npsi = 0);
+                       const float* psi32 = nullptr, int64_t ndense = 0, int64_t npsi = 0,
+                       const int32_t* wg_start = nullptr, int nwg = 0);
 
 // out[0 .. n) = (float) psi, out[n .. n + kPoolPad) = 0
 hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream);
@@ -80,9 +83,11 @@ hipError_t launch_normalise(double* dst, const double* src, const double* nrm2, 
 // h1[j] + h2[j], ab[1] = beta_j = ||w||; vnext = w / beta_j (if vnext is not
 // null).  partial needs lz_partial_size(n, nv) doubles.
 size_t lz_partial_size(int64_t n, int nv);
+// vnext32 (if not null, with vnext): an FP32 copy of vnext, for an FP32
+// product of it (the same holds for out32 below).
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
-                          hipStream_t stream);
+                          hipStream_t stream, float* vnext32 = nullptr);
 
 // A single-pass step (nv >= 2): the local three-term recurrence (alpha_j =
 // <v_j, H v_j>, beta_{j-1}) followed by one Gram-Schmidt pass on the
@@ -102,7 +107,7 @@ size_t lz_norm_partials(int64_t n);
 hipError_t launch_lz_step_onepass(double* w, double* V, int64_t ldv, int nv, int64_t n, double* h,
                                   double* partial, const double* npend, const double* beta_prev,
                                   double* nout, double* scale, double* ab, double* out,
-                                  hipStream_t stream);
+                                  hipStream_t stream, float* out32 = nullptr);
 
 // A recurrence-only step (nv >= 2, j = nv - 1): no pass over the basis.
 // V_j is stored unnormalised by the previous step (npend = that step's
@@ -113,7 +118,8 @@ hipError_t launch_lz_step_onepass(double* w, double* V, int64_t ldv, int nv, int
 // lz_norm_partials(n) doubles.  w is not modified.
 hipError_t launch_lz_step_recurrence(const double* w, double* V, int64_t ldv, int nv, int64_t n,
                                      double* partial, const double* npend, double* nout,
-                                     double* ab, double* out, hipStream_t stream);
+                                     double* ab, double* out, hipStream_t stream,
+                                     float* out32 = nullptr);
 
 // *out = sqrt(sum of the lz_norm_partials(n) partial sums at npart), in the
 // order launch_lz_step_onepass and launch_lz_step_recurrence add them.

@@ -3,7 +3,6 @@
 #include "plan.h"
 
 #include <algorithm>
-#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -330,8 +329,10 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
         if (gathered) plan.flops_alg += 2.0 * sg.K * (sg.kind == SEG_KN ? b : a);
       }
     }
-    // a tile's time is set by the chunks each of the workgroup's waves takes
-    const int64_t tcost = 8 + cost;
+    // a tile's time: a fixed part (image, first loads, reduction and stores,
+    // about as long as 25 contraction chunks) and its chunks and elementwise
+    // terms
+    const int64_t tcost = 100 + cost;
     for (int32_t m0 = 0; m0 < a; m0 += kTile)
       for (int32_t n0 = 0; n0 < b; n0 += kTile) {
         TileDesc t{};
@@ -352,111 +353,48 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
         plan.gemm_elems += kpad;
       }
   }
-  // XCD-aware order.  Tiles go to the XCDs by LPT on their cost (most
-  // expensive first, each to the least loaded XCD), so that every XCD ends
-  // at about the same time even when a few large blocks hold most of the
-  // work.  A tile stays on the XCD that took the previous tile of its block
-  // while that XCD is within one tile's cost of the least loaded one, so
-  // that a block's operators and psi rows are fetched into few L2s.  Slot b
-  // of the launch runs on XCD b % kXcds and takes the (b / kXcds)-th tile of
-  // that XCD's list, most expensive first; the hardware starts each slot as
-  // a compute unit frees up.
-  if (!std::getenv("DMRG_SCHED_BLOCKS")) {
-    std::vector<int32_t> tidx(plan.tiles.size());
-    for (size_t t = 0; t < tidx.size(); ++t) tidx[t] = (int32_t)t;
+  // Work lists of the persistent launch: min(kPersistentWGs, tiles)
+  // workgroups, one per compute unit, each taking a list of tiles.  Tiles go
+  // to the lists by LPT on their estimated cost (longest first, each to the
+  // least loaded list), so that every compute unit ends at about the same
+  // time even when a few large blocks hold most of the work; a tile stays
+  // on the XCD (workgroup w runs on XCD w % kXcds) of the previous tile of
+  // its block when a list there is about as lightly loaded as the least
+  // loaded one (within a quarter of the tile's cost), so that a block's
+  // operators and psi rows are fetched into few L2s without stacking tiles
+  // on one compute unit while another idles.  Within a list the most
+  // expensive tile runs first.
+  {
+    const int ntiles = (int)plan.tiles.size();
+    const int nwg = std::max(1, std::min(kPersistentWGs, ntiles));
+    std::vector<int32_t> tidx(ntiles);
+    for (int t = 0; t < ntiles; ++t) tidx[t] = t;
     std::stable_sort(tidx.begin(), tidx.end(),
                      [&](int32_t x, int32_t y) { return tile_cost[x] > tile_cost[y]; });
-    std::vector<int64_t> load(kXcds, 0);
+    std::vector<int64_t> load(nwg, 0);
     std::vector<int32_t> last_xcd(npairs, -1);
-    std::vector<std::vector<int32_t>> lists(kXcds);
+    std::vector<std::vector<int32_t>> lists(nwg);
     for (int32_t t : tidx) {
       int best = 0;
-      for (int x = 1; x < kXcds; ++x)
-        if (load[x] < load[best]) best = x;
+      for (int w = 1; w < nwg; ++w)
+        if (load[w] < load[best]) best = w;
       const int pref = last_xcd[tile_pair[t]];
-      if (pref >= 0 && load[pref] <= load[best] + tile_cost[t]) best = pref;
+      if (pref >= 0 && best % kXcds != pref) {
+        int alt = -1;
+        for (int w = pref; w < nwg; w += kXcds)
+          if (alt < 0 || load[w] < load[alt]) alt = w;
+        if (alt >= 0 && 4 * load[alt] <= 4 * load[best] + tile_cost[t]) best = alt;
+      }
       lists[best].push_back(t);
       load[best] += tile_cost[t];
-      last_xcd[tile_pair[t]] = best;
+      last_xcd[tile_pair[t]] = best % kXcds;
     }
-    size_t rows = 0;
-    for (auto& l : lists) rows = std::max(rows, l.size());
-    plan.order.assign(rows * kXcds, -1);
-    for (int x = 0; x < kXcds; ++x)
-      for (size_t r = 0; r < lists[x].size(); ++r) plan.order[r * kXcds + x] = lists[x][r];
-  }
-  else {
-    // Block-grouped order: whole blocks go to the least loaded XCD (LPT on
-    // block cost); a block costing more than a share of its own is cut into
-    // rectangles of tiles, one per share, so that an XCD holds few row and
-    // column stripes of it.  Each XCD's list runs most expensive first.
-    int64_t total = 0;
-    std::vector<int64_t> bcost(npairs, 0);
-    std::vector<std::vector<int32_t>> btiles(npairs);
-    for (size_t t = 0; t < plan.tiles.size(); ++t) {
-      btiles[tile_pair[t]].push_back((int32_t)t);
-      bcost[tile_pair[t]] += tile_cost[t];
-      total += tile_cost[t];
+    plan.order.clear();
+    plan.wg_start.assign(1, 0);
+    for (auto& l : lists) {
+      for (int32_t t : l) plan.order.push_back(t);
+      plan.wg_start.push_back((int32_t)plan.order.size());
     }
-    const int64_t share = std::max<int64_t>(1, (total + kXcds - 1) / kXcds);
-    // work units: (cost, tiles)
-    std::vector<std::pair<int64_t, std::vector<int32_t>>> units;
-    for (int32_t p = 0; p < npairs; ++p) {
-      if (btiles[p].empty()) continue;
-      const int32_t a = plan.dS[plan.pair_s[p]], b = plan.dE[plan.pair_e[p]];
-      const int32_t tr = (a + kTile - 1) / kTile, tc = (b + kTile - 1) / kTile;
-      int parts = (int)std::min<int64_t>(kXcds, (bcost[p] + share - 1) / share);
-      parts = std::max(1, std::min(parts, tr * tc));
-      if (parts == 1) {
-        units.push_back({bcost[p], btiles[p]});
-        continue;
-      }
-      // a pr x pc grid of rectangles, pr * pc >= parts, as square as possible
-      int pr = 1, pc = parts;
-      for (int r = 1; r <= parts; ++r) {
-        const int c = (parts + r - 1) / r;
-        if (r > tr || c > tc) continue;
-        if (std::abs(r * (double)tc / tr - c) < std::abs(pr * (double)tc / tr - pc)) {
-          pr = r;
-          pc = c;
-        }
-      }
-      pr = std::min(pr, tr);
-      pc = std::min(pc, tc);
-      for (int ri = 0; ri < pr; ++ri)
-        for (int ci = 0; ci < pc; ++ci) {
-          const int r0 = ri * tr / pr, r1 = (ri + 1) * tr / pr;
-          const int c0 = ci * tc / pc, c1 = (ci + 1) * tc / pc;
-          std::vector<int32_t> u;
-          int64_t cst = 0;
-          for (int32_t t : btiles[p]) {
-            const int r = plan.tiles[t].m0 / kTile, c = plan.tiles[t].n0 / kTile;
-            if (r >= r0 && r < r1 && c >= c0 && c < c1) {
-              u.push_back(t);
-              cst += tile_cost[t];
-            }
-          }
-          if (!u.empty()) units.push_back({cst, u});
-        }
-    }
-    std::stable_sort(units.begin(), units.end(),
-                     [](const auto& x, const auto& y) { return x.first > y.first; });
-    std::vector<int64_t> load(kXcds, 0);
-    std::vector<std::vector<int32_t>> lists(kXcds);
-    for (auto& u : units) {
-      int best = 0;
-      for (int x = 1; x < kXcds; ++x)
-        if (load[x] < load[best]) best = x;
-      for (int32_t t : u.second) lists[best].push_back(t);
-      load[best] += u.first;
-    }
-    for (auto& l : lists)
-      std::stable_sort(l.begin(), l.end(), [&](int32_t x, int32_t y) { return tile_cost[x] > tile_cost[y]; });
-    size_t rows = 0;
-    for (auto& l : lists) rows = std::max(rows, l.size());
-    plan.order.assign(rows * kXcds, -1);
-    for (int x = 0; x < kXcds; ++x)
-      for (size_t r = 0; r < lists[x].size(); ++r) plan.order[r * kXcds + x] = lists[x][r];
   }
   plan.bytes_dense = 8.0 * plan.dense.size();
   return DMRG_OK;

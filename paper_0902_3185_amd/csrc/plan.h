@@ -53,6 +53,7 @@ struct TileDesc {
 };
 
 constexpr int kXcds = 8;     // MI355X: 8 XCDs; workgroup b runs on XCD b % 8
+constexpr int kPersistentWGs = 256;   // one workgroup per compute unit
 
 constexpr int kTile = 32;    // output tile edge
 constexpr int kChunk = 16;   // contraction chunk
@@ -119,7 +120,11 @@ struct Plan {
   std::vector<SegDesc> segs;      // grouped by output pair
   std::vector<int32_t> pair_seg0, pair_nseg;
   std::vector<TileDesc> tiles;    // sorted by decreasing cost
-  std::vector<int32_t> order;     // workgroup slot -> tile (-1: idle), XCD-aware
+  // The fused product runs one workgroup per compute unit over lists of
+  // tiles: workgroup w takes slots wg_start[w] .. wg_start[w + 1] - 1, slot s
+  // being tile order[s].
+  std::vector<int32_t> order;
+  std::vector<int32_t> wg_start;
   // staged operator data (FP64; converted at upload)
   std::vector<double> dense;      // dense pool
   // A-side blocks of the pool, stored k-major (element (m, k) at off + k * rows + m);

@@ -491,6 +491,7 @@ __global__ __launch_bounds__(kLzThreads) void lz_axpy_local(const double* __rest
                                                             const double* __restrict__ h,
                                                             const double* __restrict__ scale,
                                                             bool pending, double* __restrict__ out,
+                                                            float* __restrict__ out32,
                                                             double* __restrict__ partial) {
   const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
   const bool ok = e < n;
@@ -505,6 +506,7 @@ __global__ __launch_bounds__(kLzThreads) void lz_axpy_local(const double* __rest
   if (ok) {
     if (pending) V[(int64_t)j * ldv + e] = vj;
     if (out) out[e] = x;
+    if (out32) out32[e] = (float)x;
   }
   __shared__ double sh[kLzThreads / 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -538,7 +540,8 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot_uw(const double* __restrict
 __global__ __launch_bounds__(kLzThreads) void lz_local_update(
     const double* __restrict__ w, double* __restrict__ V, int64_t ldv, int j, int64_t n,
     const double* __restrict__ dpart, const double* __restrict__ npend, int np,
-    double* __restrict__ out, double* __restrict__ nout, double* __restrict__ ab) {
+    double* __restrict__ out, float* __restrict__ out32, double* __restrict__ nout,
+    double* __restrict__ ab) {
   __shared__ double sums[2];
   __shared__ double sh[kLzThreads / 64];
   const int64_t e = (int64_t)blockIdx.x * kLzThreads + threadIdx.x;
@@ -562,6 +565,7 @@ __global__ __launch_bounds__(kLzThreads) void lz_local_update(
   if (ok) {
     V[(int64_t)j * ldv + e] = vj;
     if (out) out[e] = x;
+    if (out32) out32[e] = (float)x;
   }
   const double q = wave_sum(x * x);
   if (lane == 0) sh[wave] = q;
@@ -590,7 +594,8 @@ __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
                                                       const double* __restrict__ partial, int np,
                                                       const double* __restrict__ h1,
                                                       const double* __restrict__ h2, int j,
-                                                      double* __restrict__ ab, int64_t n) {
+                                                      double* __restrict__ ab, int64_t n,
+                                                      float* __restrict__ v32) {
   __shared__ double beta;
   // this thread's element of w is loaded before the norm is summed, so the
   // two memory latencies overlap
@@ -608,7 +613,10 @@ __global__ __launch_bounds__(kThreads) void lz_finish(double* __restrict__ v,
   }
   if (!v) return;
   const double inv = b > 0.0 ? 1.0 / b : 0.0;
-  if (i < n) v[i] = wi * inv;
+  if (i < n) {
+    v[i] = wi * inv;
+    if (v32) v32[i] = (float)(wi * inv);
+  }
 }
 
 // w -= sum_{i<nv} h[i] V_i, then partial[i * gridDim.x + blockIdx.x] = the
@@ -654,7 +662,7 @@ void launch_axpy_dot(double* w, const double* V, int64_t ldv, int nv, int64_t n,
 
 hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64_t n,
                           double* h1, double* h2, double* partial, double* ab, double* vnext,
-                          hipStream_t stream) {
+                          hipStream_t stream, float* vnext32) {
   if (nv < 1) return hipErrorInvalidValue;
   const int nb = lz_blocks(n);
   hipLaunchKernelGGL(lz_dot, dim3(nb), dim3(kLzThreads), 0, stream, V, ldv, nv, w, n, partial);
@@ -679,14 +687,14 @@ hipError_t launch_lz_step(double* w, const double* V, int64_t ldv, int nv, int64
                      partial);
   const unsigned nfin = vnext ? (unsigned)((n + kThreads - 1) / kThreads) : 1u;
   hipLaunchKernelGGL(lz_finish, dim3(nfin), dim3(kThreads), 0, stream, vnext, w, partial, nb, h1, h2,
-                     nv - 1, ab, n);
+                     nv - 1, ab, n, vnext ? vnext32 : nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_lz_step_onepass(double* w, double* V, int64_t ldv, int nv, int64_t n, double* h,
                                   double* partial, const double* npend, const double* beta_prev,
                                   double* nout, double* scale, double* ab, double* out,
-                                  hipStream_t stream) {
+                                  hipStream_t stream, float* out32) {
   if (nv < 2 || !nout || !scale || (!npend && !beta_prev)) return hipErrorInvalidValue;
   const int nb = lz_blocks(n);
   const int nbk = (int)std::max<int64_t>(1, (n + kLzThreads * kDotkE - 1) / (kLzThreads * kDotkE));
@@ -696,20 +704,20 @@ hipError_t launch_lz_step_onepass(double* w, double* V, int64_t ldv, int nv, int
   hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(320), 0, stream, partial, nbk, nv, beta_prev, h,
                      npend, nb, scale, ab - 1, ab);
   hipLaunchKernelGGL(lz_axpy_local, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, nv, n, h, scale,
-                     npend != nullptr, out, nout);
+                     npend != nullptr, out, out ? out32 : nullptr, nout);
   return hipGetLastError();
 }
 
 hipError_t launch_lz_step_recurrence(const double* w, double* V, int64_t ldv, int nv, int64_t n,
                                      double* partial, const double* npend, double* nout,
-                                     double* ab, double* out, hipStream_t stream) {
+                                     double* ab, double* out, hipStream_t stream, float* out32) {
   if (nv < 2 || !npend || !nout) return hipErrorInvalidValue;
   const int nb = lz_blocks(n);
   const int j = nv - 1;
   hipLaunchKernelGGL(lz_dot_uw, dim3(nb), dim3(kLzThreads), 0, stream, V + (int64_t)j * ldv, w, n,
                      partial);
   hipLaunchKernelGGL(lz_local_update, dim3(nb), dim3(kLzThreads), 0, stream, w, V, ldv, j, n,
-                     partial, npend, nb, out, nout, ab);
+                     partial, npend, nb, out, out ? out32 : nullptr, nout, ab);
   return hipGetLastError();
 }
 
