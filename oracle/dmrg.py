@@ -54,6 +54,9 @@ class Block:
     q: np.ndarray          # effective quantum number per state, non-decreasing
     H: dict                # {coupling group: dense block Hamiltonian piece}
     ops: dict = field(default_factory=dict)   # {(label, name): dense operator}
+    # kept eigenvectors (grown block's sorted basis x this block's states) when
+    # the block was made by truncating a grown block; None for a bare site
+    W: np.ndarray = None
 
     @property
     def n(self):
@@ -214,11 +217,8 @@ def describe(Sp, Ep, terms, q_target):
                        for (c, A, B, g) in terms])
 
 
-def solve(Sp, Ep, terms, q_target, init, tol, max_iter):
-    """Lowest state of the superblock in the target sector (Fig. 2(d))."""
-    sb = dict(S=sectors(Sp.q), E=sectors(Ep.q), q_target=int(q_target))
-    D = len(target_indices(sb))
-
+def superblock_matvec(sb, terms):
+    """psi -> H psi on the target sector, H = sum of c A (x) B (Sec. 3.3)."""
     def matvec(psi):
         P = unpack(sb, psi)
         Y = np.zeros_like(P)
@@ -227,8 +227,17 @@ def solve(Sp, Ep, terms, q_target, init, tol, max_iter):
             T = T if B is None else T @ B.T
             Y += c * T
         return pack(sb, Y)
+    return matvec
 
-    E0, psi, it, res = lanczos_ground(matvec, init(D), max_iter=max_iter, tol=tol)
+
+def solve(Sp, Ep, terms, q_target, init, tol, max_iter):
+    """Lowest state of the superblock in the target sector (Fig. 2(d)).
+
+    ``init(D)`` gives the Lanczos start vector."""
+    sb = dict(S=sectors(Sp.q), E=sectors(Ep.q), q_target=int(q_target))
+    D = len(target_indices(sb))
+    E0, psi, it, res = lanczos_ground(superblock_matvec(sb, terms), init(D),
+                                      max_iter=max_iter, tol=tol)
     return sb, E0, psi, it, res
 
 
@@ -247,8 +256,71 @@ def change_basis(block, sb, psi, side, m, no_split):
     W = np.hstack(cols)
     new = Block(sites=list(block.sites), q=np.array(qs, dtype=np.int64),
                 H={g: W.T @ h @ W for g, h in block.H.items()},
-                ops={k: W.T @ O @ W for k, O in block.ops.items()})
+                ops={k: W.T @ O @ W for k, O in block.ops.items()}, W=W)
     return new, tr
+
+
+# ---------------------------------------------------------------------------
+# Wave-function transformation (the paper's conclusions name it, after White,
+# as what makes a good Lanczos start vector in the finite phase).  The paper
+# gives no formula; the reading used is the plain change of basis of the
+# state, written out on dense matrices:
+#
+#   split p -> p+1 (S' was truncated at p):  Psi(p) is a matrix over
+#   S'(p) x E'(p), E'(p) = site(p+1) (x) R with R = R_{L-p-1}, itself the
+#   truncation W_R of E'(p+1) = site(p+2) (x) R_{L-p-2}.  Then
+#       Psi(p+1)[(a, s), e'] = sum_{alpha, r} W_L[alpha, a] Psi(p)[alpha, (s, r)] W_R[e', r]
+#   with a a state of the truncated S(p), s the state of site p+1, and
+#   (a, s) placed in the sorted basis of S'(p+1) = S(p) (x) site(p+1).
+#   split p -> p-1 is the mirror image, with the roles of the blocks swapped.
+#
+# Untruncated, both maps are exact changes of basis of the same L-site
+# state: the carried vector is then the next step's ground state itself.
+# ---------------------------------------------------------------------------
+
+
+def product_order(q_major, q_minor):
+    """Sort permutation of the product basis (major index outer), the same
+    stable ordering by effective q that grow_right / grow_left apply (Sec. 3.2):
+    sorted state k is product state perm[k]."""
+    q = (np.asarray(q_major)[:, None] + np.asarray(q_minor)[None, :]).reshape(-1)
+    return np.argsort(q, kind="stable")
+
+
+def carry_left_to_right(sb_old, psi, W_L, S_new, R_old, site_q, sb_new):
+    """Start vector at split p+1 from the ground state psi at split p.
+
+    W_L: kept vectors of S'(p) (the truncation just made), S_new = S(p);
+    R_old = R_{L-p-1} with R_old.W its kept vectors in the sorted basis of
+    E'(p+1) = site (x) R_{L-p-2}; site_q: one site's sorted q."""
+    Psi = unpack(sb_old, psi)                          # S'(p) x E'(p), sorted
+    d, nR = len(site_q), R_old.n
+    permE = product_order(site_q, R_old.q)             # E'(p) = site (x) R_old
+    U = np.zeros_like(Psi)
+    U[:, permE] = Psi                                  # columns in product order (s, r)
+    U = U.reshape(Psi.shape[0], d, nR)
+    T = np.einsum("xa,xsr,er->ase", W_L, U, R_old.W)   # (a, s, e') ; e' in E'(p+1)
+    T = T.reshape(S_new.n * d, R_old.W.shape[0])       # rows in product order (a, s)
+    permS = product_order(S_new.q, site_q)             # S'(p+1) = S(p) (x) site
+    return pack(sb_new, T[permS, :])
+
+
+def carry_right_to_left(sb_old, psi, W_E, E_new, L_old, site_q, sb_new):
+    """Start vector at split p-1 from the ground state psi at split p.
+
+    W_E: kept vectors of E'(p) (the truncation just made), E_new = E(p);
+    L_old = S_{p-1} with L_old.W its kept vectors in the sorted basis of
+    S'(p-1) = S_{p-2} (x) site; site_q: one site's sorted q."""
+    Psi = unpack(sb_old, psi)                          # S'(p) x E'(p), sorted
+    d, nL = len(site_q), L_old.n
+    permS = product_order(L_old.q, site_q)             # S'(p) = L_old (x) site
+    U = np.zeros_like(Psi)
+    U[permS, :] = Psi                                  # rows in product order (l, s)
+    U = U.reshape(nL, d, Psi.shape[1])
+    T = np.einsum("al,lsy,ye->ase", L_old.W, U, W_E)   # (a', s, e) ; a' in S'(p-1)
+    T = T.reshape(L_old.W.shape[0], d * E_new.n)       # columns in product order (s, e)
+    permE = product_order(site_q, E_new.q)             # E'(p-1) = site (x) E(p)
+    return pack(sb_new, T[:, permE])
 
 
 def _q_target(model, n, Q):
@@ -257,11 +329,16 @@ def _q_target(model, n, Q):
 
 
 def run(model, L, m, sweeps, init, tol=1e-10, max_iter=300, no_split=True,
-        keep_range=None, on_superblock=None):
+        keep_range=None, on_superblock=None, wavefunction=False):
     """Infinite phase to L sites, then ``sweeps`` finite sweeps.
 
     ``init(D, step)`` supplies the Lanczos initial vector of each step (an
-    input, so that both sides of a comparison can use the same one).
+    input, so that both sides of a comparison can use the same one).  In the
+    finite phase the previous ground state is also carried to the new basis
+    (carry_left_to_right / carry_right_to_left; unchanged when the split
+    stays put); its record gets ``carry_overlap`` = |<carried|psi>| / |carried|
+    against the new ground state and ``carry_energy`` = its Rayleigh quotient.
+    With ``wavefunction`` set, the carried vector is the Lanczos start.
     Returns a list of per-step records (dicts).
     """
     Q = L + 1
@@ -271,6 +348,22 @@ def run(model, L, m, sweeps, init, tol=1e-10, max_iter=300, no_split=True,
     step = 0
     left = {1: site_block(model, 0, Q)}
     right = {1: site_block(model, 0, Q)}
+    site_q = left[1].q
+    prev = {}
+
+    def carried(p, sb_new):
+        """The previous ground state in the basis of the superblock at split p."""
+        if not prev or prev["n"] != L:
+            return None
+        if prev["p"] == p:
+            return prev["psi"]
+        if prev["p"] + 1 == p and 0 in prev["out"]:
+            return carry_left_to_right(prev["sb"], prev["psi"], prev["out"][0].W,
+                                       prev["out"][0], right[L - p], site_q, sb_new)
+        if prev["p"] - 1 == p and 1 in prev["out"]:
+            return carry_right_to_left(prev["sb"], prev["psi"], prev["out"][1].W,
+                                       prev["out"][1], left[p], site_q, sb_new)
+        return None
 
     def one(Sp, Ep, n, truncate_sides, phase, p):
         nonlocal step
@@ -279,9 +372,17 @@ def run(model, L, m, sweeps, init, tol=1e-10, max_iter=300, no_split=True,
         qt = _q_target(model, n, Q)
         if on_superblock is not None:
             on_superblock(phase, n, p, describe(Sp, Ep, terms, qt))
-        sb, E0, psi, it, res = solve(Sp, Ep, terms, qt, lambda D: init(D, step), tol, max_iter)
+        sb0 = dict(S=sectors(Sp.q), E=sectors(Ep.q), q_target=int(qt))
+        c = carried(p, sb0) if phase == "finite" else None
+        start = (lambda D: c) if (wavefunction and c is not None
+                                  and np.linalg.norm(c) > 0.0) else (lambda D: init(D, step))
+        sb, E0, psi, it, res = solve(Sp, Ep, terms, qt, start, tol, max_iter)
         rec = dict(phase=phase, n=n, p=p, energy=E0, iters=it, resid=res,
                    dimS=Sp.n, dimE=Ep.n, D=len(psi), step=step)
+        if c is not None and np.linalg.norm(c) > 0.0:
+            nc = float(np.linalg.norm(c))
+            rec["carry_overlap"] = abs(float(np.dot(c, psi))) / nc
+            rec["carry_energy"] = float(np.dot(c, superblock_matvec(sb, terms)(c))) / nc ** 2
         out = {}
         for side in truncate_sides:
             blk = Sp if side == 0 else Ep
@@ -291,6 +392,8 @@ def run(model, L, m, sweeps, init, tol=1e-10, max_iter=300, no_split=True,
             out[side] = new
         log.append(rec)
         step += 1
+        prev.clear()
+        prev.update(n=n, p=p, sb=sb, psi=psi, out=out)
         return out
 
     # infinite phase (Fig. 2): superblocks of n = 4, 6, ..., L sites

@@ -53,8 +53,3 @@ def lanczos_ground(matvec, v0, max_iter=300, tol=1e-10):
     psi /= np.linalg.norm(psi)
     r = matvec(psi) - theta * psi
     return theta, psi, it, float(np.linalg.norm(r))
-
-
-def rayleigh(matvec, psi):
-    """<psi|H|psi> / <psi|psi>."""
-    return float(np.dot(psi, matvec(psi)) / np.dot(psi, psi))

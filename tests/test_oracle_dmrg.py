@@ -72,3 +72,42 @@ def test_superblock_description_matches_dense_product():
     _, D = OS.target_pairs(sb)
     x = init_vector(D, 0)
     assert np.allclose(OS.hpsi_blocks(sb, x), OS.hpsi_dense(sb, x), atol=1e-12)
+
+
+@pytest.mark.parametrize("name,model,L,m", [
+    ("heisenberg", M.heisenberg_model(M.chain_bonds), 8, 256),
+    ("j1j2", M.heisenberg_model(lambda n: M.j1j2_bonds(n, 1.0, 0.3)), 8, 256),
+    ("hubbard_u4", M.hubbard_model(4.0), 6, 4096),
+])
+def test_carried_state_is_next_ground_state_when_untruncated(name, model, L, m):
+    """Untruncated, the wave-function transformation is an exact change of
+    basis of the same L-site state (the paper's conclusions, after White):
+    the carried vector is the next step's ground state, in both sweep
+    directions and at the turns."""
+    log = OD.run(model, L, m, 1, _init, tol=1e-12)
+    fin = [r for r in log if r["phase"] == "finite"]
+    assert all(r.get("eps0", 0.0) == 0.0 and r.get("eps1", 0.0) == 0.0 for r in log)
+    moved = [r for r in fin if "carry_overlap" in r]
+    assert len(moved) == len(fin)
+    for r in moved:
+        assert r["carry_overlap"] >= 1 - 1e-10, (name, r["p"], r["carry_overlap"])
+        assert abs(r["carry_energy"] - r["energy"]) <= 1e-9 * abs(r["energy"])
+
+
+def test_carried_state_truncated_is_variational_and_close():
+    """Truncated, the carried vector lies in the next superblock's space, so
+    its energy is at least the next ground-state energy (variational), and
+    it stays close to that ground state; starting Lanczos from it saves
+    iterations against a random start."""
+    model = M.heisenberg_model(M.chain_bonds)
+    cold = OD.run(model, 16, 16, 1, _init)
+    warm = OD.run(model, 16, 16, 1, _init, wavefunction=True)
+    fin = [r for r in warm if r["phase"] == "finite"]
+    assert all("carry_overlap" in r for r in fin)
+    for r in fin:
+        assert r["carry_energy"] >= r["energy"] - 1e-9 * abs(r["energy"])
+        assert r["carry_overlap"] > 0.99, (r["p"], r["carry_overlap"])
+    assert abs(warm[-1]["energy"] - cold[-1]["energy"]) < 1e-8
+    it_cold = sum(r["iters"] for r in cold if r["phase"] == "finite")
+    it_warm = sum(r["iters"] for r in fin)
+    assert it_warm < 0.7 * it_cold, (it_warm, it_cold)

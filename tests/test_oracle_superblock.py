@@ -237,3 +237,59 @@ def test_basis_change_block_identities():
         for j in range(3):
             assert abs(T[i, j] - sum(Wr[a, i] * B[a, b] * Wc[b, j]
                                      for a in range(n) for b in range(n))) < 1e-12
+
+
+def _term_matrices(sb):
+    """Each term's explicit Kronecker matrix (target rows and columns), built
+    from the dense operators term by term."""
+    idx = OS.target_indices(sb)
+    out = []
+    for t in sb["terms"]:
+        A = OS.full_operator(t["A"], sb["S"])
+        B = OS.full_operator(t["B"], sb["E"])
+        out.append((t["c"], np.kron(A, B)[np.ix_(idx, idx)]))
+    return out
+
+
+def test_element_matches_blocks_at_every_entry(small_sb):
+    """hpsi_element (the single-entry form used for sampled checks at full
+    size) equals hpsi_blocks entry by entry, and its absolute form equals
+    sum_k |c_k| (|A_k| (x) |B_k|) |psi| from the explicit Kronecker matrices."""
+    pairs, D = OS.target_pairs(small_sb)
+    psi = seeded_vector(D, 7)
+    y = OS.hpsi_blocks(small_sb, psi)
+    yabs = sum(abs(c) * (np.abs(K) @ np.abs(psi)) for c, K in _term_matrices(small_sb))
+    dS, dE = small_sb["S"]["dim"], small_sb["E"]["dim"]
+    scale = np.max(np.abs(yabs))
+    for (i, j, off) in pairs:
+        a, b = int(dS[i]), int(dE[j])
+        for m in range(a):
+            for n in range(b):
+                e = off + m * b + n
+                assert abs(OS.hpsi_element(small_sb, psi, i, j, m, n) - y[e]) <= 1e-13 * scale
+                got = OS.hpsi_element(small_sb, np.abs(psi), i, j, m, n, absolute=True)
+                assert abs(got - yabs[e]) <= 1e-13 * scale
+
+
+def test_abs_description_bounds_the_product(small_sb):
+    """hpsi_blocks(abs_description(sb), |psi|) -- the tolerance scale of the
+    GPU parity tests -- is sum_k |c_k| (|A_k| (x) |B_k|) |psi| from the
+    explicit Kronecker matrices, and bounds |H psi| entry by entry (triangle
+    inequality); every block of the description is the elementwise absolute
+    value of the original's."""
+    _, D = OS.target_pairs(small_sb)
+    psi = seeded_vector(D, 8)
+    ab = OS.abs_description(small_sb)
+    for t, ta in zip(small_sb["terms"], ab["terms"]):
+        assert ta["c"] == abs(t["c"])
+        for side in ("A", "B"):
+            if t[side] is None:
+                assert ta[side] is None
+                continue
+            assert ta[side]["delta"] == t[side]["delta"]
+            for (r, c, blk), (r2, c2, blk2) in zip(t[side]["blocks"], ta[side]["blocks"]):
+                assert (r, c) == (r2, c2) and np.array_equal(blk2, np.abs(blk))
+    s = OS.hpsi_blocks(ab, np.abs(psi))
+    want = sum(abs(c) * (np.abs(K) @ np.abs(psi)) for c, K in _term_matrices(small_sb))
+    assert np.max(np.abs(s - want)) <= 1e-13 * np.max(want)
+    assert np.all(np.abs(OS.hpsi_blocks(small_sb, psi)) <= s * (1 + 1e-12) + 1e-300)
