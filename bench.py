@@ -16,7 +16,9 @@ value = algorithmic H*psi flops executed in the timed steps / wall time
 (TFLOP/s).  roofline = the FP32 product kernel alone: algorithmic flops per
 launch / mean launch time from HIP events around every launch in the timed
 region.  The oracle's per-block numpy product on the host cores is reported
-beside it (cpu_baseline).
+beside it (cpu_baseline), with the oracle's own Lanczos ground state of the
+same superblock, against which the GPU solves' energy and wave-function
+errors are given (cpu_baseline.accuracy_vs_oracle).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -197,6 +199,25 @@ def cpu_baseline(desc, flops, seconds):
     return out
 
 
+def oracle_accuracy(desc, psi0, L, solves):
+    """Part of the CPU-baseline leg: the oracle's FP64 Lanczos (full
+    reorthogonalisation) on the same superblock from the same start vector,
+    and each GPU solve's |dE|/L and 1 - |<psi_gpu|psi_oracle>| against it."""
+    import numpy as np
+    from oracle import lanczos as OL
+    from oracle import superblock as OS
+    t0 = time.perf_counter()
+    E, psi, it, res = OL.lanczos_ground(lambda v: OS.hpsi_blocks(desc, v), psi0,
+                                        max_iter=600, tol=1e-10)
+    out = {"E0_oracle": E, "oracle_iterations": it, "oracle_residual": res,
+           "oracle_seconds": round(time.perf_counter() - t0, 2)}
+    for name, (e, v) in solves.items():
+        v = np.asarray(v) / np.linalg.norm(v)
+        out[name] = {"abs_dE_per_site": abs(e - E) / L,
+                     "one_minus_overlap": 1.0 - abs(float(np.dot(v, psi)))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +347,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(desc, F, args.cpu_seconds)
+        out["cpu_baseline"]["accuracy_vs_oracle"] = oracle_accuracy(
+            desc, psi0.cpu().numpy(), L, {"gpu_fp32_refined": (E32, psi32),
+                                          "gpu_fp64": (r64["energy"], psi64)})
+        log(f"[bench] vs oracle Lanczos: {out['cpu_baseline']['accuracy_vs_oracle']}")
     print(json.dumps(out), flush=True)
 
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <atomic>
 #include <cmath>
 #include <condition_variable>
@@ -168,6 +169,8 @@ struct Staged {
   DevBuf images;            // one tile image per workgroup slot of the fused kernel
   DevBuf psi32;             // FP32 copy of the input vector (products that read one)
   DevBuf wg_start;          // persistent launch: each workgroup's slots
+  DevBuf coef_img, coef_seg;   // where each coefficient sits in images / segs
+  int64_t ncoef_img = 0, ncoef_seg = 0;
   int32_t nwg = 0;
   int32_t img_stride = 0;   // words per image
   int32_t nslots = 0;
@@ -260,13 +263,17 @@ dmrg_status upload(DevBuf& b, const void* src, size_t bytes, hipStream_t s) {
 // Tile images of a staged plan (again after a coefficient change).
 dmrg_status stage_images(Staged& st, hipStream_t s) {
   std::vector<uint32_t> img;
+  std::vector<CoefRef> coefs;
   std::string err;
   if (!build_images(st.plan.tiles, st.plan.segs, st.plan.order, st.plan.gsrc, st.plan.gscale, img,
-                    st.img_stride, err))
+                    st.img_stride, err, &coefs))
     return fail(DMRG_E_UNSUPPORTED, err);
   st.nslots = (int32_t)st.plan.order.size();
   dmrg_status r = upload(st.images, img.data(), img.size() * sizeof(uint32_t), s);
   if (r != DMRG_OK) return r;
+  st.ncoef_img = (int64_t)coefs.size();
+  if (!coefs.empty() && (r = upload(st.coef_img, coefs.data(), coefs.size() * sizeof(CoefRef), s)) != DMRG_OK)
+    return r;
   st.nwg = (int32_t)st.plan.wg_start.size() - 1;
   if (st.nwg > 0 &&
       (r = upload(st.wg_start, st.plan.wg_start.data(), st.plan.wg_start.size() * sizeof(int32_t), s)) !=
@@ -283,6 +290,15 @@ dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
   if ((r = stage_images(st, s)) != DMRG_OK) return r;
   if ((r = upload(st.tiles, p.tiles.data(), p.tiles.size() * sizeof(TileDesc), s)) != DMRG_OK) return r;
   if ((r = upload(st.segs, p.segs.data(), p.segs.size() * sizeof(SegDesc), s)) != DMRG_OK) return r;
+  {
+    std::vector<CoefRef> refs(p.segs.size());
+    for (size_t i = 0; i < p.segs.size(); ++i)
+      refs[i] = {(int64_t)(i * sizeof(SegDesc) + offsetof(SegDesc, c)), p.segs[i].term, 0};
+    st.ncoef_seg = (int64_t)refs.size();
+    if (!refs.empty() && (r = upload(st.coef_seg, refs.data(), refs.size() * sizeof(CoefRef), s)) != DMRG_OK)
+      return r;
+    HIP_TRY(hipStreamSynchronize(s));   // the host table dies here
+  }
   if ((r = upload(st.gsrc, p.gsrc.data(), p.gsrc.size() * sizeof(int32_t), s)) != DMRG_OK) return r;
   if ((r = upload(st.gscale, p.gscale.data(), p.gscale.size() * sizeof(double), s)) != DMRG_OK) return r;
   if ((r = upload(st.dense64, p.dense.data(), p.dense.size() * sizeof(double), s)) != DMRG_OK) return r;
@@ -627,16 +643,19 @@ dmrg_status dmrg_sb_set_coeffs(dmrg_sb sb, const double* c_h) {
   if (!sb || !c_h) return fail(DMRG_E_ARG, "null argument");
   for (size_t k = 0; k < sb->coeff.size(); ++k) sb->coeff[k] = c_h[k];
   Staged* plans[2] = {&sb->fwd, sb->adj.get()};
+  const int32_t nt = (int32_t)sb->coeff.size();
   for (Staged* st : plans) {
     if (!st) continue;
+    // host copies (images rebuilt later, the plain path's launch arguments)
     for (auto& s : st->plan.segs) s.c = c_h[s.term];
     for (auto& w : st->plain) w.first.c = c_h[w.first.term];
+    // device copies: written in place, in stream order, by a small kernel
     if (sb->ctx) {
       DeviceGuard g(sb->ctx->device);
-      HIP_TRY(hipMemcpyAsync(st->segs.p, st->plan.segs.data(), st->plan.segs.size() * sizeof(SegDesc),
-                             hipMemcpyHostToDevice, sb->ctx->stream));
-      dmrg_status r = stage_images(*st, sb->ctx->stream);
-      if (r != DMRG_OK) return r;
+      HIP_TRY(launch_patch_coeffs(st->images.p, st->coef_img.as<CoefRef>(), st->ncoef_img,
+                                  sb->coeff.data(), nt, sb->ctx->stream));
+      HIP_TRY(launch_patch_coeffs(st->segs.p, st->coef_seg.as<CoefRef>(), st->ncoef_seg,
+                                  sb->coeff.data(), nt, sb->ctx->stream));
     }
   }
   return DMRG_OK;

@@ -970,6 +970,35 @@ void launch_tiles(int nslots, const uint32_t* images, int32_t stride, const void
                         (const typename Cfg::psi_t*)psi, y, alpha, beta, ndense, npsi, wg_start);
 }
 
+struct CoefBatch {
+  double v[kCoefBatch];
+  int32_t t0;
+};
+
+__global__ __launch_bounds__(256) void patch_coeffs(char* __restrict__ base,
+                                                    const CoefRef* __restrict__ refs, int64_t n,
+                                                    CoefBatch c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const CoefRef r = refs[i];
+  const int32_t t = r.term - c.t0;
+  if (t >= 0 && t < kCoefBatch) *reinterpret_cast<double*>(base + r.off) = c.v[t];
+}
+
+hipError_t launch_patch_coeffs(void* base, const CoefRef* refs, int64_t n, const double* c,
+                               int32_t nterms, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (!base || !refs || !c || nterms < 0) return hipErrorInvalidValue;
+  for (int32_t t0 = 0; t0 < nterms; t0 += kCoefBatch) {
+    CoefBatch b{};
+    b.t0 = t0;
+    for (int32_t k = 0; k < kCoefBatch && t0 + k < nterms; ++k) b.v[k] = c[t0 + k];
+    hipLaunchKernelGGL(patch_coeffs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       static_cast<char*>(base), refs, n, b);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream) {
   if (n < 0) return hipErrorInvalidValue;
   const int64_t m = n + kPoolPad;

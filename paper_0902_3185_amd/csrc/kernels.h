@@ -35,6 +35,14 @@ hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images
 // out[0 .. n) = (float) psi, out[n .. n + kPoolPad) = 0
 hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream);
 
+// Writes c[refs[i].term] to the double at base + refs[i].off for i < n (the
+// coefficient fields of staged tile images or segment tables), in stream
+// order: products enqueued later see the new coefficients.  The coefficients
+// travel as kernel arguments, kCoefBatch terms per launch.
+constexpr int kCoefBatch = 240;
+hipError_t launch_patch_coeffs(void* base, const CoefRef* refs, int64_t n, const double* c,
+                               int32_t nterms, hipStream_t stream);
+
 // The fixed device scratch of dmrg_hpsi_noalloc (noalloc.hip): kScratchFloats
 // floats per device.  scratch_setup(device) looks up the device's copy once
 // (hipGetSymbolAddress with that device current); scratch_ptr(device) returns

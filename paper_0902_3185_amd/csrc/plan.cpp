@@ -3,6 +3,7 @@
 #include "plan.h"
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -403,7 +404,7 @@ dmrg_status build_plan_between(const dmrg_basis* S, const dmrg_basis* E, int64_t
 bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>& segs,
                   const std::vector<int32_t>& order, const std::vector<int32_t>& gsrc,
                   const std::vector<double>& gscale, std::vector<uint32_t>& out,
-                  int32_t& stride, std::string& err) {
+                  int32_t& stride, std::string& err, std::vector<CoefRef>* coefs) {
   const size_t nslots = order.empty() ? tiles.size() : order.size();
   auto tile_of = [&](size_t slot) { return order.empty() ? (int32_t)slot : order[slot]; };
   // gather entry of output index idx (< limit) through pool offset g (-1: identity)
@@ -463,6 +464,11 @@ bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>
   }
   stride = (words + 3) / 4 * 4;
   out.assign(nslots * (size_t)stride, 0u);
+  if (coefs) coefs->clear();
+  auto note = [&](const uint32_t* rec, size_t field, int32_t term) {
+    if (coefs)
+      coefs->push_back({(int64_t)((rec - out.data()) * sizeof(uint32_t) + field), term, 0});
+  };
   for (size_t slot = 0; slot < nslots; ++slot) {
     const int32_t ti = tile_of(slot);
     uint32_t* img = out.data() + slot * (size_t)stride;
@@ -499,12 +505,14 @@ bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>
             w.pad = win.first;
             w.ch0 = nch;
             nch += c;
+            note(img + kHdrWords + nrec * kSegWords, offsetof(ImgSeg, c), sg.term);
             std::memcpy(img + kHdrWords + nrec++ * kSegWords, &w, sizeof(w));
           }
         } else {
           for (int32_t i = 0; i < kTile; ++i) gather(sg.gA, t.m0 + i, t.a, r.src[i], r.scl[i]);
           r.ch0 = nch;
           nch += c;
+          note(img + kHdrWords + nrec * kSegWords, offsetof(ImgSeg, c), sg.term);
           std::memcpy(img + kHdrWords + nrec++ * kSegWords, &r, sizeof(r));
         }
       }
@@ -524,6 +532,7 @@ bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>
           r.col[i] = src;
           r.cs[i] = scl;
         }
+        note(img + kHdrWords + nrec * kSegWords + q * kGGWords, offsetof(ImgGG, c), sg.term);
         std::memcpy(img + kHdrWords + nrec * kSegWords + q * kGGWords, &r, sizeof(r));
       }
     }

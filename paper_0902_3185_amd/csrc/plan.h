@@ -94,13 +94,23 @@ constexpr int kImgWords = 6144;   // LDS room for one image (24 KiB)
 static_assert(sizeof(ImgHeader) == 64 && sizeof(ImgSeg) % 8 == 0 && sizeof(ImgGG) % 8 == 0,
               "image records must keep 8-byte alignment");
 
+// Where a term coefficient sits in a device buffer (byte offset of a double),
+// so that new coefficients can be written in place by a kernel.
+struct CoefRef {
+  int64_t off;
+  int32_t term;
+  int32_t pad;
+};
+
 // Images of the given tiles in launch order (order[slot] = tile, -1 idle; an
 // empty order means slot = tile).  stride (words, a multiple of 4) is the
 // largest image.  Returns false with err set if an image exceeds kImgWords.
+// coefs, if given, receives the byte offset and term of every coefficient
+// field in out.
 bool build_images(const std::vector<TileDesc>& tiles, const std::vector<SegDesc>& segs,
                   const std::vector<int32_t>& order, const std::vector<int32_t>& gsrc,
                   const std::vector<double>& gscale, std::vector<uint32_t>& out,
-                  int32_t& stride, std::string& err);
+                  int32_t& stride, std::string& err, std::vector<CoefRef>* coefs = nullptr);
 
 struct Plan {
   // bases

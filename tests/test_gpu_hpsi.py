@@ -145,6 +145,38 @@ def test_set_coeffs_is_linear(ctx):
     assert np.linalg.norm(y - ref) <= 1e-14 * _scale(desc, psi) * 2
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp64_plain"])
+def test_set_coeffs_between_products(ctx, prec):
+    """New coefficients apply to the products enqueued after them and not to
+    the ones before, with no synchronisation in between; the adjoint too."""
+    import torch
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("hubbard_L64_U4_m512", m=96, seed=4)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    psi = _dev(seeded_vector(sb.D, 42))
+    g = _dev(seeded_vector(sb.D, 43))
+    c1 = np.array([t["c"] for t in desc["terms"]])
+    c2 = c1 * np.linspace(-1.5, 2.0, len(c1))
+    outs = []
+    for c in (c1, c2, c1, c2):
+        sb.set_coeffs(c)
+        outs.append(torch.clone(sb.hpsi(psi)))
+    gp2, gc2 = sb.adjoint(psi, g)
+    torch.cuda.synchronize()
+    p = psi.cpu().numpy()
+    for c, y in zip((c1, c2, c1, c2), outs):
+        d = dict(desc, terms=[dict(t, c=float(ck)) for t, ck in zip(desc["terms"], c)])
+        ref = OS.hpsi_blocks(d, p)
+        _, bound = FB.product_bound(d, p, prec)
+        assert np.all(np.abs(y.cpu().numpy() - ref) <= bound)
+    if prec in ("fp64", "fp32"):
+        d2 = dict(desc, terms=[dict(t, c=float(ck)) for t, ck in zip(desc["terms"], c2)])
+        gp_ref, gc_ref = OS.hpsi_adjoint_blocks(d2, p, g.cpu().numpy())
+        _, gp_bound, gc_bound = FB.adjoint_bound(d2, p, g.cpu().numpy(), prec)
+        assert np.all(np.abs(_host(gp2) - gp_ref) <= gp_bound)
+        assert np.all(np.abs(np.asarray(gc2) - gc_ref) <= gc_bound)
+
+
 def test_argument_errors(ctx):
     from paper_0902_3185_amd import _lib
     from paper_0902_3185_amd.superblock import Superblock
