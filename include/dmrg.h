@@ -216,17 +216,25 @@ dmrg_status dmrg_sb_set_coeffs(dmrg_sb sb, const double* c_h);
  * or if this call stages them).                                            */
 dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec);
 
-/* Tile-shape autotuner: times every variant of the fused product kernel for
- * the current precision on this superblock (reps launches each, on zeroed
- * device vectors the call allocates and frees) and keeps the fastest for
- * later products.  The variants differ only in how row-walking operands are
- * read (per lane, or whole rows per group of lanes through LDS): results are
- * identical.  *variant (may be NULL) receives the choice; FP64 and the plain
- * baseline have one variant (0).  Synchronous.                              */
+/* Tile-shape autotuner for the FP32 and BF16 products: times every variant
+ * of the product on this superblock (reps launches each, on zeroed device
+ * vectors the call allocates and frees) and keeps the fastest for later
+ * products.  Variant 0: 32 x 32 output tiles, the sixteen waves of a
+ * workgroup splitting a tile's contraction, one tile list per compute unit.
+ * Variant 1: 64 x 64 output tiles whose two operand panels are staged once
+ * in LDS for four waves; all tiles' contraction stages dealt out in equal
+ * shares to the workgroups (a tile may be cut between workgroups, whose
+ * partial sums a second kernel adds in a fixed order).  Variants 2 and 3:
+ * as 0 with eight or four waves per tile and one workgroup per tile, several
+ * resident per compute unit.  All are deterministic and within the same
+ * rounding bound; their results differ in the last bits (different
+ * summation orders).  *variant (may be NULL) receives the choice; FP64 and
+ * the plain baseline have one variant (0).  Synchronous.                    */
 dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant);
 
-/* Pin the fused-kernel variant for the current precision (0 or 1, as
- * dmrg_sb_autotune reports it); DMRG_E_ARG for an unknown variant.         */
+/* Pin the product variant for the current precision (0 to 3, as
+ * dmrg_sb_autotune reports it); DMRG_E_ARG for an unknown variant.  FP64
+ * products ignore it.                                                       */
 dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant);
 
 /* Reorthogonalisation of dmrg_lanczos_ground's basis (paper Sec. 3.3 gives
@@ -249,11 +257,14 @@ dmrg_status dmrg_hpsi(dmrg_sb sb, const double* psi_d, double* y_d, double alpha
 /* The product of dmrg_hpsi for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same arguments and result, but every temporary (the
- * FP32 copy of psi that the FP32 and BF16 products read) lives in a fixed
- * device scratch array of 2^24 floats (64 MiB) that the library holds on
- * each device from the first dmrg_ctx_create there until the process ends;
- * the call makes no allocation and takes no timing events.  DMRG_E_NOMEM if
- * D_in + 16 exceeds 2^24.  Calls on one device share the scratch: calls that
+ * FP32 copy of psi that the FP32 and BF16 products read, and the partial
+ * tiles of the macro-tile variant) lives in a fixed device scratch array of
+ * 2^24 floats (64 MiB) that the library holds on each device from the first
+ * dmrg_ctx_create there until the process ends; the call makes no
+ * allocation and takes no timing events.  DMRG_E_NOMEM if D_in + 16 exceeds
+ * 2^24; when the macro-tile variant is selected but its partial tiles do
+ * not fit beside psi, the 32 x 32 tile variant runs.  Calls on one device
+ * share the scratch: calls that
  * overlap on one GPU (other host threads, other streams) race; calls queued
  * on one stream do not.  Asynchronous on the context's stream.            */
 dmrg_status dmrg_hpsi_noalloc(dmrg_sb sb, const double* psi_d, double* y_d, double alpha, double beta);

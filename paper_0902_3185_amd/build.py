@@ -20,7 +20,8 @@ BUILD = os.path.join(CSRC, "_build")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdmrg.so")
 
-SOURCES = ["api.cpp", "plan.cpp", "eigen.cpp", "hpsi.hip", "vec.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "macro_plan.cpp", "eigen.cpp", "hpsi.hip", "macro.hip", "vec.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

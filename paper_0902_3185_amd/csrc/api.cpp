@@ -171,6 +171,12 @@ struct Staged {
   DevBuf wg_start;          // persistent launch: each workgroup's slots
   DevBuf coef_img, coef_seg;   // where each coefficient sits in images / segs
   int64_t ncoef_img = 0, ncoef_seg = 0;
+  // the macro-tile plan (FP32 / BF16 variant 1), staged with the FP32 pool
+  bool has_mac = false;
+  int32_t mac_nwg = 0, mac_nshared = 0, mac_nparts = 0;
+  DevBuf mtiles, msegs, mggs, mitems, mwg, mshared, mpart, mcoef_seg, mcoef_gg, mdense;
+  int64_t mac_ndense = 0;
+  int64_t ncoef_mseg = 0, ncoef_mgg = 0;
   int32_t nwg = 0;
   int32_t img_stride = 0;   // words per image
   int32_t nslots = 0;
@@ -283,6 +289,39 @@ dmrg_status stage_images(Staged& st, hipStream_t s) {
   return DMRG_OK;
 }
 
+// The macro-tile plan of a staged plan: records, work lists and room for
+// the partial tiles on the device.
+dmrg_status stage_macro(Staged& st, hipStream_t s) {
+  MacroPlan mp;
+  {
+    std::vector<float> pool32;
+    dense_f32(st.plan, pool32);
+    build_macro(st.plan, pool32, kPersistentWGs * kMacWGsPerCU, 8, mp);
+  }
+  dmrg_status r;
+  if ((r = upload(st.mdense, mp.dense.data(), mp.dense.size() * sizeof(float), s)) != DMRG_OK) return r;
+  st.mac_ndense = (int64_t)mp.dense.size();
+  if ((r = upload(st.mtiles, mp.tiles.data(), mp.tiles.size() * sizeof(MacTile), s)) != DMRG_OK) return r;
+  if ((r = upload(st.msegs, mp.segs.data(), mp.segs.size() * sizeof(MacSeg), s)) != DMRG_OK) return r;
+  if ((r = upload(st.mggs, mp.ggs.data(), mp.ggs.size() * sizeof(MacGG), s)) != DMRG_OK) return r;
+  if ((r = upload(st.mitems, mp.items.data(), mp.items.size() * sizeof(MacItem), s)) != DMRG_OK) return r;
+  if ((r = upload(st.mwg, mp.wg_start.data(), mp.wg_start.size() * sizeof(int32_t), s)) != DMRG_OK) return r;
+  if ((r = upload(st.mshared, mp.shared.data(), mp.shared.size() * sizeof(int32_t), s)) != DMRG_OK) return r;
+  if ((r = upload(st.mcoef_seg, mp.coef_seg.data(), mp.coef_seg.size() * sizeof(CoefRef), s)) != DMRG_OK)
+    return r;
+  if ((r = upload(st.mcoef_gg, mp.coef_gg.data(), mp.coef_gg.size() * sizeof(CoefRef), s)) != DMRG_OK)
+    return r;
+  st.mac_nwg = (int32_t)mp.wg_start.size() - 1;
+  st.mac_nshared = (int32_t)mp.shared.size();
+  st.mac_nparts = mp.nparts;
+  st.ncoef_mseg = (int64_t)mp.coef_seg.size();
+  st.ncoef_mgg = (int64_t)mp.coef_gg.size();
+  HIP_TRY(st.mpart.ensure((size_t)std::max(1, mp.nparts) * kMac * kMac * sizeof(float)));
+  HIP_TRY(hipStreamSynchronize(s));   // the host records die here
+  st.has_mac = st.mac_nwg > 0;
+  return DMRG_OK;
+}
+
 dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
   const Plan& p = st.plan;
   hipStream_t s = ctx->stream;
@@ -308,6 +347,7 @@ dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
     if ((r = upload(st.dense32, f.data(), f.size() * sizeof(float), s)) != DMRG_OK) return r;
     HIP_TRY(hipStreamSynchronize(s));   // the host staging vector dies here
     st.has32 = true;
+    if ((r = stage_macro(st, s)) != DMRG_OK) return r;
   }
   st.max_nseg = 0;
   st.plain.clear();
@@ -344,15 +384,21 @@ hipError_t take_event(dmrg_ctx c, hipEvent_t* e) {
 // room past the end, so that their vector loads stay inside it): psi32, if
 // given, already holds it; otherwise psi is converted into it first.  The
 // event pair, if any, brackets the product alone.
+//
+// Variant 1 (FP32 / BF16, when the macro plan is staged) runs the macro-tile
+// kernels with their partial tiles in `part` if given, else in the plan's
+// own buffer.
+
 dmrg_status launch_fused(Staged& st, int kp, int variant, const void* dense, const double* psi,
                          double* y, double alpha, double beta, hipStream_t s, hipEvent_t t0,
-                         hipEvent_t t1, const float* psi32 = nullptr) {
+                         hipEvent_t t1, const float* psi32 = nullptr, float* part = nullptr) {
   const int32_t* wgs = st.nwg > 0 ? st.wg_start.as<int32_t>() : nullptr;
   if (kp == kPrecF64) {
-    HIP_TRY(launch_hpsi(kp, variant, st.nslots, st.images.as<uint32_t>(), st.img_stride, dense, psi, y,
+    HIP_TRY(launch_hpsi(kp, 0, st.nslots, st.images.as<uint32_t>(), st.img_stride, dense, psi, y,
                         alpha, beta, s, t0, t1, nullptr, 0, 0, wgs, st.nwg));
     return DMRG_OK;
   }
+  const bool mac = variant == 1 && st.has_mac;
   const int64_t n = st.plan.D_in + kPoolPad;
   if (!psi32) {
     HIP_TRY(st.psi32.ensure((size_t)n * sizeof(float)));
@@ -360,8 +406,16 @@ dmrg_status launch_fused(Staged& st, int kp, int variant, const void* dense, con
     psi32 = st.psi32.as<float>();
   }
   const int64_t ndense = (int64_t)st.plan.dense.size() + kPoolPad;
-  HIP_TRY(launch_hpsi(kp, variant, st.nslots, st.images.as<uint32_t>(), st.img_stride, dense, psi, y,
-                      alpha, beta, s, t0, t1, psi32, ndense, n, wgs, st.nwg));
+  if (mac) {
+    HIP_TRY(launch_hpsi_macro(kp == kPrecBF16X3, st.mac_nwg, st.mac_nshared, st.mtiles.as<MacTile>(),
+                              st.msegs.as<MacSeg>(), st.mggs.as<MacGG>(), st.mitems.as<MacItem>(),
+                              st.mwg.as<int32_t>(), st.mshared.as<int32_t>(), st.mdense.as<float>(),
+                              st.mac_ndense, psi32, n, psi, y, alpha, beta, part ? part : st.mpart.as<float>(), s,
+                              t0, t1));
+    return DMRG_OK;
+  }
+  HIP_TRY(launch_hpsi(kp, variant == 1 ? 0 : variant, st.nslots, st.images.as<uint32_t>(), st.img_stride,
+                      dense, psi, y, alpha, beta, s, t0, t1, psi32, ndense, n, wgs, st.nwg));
   return DMRG_OK;
 }
 
@@ -656,6 +710,12 @@ dmrg_status dmrg_sb_set_coeffs(dmrg_sb sb, const double* c_h) {
                                   sb->coeff.data(), nt, sb->ctx->stream));
       HIP_TRY(launch_patch_coeffs(st->segs.p, st->coef_seg.as<CoefRef>(), st->ncoef_seg,
                                   sb->coeff.data(), nt, sb->ctx->stream));
+      if (st->has_mac) {
+        HIP_TRY(launch_patch_coeffs(st->msegs.p, st->mcoef_seg.as<CoefRef>(), st->ncoef_mseg,
+                                    sb->coeff.data(), nt, sb->ctx->stream));
+        HIP_TRY(launch_patch_coeffs(st->mggs.p, st->mcoef_gg.as<CoefRef>(), st->ncoef_mgg,
+                                    sb->coeff.data(), nt, sb->ctx->stream));
+      }
     }
   }
   return DMRG_OK;
@@ -672,6 +732,7 @@ dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec) {
     if (r != DMRG_OK) return r;
     HIP_TRY(hipStreamSynchronize(sb->ctx->stream));
     sb->fwd.has32 = true;
+    if ((r = stage_macro(sb->fwd, sb->ctx->stream)) != DMRG_OK) return r;
   }
   sb->prec = prec;
   return DMRG_OK;
@@ -701,6 +762,7 @@ dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant) {
   float best_ms = 0.f;
   hipError_t err = hipSuccess;
   for (int v = 0; v < kVariants && err == hipSuccess; ++v) {
+    if (v == 1 && !stg.has_mac) continue;
     auto go = [&]() {
       return launch_fused(sb->fwd, kp, v, stg.dense32.p, x.as<double>(), y.as<double>(), 1.0, 0.0, s,
                           nullptr, nullptr) == DMRG_OK
@@ -776,9 +838,15 @@ dmrg_status dmrg_hpsi_noalloc(dmrg_sb sb, const double* psi_d, double* y_d, doub
        << " of padding) exceeds the fixed scratch of " << kScratchFloats << " floats";
     return fail(DMRG_E_NOMEM, os.str());
   }
+  // the macro-tile variant's partial tiles follow psi in the scratch; when
+  // they do not fit, the 32 x 32 tile kernel runs instead
+  int variant = sb->variant[kp];
+  const int64_t psi_room = (p.D_in + kPoolPad + 63) / 64 * 64;
+  const int64_t need = psi_room + (int64_t)f.mac_nparts * kMac * kMac;
+  if (variant == 1 && (!f.has_mac || need > kScratchFloats)) variant = 0;
   HIP_TRY(launch_psi_to_f32(psi_d, buf, p.D_in, s));
-  return launch_fused(f, kp, sb->variant[kp], f.dense32.p, psi_d, y_d, alpha, beta, s, nullptr, nullptr,
-                      buf);
+  return launch_fused(f, kp, variant, f.dense32.p, psi_d, y_d, alpha, beta, s, nullptr, nullptr, buf,
+                      variant == 1 ? buf + psi_room : nullptr);
 }
 
 dmrg_status dmrg_hpsi_adjoint(dmrg_sb sb, const double* psi_d, const double* g_d, double* gpsi_d,

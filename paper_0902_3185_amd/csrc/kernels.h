@@ -6,6 +6,7 @@
 #include <utility>
 #include <vector>
 
+#include "macro.h"
 #include "plan.h"
 
 namespace dmrg {
@@ -25,7 +26,15 @@ constexpr int kMaxSegPerBlock = 32;
 // psi (npsi elements); both buffers must hold at least 4 elements (vector
 // loads are clamped inside them).  Events t0/t1, when not null, are recorded
 // at the start and end of the kernel itself.
-constexpr int kVariants = 1;
+//
+// Variants of the FP32 and BF16 products (the FP64 product has variant 0
+// only): 0 = the 32 x 32 tile kernel above, sixteen waves per tile, one
+// persistent workgroup per compute unit; 1 = the 64 x 64 macro-tile kernel
+// (launch_hpsi_macro), for superblocks whose blocks are large; 2 and 3 =
+// the 32 x 32 tile kernel with eight or four waves per tile and one
+// workgroup per tile slot, several resident per compute unit (for
+// superblocks of many small tiles, whose time is latency).
+constexpr int kVariants = 4;
 hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
                        hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
@@ -34,6 +43,20 @@ hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images
 
 // out[0 .. n) = (float) psi, out[n .. n + kPoolPad) = 0
 hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream);
+
+// y = alpha * H psi + beta * y with the macro-tile kernel (macro.h): nwg
+// workgroups, workgroup w taking items wg_start[w] .. wg_start[w + 1] - 1,
+// then a combining kernel over the nshared tiles listed in `shared` (tiles
+// split between workgroups).  dense is the FP32 operator pool (ndense
+// elements), psi32 the FP32 copy of psi (npsi elements), psi64 psi itself
+// (elementwise terms are summed in FP64).  part holds the plan's nparts
+// partial tiles (kMac * kMac floats each).  Both pools must be under 2 GiB.
+// Events t0/t1 bracket the two kernels.
+hipError_t launch_hpsi_macro(bool bf16, int nwg, int nshared, const MacTile* tiles, const MacSeg* segs,
+                             const MacGG* ggs, const MacItem* items, const int32_t* wg_start,
+                             const int32_t* shared, const float* dense, int64_t ndense, const float* psi32,
+                             int64_t npsi, const double* psi64, double* y, double alpha, double beta,
+                             float* part, hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // Writes c[refs[i].term] to the double at base + refs[i].off for i < n (the
 // coefficient fields of staged tile images or segment tables), in stream

@@ -77,17 +77,23 @@ def test_hpsi_parity(ctx, name, m, prec):
     assert np.linalg.norm(y2 - OS.hpsi_blocks(desc, psi)) <= TOL[prec] * _scale(desc, psi)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp64_plain"])
+FULL_CASES = [(p, 0) for p in ("fp64", "fp32", "bf16x3", "fp64_plain")] + [("fp32", 1), ("bf16x3", 1)]
+
+
+@pytest.mark.parametrize("prec,variant", FULL_CASES, ids=[f"{p}-v{v}" for p, v in FULL_CASES])
 @pytest.mark.parametrize("name", list(WORKLOADS))
-def test_full_size_elementwise(ctx, name, prec):
+def test_full_size_elementwise(ctx, name, prec, variant):
     """Every workload at its full size (the centre superblocks the benchmark
-    times, same launch path): every entry of H psi within its rounding bound,
-    and the error norm within the aggregate tolerance."""
+    times, same launch paths: the 32 x 32 tile kernel and the 64 x 64
+    macro-tile kernel): every entry of H psi within its rounding bound, and
+    the error norm within the aggregate tolerance."""
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock(name, seed=0)
     sb = Superblock(desc, prec=prec, ctx=ctx)
+    if variant:
+        sb.set_variant(variant)
     psi = seeded_vector(sb.D, 21)
-    print(f"full-size product {name} {prec} D={sb.D}", flush=True)
+    print(f"full-size product {name} {prec} variant {variant} D={sb.D}", flush=True)
     y = _host(sb.hpsi(_dev(psi)))
     ref = OS.hpsi_blocks(desc, psi)
     s, bound = FB.product_bound(desc, psi, prec)

@@ -45,12 +45,21 @@ def _call(fn, sb, psi, y, alpha, beta):
                                         float(alpha), float(beta)))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
-def test_noalloc_matches_hpsi_on_two_calls(ctx, prec):
+CASES = [("fp32", 0), ("bf16x3", 0), ("fp64", 0), ("fp32", 1), ("bf16x3", 1)]
+
+
+@pytest.mark.parametrize("prec,variant", CASES, ids=[f"{p}-v{v}" for p, v in CASES])
+def test_noalloc_matches_hpsi_on_two_calls(ctx, prec, variant):
+    """Variant 1 (the macro-tile kernel) also keeps its partial tiles and
+    tile counters in the scratch; the ladder superblock shares most of its
+    tiles between workgroups."""
     from paper_0902_3185_amd.superblock import Superblock
-    for name, m, seed in [("hubbard_L64_U4_m512", None, 0), ("heisenberg_L100_m256", 64, 1)]:
+    first = ("ladder_2x32_m1024", None, 0) if variant else ("hubbard_L64_U4_m512", None, 0)
+    for name, m, seed in [first, ("heisenberg_L100_m256", 64, 1)]:
         desc = workload_superblock(name, m=m, seed=seed)
         sb = Superblock(desc, prec=prec, ctx=ctx)
+        if variant:
+            sb.set_variant(variant)
         psi = seeded_vector(sb.D, 71)
         y0 = seeded_vector(sb.D, 72)
         ya, yb = _dev(y0), _dev(y0)
