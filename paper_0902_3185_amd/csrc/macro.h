@@ -19,7 +19,7 @@ namespace dmrg {
 constexpr int kMac = 64;         // output tile edge
 constexpr int kMacStage = 32;    // contraction positions per stage
 constexpr int kMacThreads = 256; // four waves, one 32 x 32 quarter each
-constexpr int kMacWGsPerCU = 2;  // persistent workgroups per compute unit
+constexpr int kMacWGsPerCU = 3;  // persistent workgroups per compute unit
 constexpr int kMacSegLds = 24;   // segments of one item held in LDS (items are cut to fit)
 
 struct MacTile {

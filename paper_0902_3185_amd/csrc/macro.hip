@@ -10,7 +10,7 @@
 // operand element fetched from memory feeds 64 multiply-adds (a 32 x 32
 // tile per workgroup would give each element 32).  Two LDS buffers
 // alternate: while the waves work on one stage, the next is being written;
-// the loads of the four stages after it are in flight in registers.
+// the loads of the two stages after it are in flight in registers.
 //
 // Panel loads (256 threads, thread t, wave w, lane l):
 //   A rows t/8 and t/8 + 32, positions 4*(t%8) .. +3, one 16-byte load
@@ -301,7 +301,7 @@ __device__ inline void finish(double (&v)[16], const MacTile& T, const MacGG* __
 }
 
 template <bool kBF16>
-__global__ __launch_bounds__(kMacThreads) void hpsi_macro(
+__global__ __launch_bounds__(kMacThreads, kMacWGsPerCU) void hpsi_macro(
     const MacTile* __restrict__ tiles, const MacSeg* __restrict__ msegs, const MacGG* __restrict__ mggs,
     const MacItem* __restrict__ items, const int32_t* __restrict__ wg_start,
     const float* __restrict__ dense, int64_t ndense, const float* __restrict__ psi32, int64_t npsi,
@@ -353,15 +353,11 @@ __global__ __launch_bounds__(kMacThreads) void hpsi_macro(
       // kDepth stages in flight ahead of the one being written: register set
       // R[(r + 1) % kDepth] holds stage s + 1 when stage s = s0 + r is on the
       // matrix cores (the loop is unrolled so that the sets stay registers)
-      constexpr int kDepth = 4;
-      Raw R0, R1, R2, R3;
+      constexpr int kDepth = 2;
+      Raw R0, R1;
       fetch(R0, s0);
       adv_fetch(s0 + 1);
       fetch(R1, s0 + 1);
-      adv_fetch(s0 + 2);
-      fetch(R2, s0 + 2);
-      adv_fetch(s0 + 3);
-      fetch(R3, s0 + 3);
       __builtin_amdgcn_sched_barrier(0);
       put(R0, s0, buf0);
       adv_fetch(s0 + kDepth);
@@ -379,11 +375,9 @@ __global__ __launch_bounds__(kMacThreads) void hpsi_macro(
         __syncthreads();
         return s + 1 < s1;
       };
-      for (int s = s0;; s += 4) {
+      for (int s = s0;; s += 2) {
         if (!step(buf0, buf1, R1, s)) break;
-        if (!step(buf1, buf0, R2, s + 1)) break;
-        if (!step(buf0, buf1, R3, s + 2)) break;
-        if (!step(buf1, buf0, R0, s + 3)) break;
+        if (!step(buf1, buf0, R0, s + 1)) break;
       }
     }
     // epilogue: a shared tile's share stores its partial sum (added up by
