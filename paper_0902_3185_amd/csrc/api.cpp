@@ -1108,6 +1108,18 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
     HIP_TRY(launch_multi_dot(w, 0, 1, w, D, part, nrm2, s));
     HIP_TRY(launch_normalise(V, w, nrm2, D, s));
   }
+  if (!converged) {
+    // the product cap ended the solve inside a cycle: V[0] now holds that
+    // cycle's Ritz vector, whose energy and residual the checks never saw
+    // (they belong to the cycle's start); one FP64 product gives them
+    if ((st = run_product(sb, sb->fwd, DMRG_FP64, V, w, 1.0, 0.0)) != DMRG_OK) return st;
+    HIP_TRY(launch_multi_dot(V, 0, 1, w, D, part, nrm2, s));
+    HIP_TRY(launch_multi_dot(w, 0, 1, w, D, part, nrm2 + 1, s));
+    HIP_TRY(hipMemcpyAsync(hs, nrm2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    E = hs[0];
+    res = std::sqrt(std::max(0.0, hs[1] - hs[0] * hs[0]));
+  }
   HIP_TRY(hipMemcpyAsync(psi_d, V, (size_t)D * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   *E0_h = E;

@@ -599,12 +599,15 @@ def e0_of(ctx, Sp, Ep, model, n, q_target, psi, prec):
 
 def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=2000,
         no_split=True, keep_range=None, on_step=None, wavefunction=True, reflect=False,
-        on_solve=None):
+        on_solve=None, on_carry=None):
     """Infinite phase to L sites, then ``sweeps`` finite sweeps (Secs. 1, 3.1).
 
     ``init(D, step)`` gives the Lanczos start vector of each infinite-phase
     step (numpy); finite-sweep steps start from the previous ground state
     carried to the new basis when ``wavefunction`` is set (else ``init``).
+    ``on_carry(info)``, if given, sees every carried vector with what made
+    it (direction, old and new superblock bases, old ground state, the kept
+    vectors used, the blocks involved).
     Returns a list of per-step records.
     """
     import torch
@@ -678,15 +681,27 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
                 if same:
                     start = lambda sb, pv=pv: pv["psi"] if sb.D == pv["sb"].D else None
                 elif pv["p"] + 1 == p and 0 in pv["sides"]:
-                    start = lambda sb, pv=pv, Sp=Sp, Ep=Ep: wf_left_to_right(
-                        ctx, pv["sb"], pv["psi"], pv["Sp"].product, pv["Ep"].product,
-                        pv["trs"][0]["W"], pv["out"][0], right[L - pv["p"] - 1], sb,
-                        Sp.product, Ep.product)
+                    def start(sb, pv=pv, Sp=Sp, Ep=Ep, other=right[L - pv["p"] - 1]):
+                        v = wf_left_to_right(ctx, pv["sb"], pv["psi"], pv["Sp"].product,
+                                             pv["Ep"].product, pv["trs"][0]["W"], pv["out"][0],
+                                             other, sb, Sp.product, Ep.product)
+                        if on_carry is not None:
+                            on_carry(dict(direction="left_to_right", p_old=pv["p"], p=p,
+                                          old=(pv["Sp"].basis, pv["Ep"].basis), new=(Sp.basis, Ep.basis),
+                                          psi_old=pv["psi"], W=pv["trs"][0]["W"], truncated=pv["out"][0],
+                                          other=other, carried=v))
+                        return v
                 elif pv["p"] - 1 == p and 1 in pv["sides"]:
-                    start = lambda sb, pv=pv, Sp=Sp, Ep=Ep: wf_right_to_left(
-                        ctx, pv["sb"], pv["psi"], pv["Sp"].product, pv["Ep"].product,
-                        pv["trs"][1]["W"], pv["out"][1], left[pv["p"] - 1], sb,
-                        Sp.product, Ep.product)
+                    def start(sb, pv=pv, Sp=Sp, Ep=Ep, other=left[pv["p"] - 1]):
+                        v = wf_right_to_left(ctx, pv["sb"], pv["psi"], pv["Sp"].product,
+                                             pv["Ep"].product, pv["trs"][1]["W"], pv["out"][1],
+                                             other, sb, Sp.product, Ep.product)
+                        if on_carry is not None:
+                            on_carry(dict(direction="right_to_left", p_old=pv["p"], p=p,
+                                          old=(pv["Sp"].basis, pv["Ep"].basis), new=(Sp.basis, Ep.basis),
+                                          psi_old=pv["psi"], W=pv["trs"][1]["W"], truncated=pv["out"][1],
+                                          other=other, carried=v))
+                        return v
             out = solve(Sp, Ep, L, (side,), "finite", p, start=start)
             if side == 0:
                 left[p] = out[0]

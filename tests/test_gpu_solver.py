@@ -133,6 +133,22 @@ def test_lanczos_cap_reports_noconv(ctx):
     sb = Superblock(desc, prec="fp64", ctx=ctx)
     r = sb.lanczos(_dev(seeded_vector(sb.D, 1)), max_iter=2, tol=1e-12, raise_noconv=False)
     assert not r["converged"] and r["iters"] == 2 and np.isfinite(r["energy"])
+    # the reported energy and residual are those of the returned vector
+    psi = _host(r["psi"])
+    hp = OS.hpsi_blocks(desc, psi)
+    e = float(np.dot(psi, hp))
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-12
+    assert abs(r["energy"] - e) <= 1e-12 * max(1.0, abs(e))
+    assert abs(r["resid"] - np.linalg.norm(hp - e * psi)) <= 1e-10 * max(1.0, abs(e))
+    for prec in ("fp32", "bf16x3"):
+        sb.set_prec(prec)
+        r = sb.lanczos(_dev(seeded_vector(sb.D, 1)), max_iter=5, tol=1e-14, raise_noconv=False)
+        psi = _host(r["psi"])
+        hp = OS.hpsi_blocks(desc, psi)
+        e = float(np.dot(psi, hp))
+        assert not r["converged"]
+        assert abs(r["energy"] - e) <= 1e-12 * max(1.0, abs(e)), prec
+        assert abs(r["resid"] - np.linalg.norm(hp - e * psi)) <= 1e-10 * max(1.0, abs(e)), prec
 
 
 def test_lanczos_exact_eigenvector_stops_at_once(ctx):
