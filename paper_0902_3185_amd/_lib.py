@@ -10,7 +10,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdmrg.so")
+# DMRG_LIB may name another build of the same library (the host-sanitizer
+# build used by the CPU tests)
+LIB_PATH = os.environ.get("DMRG_LIB") or os.path.join(_HERE, "libdmrg.so")
 
 DMRG_OK = 0
 STATUS = {0: "DMRG_OK", 1: "DMRG_E_ARG", 2: "DMRG_E_QN", 3: "DMRG_E_SHAPE", 4: "DMRG_E_NOMEM",

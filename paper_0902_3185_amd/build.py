@@ -54,6 +54,71 @@ def _run(cmd):
     return p.returncode, out
 
 
+# Host-side address and undefined-behaviour sanitizers (each flag after
+# -Xarch_host: they do not reach the device code).
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+            "-Xarch_host", "-g"]
+BUILD_SAN = os.path.join(CSRC, "_build_san")
+LIB_SAN = os.path.join(HERE, "libdmrg_san.so")
+
+
+def asan_runtime():
+    """The compiler's shared address-sanitizer runtime (to preload into a
+    process that loads the sanitized library)."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return hits[-1] if hits else None
+
+
+def build_sanitized(verbose=False):
+    """libdmrg_san.so: the host code (plan, API, eigen-solvers, launchers)
+    built with the sanitizers above (the device code as usual), for host-only tests
+    run with asan_runtime() preloaded.  Rebuilt only when a source changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for src in SOURCES + ["plan.h", "macro.h", "kernels.h", "eigen.h"]:
+        path = os.path.join(CSRC, src)
+        if os.path.exists(path):
+            with open(path, "rb") as f:
+                h.update(f.read())
+    with open(os.path.join(ROOT, "include", "dmrg.h"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.abspath(__file__), "rb") as f:   # the build recipe itself
+        h.update(f.read())
+    stamp = os.path.join(BUILD_SAN, "stamp")
+    if os.path.exists(LIB_SAN) and os.path.exists(stamp) and open(stamp).read() == h.hexdigest():
+        return LIB_SAN
+    os.makedirs(BUILD_SAN, exist_ok=True)
+    base = ["-O1", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
+            "-Wno-unused-variable", "-I" + os.path.join(ROOT, "include")]
+    cmds, objs = [], []
+    for src in SOURCES:
+        obj = os.path.join(BUILD_SAN, os.path.splitext(src)[0] + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmds.append(([HIPCC] + base + SANITIZE + lang + ["-c", os.path.join(CSRC, src), "-o", obj], src))
+        objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as ex:
+        results = list(ex.map(lambda c: (c[1],) + _run(c[0]), cmds))
+    for src, rc, out in results:
+        if verbose and out.strip():
+            print(f"[{src}]\n{out}")
+        if rc != 0:
+            raise RuntimeError(f"hipcc (sanitized) failed on {src}:\n{out}")
+    link = [HIPCC, "-shared", "-fPIC", "-o", LIB_SAN + ".tmp"] + objs
+    tl = _torch_lib_dir()
+    if tl:
+        link += [f"-Wl,-rpath,{tl}", f"-L{tl}"]
+    link += ["-Wl,-rpath,/opt/rocm/lib"]
+    rc, out = _run(link)
+    if rc != 0:
+        raise RuntimeError(f"link (sanitized) failed:\n{out}")
+    os.replace(LIB_SAN + ".tmp", LIB_SAN)
+    with open(stamp, "w") as f:
+        f.write(h.hexdigest())
+    return LIB_SAN
+
+
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     objs = []
@@ -85,4 +150,7 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))
