@@ -224,15 +224,13 @@ dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec);
  * Variant 1: 64 x 64 output tiles whose two operand panels are staged once
  * in LDS for four waves; all tiles' contraction stages dealt out in equal
  * shares to the workgroups (a tile may be cut between workgroups, whose
- * partial sums a second kernel adds in a fixed order).  Variants 2 and 3:
- * as 0 with eight or four waves per tile and one workgroup per tile, several
- * resident per compute unit.  All are deterministic and within the same
- * rounding bound; their results differ in the last bits (different
- * summation orders).  *variant (may be NULL) receives the choice; FP64 and
+ * partial sums a second kernel adds in a fixed order).  Both are
+ * deterministic and within the same rounding bound; their results differ
+ * in the last bits (different summation orders).  *variant (may be NULL) receives the choice; FP64 and
  * the plain baseline have one variant (0).  Synchronous.                    */
 dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant);
 
-/* Pin the product variant for the current precision (0 to 3, as
+/* Pin the product variant for the current precision (0 or 1, as
  * dmrg_sb_autotune reports it); DMRG_E_ARG for an unknown variant.  FP64
  * products ignore it.                                                       */
 dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant);

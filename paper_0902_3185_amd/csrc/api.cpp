@@ -414,8 +414,8 @@ dmrg_status launch_fused(Staged& st, int kp, int variant, const void* dense, con
                               t0, t1));
     return DMRG_OK;
   }
-  HIP_TRY(launch_hpsi(kp, variant == 1 ? 0 : variant, st.nslots, st.images.as<uint32_t>(), st.img_stride,
-                      dense, psi, y, alpha, beta, s, t0, t1, psi32, ndense, n, wgs, st.nwg));
+  HIP_TRY(launch_hpsi(kp, 0, st.nslots, st.images.as<uint32_t>(), st.img_stride, dense, psi, y, alpha, beta,
+                      s, t0, t1, psi32, ndense, n, wgs, st.nwg));
   return DMRG_OK;
 }
 

@@ -298,16 +298,15 @@ __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, int64_t byte
 }
 constexpr uint32_t kNoRead = 0x80000000u;   // an offset past every buffer: reads zeros, no traffic
 
-template <bool kBF16, int kW = 16>
+template <bool kBF16>
 struct F32S {
   using op_t = float;
   using psi_t = float;
   using red_t = float;
-  static constexpr int kWaves = kW;
-  // waves per SIMD the register budget must allow: sixteen-wave and
-  // eight-wave workgroups four (one or two workgroups per compute unit),
-  // four-wave ones three (three per compute unit, as many as LDS holds)
-  static constexpr int kMinWavesPerEU = kW == 4 ? 3 : 4;
+  static constexpr int kWaves = 16;
+  // waves per SIMD the register budget must allow (one workgroup of
+  // sixteen waves per compute unit)
+  static constexpr int kMinWavesPerEU = 4;
   static constexpr int kLdn = 36;                      // [k][w] window row stride (floats)
   static constexpr int kAFloats = kTile * kChunk;      // A panel [m][k]
   static constexpr int kBFloats = kChunk * kLdn;       // B panel ([k][w]; [n][k] uses 512)
@@ -1021,30 +1020,13 @@ hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images
   if (wg_start && nwg <= 0) return hipErrorInvalidValue;
   if (prec == kPrecF32 || prec == kPrecBF16X3) {
     if (!psi32 || npsi < 4 || ndense < 4) return hipErrorInvalidValue;
-    const bool bf = prec == kPrecBF16X3;
-    // variants 2 and 3: 8 or 4 waves per tile, one workgroup per tile slot
-    // (several resident per compute unit), no persistent lists
-    if (variant == 2) {
-      if (bf)
-        launch_tiles<F32S<true, 8>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0, t1,
-                                          ndense, npsi, nullptr, 0);
-      else
-        launch_tiles<F32S<false, 8>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0,
-                                           t1, ndense, npsi, nullptr, 0);
-    } else if (variant == 3) {
-      if (bf)
-        launch_tiles<F32S<true, 4>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0, t1,
-                                          ndense, npsi, nullptr, 0);
-      else
-        launch_tiles<F32S<false, 4>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0,
-                                           t1, ndense, npsi, nullptr, 0);
-    } else if (bf) {
+    (void)variant;   // variant 1 (the macro-tile kernel) is launched by launch_hpsi_macro
+    if (prec == kPrecBF16X3)
       launch_tiles<F32S<true>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0, t1,
                                      ndense, npsi, wg_start, nwg);
-    } else {
+    else
       launch_tiles<F32S<false>, true>(nslots, images, stride, dense, psi32, y, alpha, beta, stream, t0, t1,
                                       ndense, npsi, wg_start, nwg);
-    }
   } else {
     launch_tiles<F64Tile, false>(nslots, images, stride, dense, psi, y, alpha, beta, stream, t0, t1, 0, 0,
                                  wg_start, nwg);

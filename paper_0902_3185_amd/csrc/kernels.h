@@ -30,11 +30,8 @@ constexpr int kMaxSegPerBlock = 32;
 // Variants of the FP32 and BF16 products (the FP64 product has variant 0
 // only): 0 = the 32 x 32 tile kernel above, sixteen waves per tile, one
 // persistent workgroup per compute unit; 1 = the 64 x 64 macro-tile kernel
-// (launch_hpsi_macro), for superblocks whose blocks are large; 2 and 3 =
-// the 32 x 32 tile kernel with eight or four waves per tile and one
-// workgroup per tile slot, several resident per compute unit (for
-// superblocks of many small tiles, whose time is latency).
-constexpr int kVariants = 4;
+// (launch_hpsi_macro), for superblocks whose blocks are large.
+constexpr int kVariants = 2;
 hipError_t launch_hpsi(int prec, int variant, int nslots, const uint32_t* images, int32_t stride,
                        const void* dense, const double* psi, double* y, double alpha, double beta,
                        hipStream_t stream, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,

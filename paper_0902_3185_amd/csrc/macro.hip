@@ -397,24 +397,69 @@ __global__ __launch_bounds__(kMacThreads, kMacWGsPerCU) void hpsi_macro(
 }
 
 // The shared tiles' partial sums in share order (FP64), their elementwise
-// terms, and y: one workgroup per shared tile, each thread the same sixteen
-// elements its counterpart stored.
-__global__ __launch_bounds__(kMacThreads) void hpsi_macro_combine(
+// terms, and y: one workgroup of 1024 threads per shared tile, thread T the
+// four stored entries 4T .. 4T + 3 (entry e = (w * 16 + r) * 64 + lane of
+// the storing wave w, register r, lane).  The loads of four shares, and of
+// four elementwise terms, go out together before their sums.
+constexpr int kCombineThreads = 1024;
+
+__global__ __launch_bounds__(kCombineThreads) void hpsi_macro_combine(
     const MacTile* __restrict__ tiles, const int32_t* __restrict__ shared, const MacGG* __restrict__ mggs,
     const float* __restrict__ part, const double* __restrict__ psi64, double* __restrict__ y, double alpha,
     double beta) {
   const MacTile T = tiles[shared[blockIdx.x]];
-  const int w = rfl(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int nsplit = rfl(T.nsplit);
-  const float* p0 = part + (int64_t)T.part0 * (kMac * kMac);
-  double v[16];
+  const int nsplit = rfl(T.nsplit), ngg = rfl(T.ngg);
+  const int e0 = threadIdx.x * 4;
+  const float* p0 = part + (int64_t)T.part0 * (kMac * kMac) + e0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < nsplit; s += 4) {
+    f4 x[4];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = 0.0;
-  for (int s = 0; s < nsplit; ++s) {
+    for (int u = 0; u < 4; ++u)
+      x[u] = s + u < nsplit ? *reinterpret_cast<const f4*>(p0 + (int64_t)(s + u) * (kMac * kMac))
+                            : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] += (double)p0[(int64_t)s * (kMac * kMac) + (w * 16 + r) * 64 + lane];
+    for (int u = 0; u < 4; ++u)
+      if (s + u < nsplit) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += (double)x[u][k];
+      }
   }
-  finish(v, T, mggs, psi64, y, alpha, beta, w, lane);
+  int mt[4], nt[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = e0 + k, w = e >> 10, r = (e >> 6) & 15, lane = e & 63;
+    mt[k] = 32 * (w >> 1) + 16 * ((r >> 2) >> 1) + 4 * (lane >> 4) + (r & 3);
+    nt[k] = 32 * (w & 1) + 16 * ((r >> 2) & 1) + (lane & 15);
+  }
+  for (int q = 0; q < ngg; q += 4) {
+    double x[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const MacGG& G = mggs[T.gg0 + (q + u < ngg ? q + u : q)];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t row = G.row[mt[k]];
+        const int32_t col = G.col[nt[k]];
+        x[u][k] = psi64[(row < 0 ? 0 : row) + (col < 0 ? 0 : col)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u < ngg) {
+        const MacGG& G = mggs[T.gg0 + q + u];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += G.c * G.rs[mt[k]] * G.cs[nt[k]] * x[u][k];
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int m = T.m0 + mt[k], n = T.n0 + nt[k];
+    if (m < T.a && n < T.b) {
+      const int64_t idx = T.y_off + (int64_t)m * T.ldy + n;
+      y[idx] = beta == 0.0 ? alpha * v[k] : alpha * v[k] + beta * y[idx];
+    }
+  }
 }
 
 }  // namespace
@@ -434,8 +479,8 @@ hipError_t launch_hpsi_macro(bool bf16, int nwg, int nshared, const MacTile* til
     hipExtLaunchKernelGGL(hpsi_macro<false>, dim3(nwg), dim3(kMacThreads), 0, stream, t0, end_main, 0, tiles,
                           segs, ggs, items, wg_start, dense, ndense, psi32, npsi, psi64, y, alpha, beta, part);
   if (nshared > 0)
-    hipExtLaunchKernelGGL(hpsi_macro_combine, dim3(nshared), dim3(kMacThreads), 0, stream, nullptr, t1, 0,
-                          tiles, shared, ggs, part, psi64, y, alpha, beta);
+    hipExtLaunchKernelGGL(hpsi_macro_combine, dim3(nshared), dim3(kCombineThreads), 0, stream, nullptr, t1,
+                          0, tiles, shared, ggs, part, psi64, y, alpha, beta);
   return hipGetLastError();
 }
 
