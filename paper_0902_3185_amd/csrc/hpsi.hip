@@ -771,13 +771,19 @@ __global__ __launch_bounds__(Cfg::kWaves * 64, Cfg::kMinWavesPerEU) void hpsi_ti
   g.m0 = rfl(H.m0);
   g.n0 = rfl(H.n0);
   const int ngemm = rfl(H.ngemm), ngg = rfl(H.ngg), nchunk = rfl(H.nchunk);
+  // The thread index as a fresh value in every tile: the lane offsets
+  // derived from it are formed again per tile instead of being held across
+  // the tile loop, where they would not fit the register budget and would
+  // be spilled (and their reloads wait for the first operand loads).
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   // the wave index is uniform in a wave: say so, so that chunk and segment
   // bookkeeping stays in scalar registers
-  const int wave = rfl(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int wave = rfl(tid >> 6), lane = tid & 63;
 
   // phase 1
   const bool gg_thread = ngg > 0 && wave < kGGThreads / 64;   // uniform per wave
-  const int gmi = threadIdx.x >> 3, gnj = (threadIdx.x & 7) * 4;
+  const int gmi = tid >> 3, gnj = (tid & 7) * 4;
   typename Cfg::Acc acc;
   Cfg::zero(acc);
   if (wave < nchunk)
