@@ -180,6 +180,7 @@ class Product:
 
     def __init__(self, left: Basis, right: Basis, left_major=True):
         self.left, self.right = left, right
+        self.left_major = left_major
         runs = {}
         for a in range(len(left.q)):
             for b in range(len(right.q)):
@@ -599,7 +600,7 @@ def e0_of(ctx, Sp, Ep, model, n, q_target, psi, prec):
 
 def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=2000,
         no_split=True, keep_range=None, on_step=None, wavefunction=True, reflect=False,
-        on_solve=None, on_carry=None):
+        on_solve=None, on_carry=None, checkpoint=None, resume=None, stop_after=None):
     """Infinite phase to L sites, then ``sweeps`` finite sweeps (Secs. 1, 3.1).
 
     ``init(D, step)`` gives the Lanczos start vector of each infinite-phase
@@ -608,7 +609,16 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
     ``on_carry(info)``, if given, sees every carried vector with what made
     it (direction, old and new superblock bases, old ground state, the kept
     vectors used, the blocks involved).
-    Returns a list of per-step records.
+
+    ``checkpoint`` (a path prefix): after every step the block stacks, the
+    step records and the run's position go to ``<prefix>.blocks.npz`` and
+    that step's superblock with its ground state to
+    ``<prefix>.superblock.npz`` (see ``checkpoint.py``).  ``resume`` (a
+    prefix written so) continues such a run with the same model, L, m and
+    sweeps from the step after the saved one; its first step starts from
+    ``init`` (the previous ground state is not kept).  ``stop_after=k``
+    returns after k steps of this call (to end a run early on purpose).
+    Returns a list of per-step records (those before a resume included).
     """
     import torch
 
@@ -624,7 +634,7 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
     step = [0]
     prev = {}
 
-    def solve(Sp, Ep, n, sides, phase, p, start=None):
+    def solve(Sp, Ep, n, sides, phase, p, start=None, on=None):
         bonds = model.bonds(n)
         nu, nd = model.target(n)
         desc = superblock(Sp, Ep, model, Q, n, bonds, nu + Q * nd)
@@ -644,7 +654,9 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
             blk = Sp if side == 0 else Ep
             out[side] = change_basis(ctx, blk, tr, product=blk.product)
             trs[side] = tr
-        if on_step is not None:
+        if on is not None:
+            on(rec, desc, r)
+        elif on_step is not None:
             on_step(rec, desc, r)
         if on_solve is not None:
             on_solve(Sp, Ep, n, desc, r)
@@ -656,22 +668,54 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
                     phase=phase)
         return out
 
-    for n in range(4, L + 1, 2):
-        h = n // 2
-        bonds = model.bonds(n)
-        Sp = grow_right(left[h - 1], model, Q, bonds, keep_range)
-        Ep = grow_left(right[h - 1], model, Q, n, bonds, keep_range)
-        if reflect and mirror_symmetric(model, n):
-            out = solve(Sp, Ep, n, (0,), "infinite", h)
-            left[h], right[h] = out[0], mirrored(out[0])
-        else:
-            out = solve(Sp, Ep, n, (0, 1), "infinite", h)
-            left[h], right[h] = out[0], out[1]
+    # the whole run as one schedule: the infinite phase by size, then the
+    # sweeps' (position, side) steps
+    path = ([(p, 0) for p in range(L // 2, L - 1)] + [(p, 1) for p in range(L - 2, 1, -1)]
+            + [(p, 0) for p in range(2, L // 2 + 1)])
+    schedule = [("infinite", n, 0) for n in range(4, L + 1, 2)]
+    schedule += [("finite", p, side) for _ in range(sweeps) for (p, side) in path]
+    first = 0
+    if resume is not None:
+        from .checkpoint import load_blocks
+        stacks, state = load_blocks(f"{resume}.blocks.npz")
+        if (state["L"], state["m"], state["sweeps"], state["model"]) != (L, m, sweeps, model.name):
+            raise ValueError(f"{resume}: checkpoint of another run ({state})")
+        left, right = stacks["left"], stacks["right"]
+        log[:] = state["log"]
+        step[0] = state["step"]
+        first = state["done"]
+
+    def save(done, desc, psi):
+        from .checkpoint import save_blocks, save_superblock
+        save_superblock(f"{checkpoint}.superblock.npz", desc, psi.cpu().numpy())
+        save_blocks(f"{checkpoint}.blocks.npz", {"left": left, "right": right},
+                    state=dict(L=L, m=m, sweeps=sweeps, model=model.name, done=done, step=step[0],
+                               log=log))
+
+    last = {}
+
+    def keep_last(rec, desc, r):
+        last.update(desc=desc, psi=r["psi"])
+        if on_step is not None:
+            on_step(rec, desc, r)
+
     bonds = model.bonds(L)
-    for _ in range(sweeps):
-        path = ([(p, 0) for p in range(L // 2, L - 1)] + [(p, 1) for p in range(L - 2, 1, -1)]
-                + [(p, 0) for p in range(2, L // 2 + 1)])
-        for (p, side) in path:
+    for i in range(first, len(schedule)):
+        kind, a, side = schedule[i]
+        if kind == "infinite":
+            n = a
+            h = n // 2
+            nb = model.bonds(n)
+            Sp = grow_right(left[h - 1], model, Q, nb, keep_range)
+            Ep = grow_left(right[h - 1], model, Q, n, nb, keep_range)
+            if reflect and mirror_symmetric(model, n):
+                out = solve(Sp, Ep, n, (0,), "infinite", h, on=keep_last)
+                left[h], right[h] = out[0], mirrored(out[0])
+            else:
+                out = solve(Sp, Ep, n, (0, 1), "infinite", h, on=keep_last)
+                left[h], right[h] = out[0], out[1]
+        else:
+            p = a
             Sp = grow_right(left[p - 1], model, Q, bonds, keep_range)
             Ep = grow_left(right[L - p - 1], model, Q, L, bonds, keep_range)
             start = None
@@ -702,9 +746,13 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
                                           psi_old=pv["psi"], W=pv["trs"][1]["W"], truncated=pv["out"][1],
                                           other=other, carried=v))
                         return v
-            out = solve(Sp, Ep, L, (side,), "finite", p, start=start)
+            out = solve(Sp, Ep, L, (side,), "finite", p, start=start, on=keep_last)
             if side == 0:
                 left[p] = out[0]
             else:
                 right[L - p] = out[1]
+        if checkpoint is not None:
+            save(i + 1, last["desc"], last["psi"])
+        if stop_after is not None and i + 1 - first >= stop_after:
+            break
     return log

@@ -127,3 +127,28 @@ def test_reflection_skips_fermions(fake):
     DR = fake
     assert not DR.mirror_symmetric(DR.hubbard(1.0), 8)
     assert DR.mirror_symmetric(DR.heisenberg(DR.ladder()), 8)
+
+
+def test_checkpoint_and_resume(fake, tmp_path):
+    """A run stopped after nine steps (inside the finite sweep) with
+    checkpoints, then resumed from them: the saved records come back as they
+    were, the remaining steps give the uninterrupted run's energies, and the
+    resumed steps after the first start from carried vectors close to their
+    ground states (the blocks' cut records were saved with them)."""
+    DR = fake
+    L = 12
+    model = DR.heisenberg(DR.chain(1.0))
+    full = DR.run(model, L, 12, 1, _init, ctx=FakeContext(), tol=1e-12)
+    pre = str(tmp_path / "ck")
+    part = DR.run(model, L, 12, 1, _init, ctx=FakeContext(), tol=1e-12, checkpoint=pre, stop_after=9)
+    assert len(part) == 9
+    STARTS.clear()
+    rest = DR.run(model, L, 12, 1, _init, ctx=FakeContext(), tol=1e-12, resume=pre)
+    assert len(rest) == len(full)
+    for a, b in zip(rest[:9], part):
+        assert a == b
+    for a, b in zip(rest, full):
+        assert (a["phase"], a["n"], a["p"]) == (b["phase"], b["n"], b["p"])
+        assert abs(a["energy"] - b["energy"]) < 1e-10 * L
+    assert len(STARTS) == len(full) - 9
+    assert min(STARTS[1:]) > 0.99

@@ -202,3 +202,35 @@ def test_carried_vector_matches_oracle_transformation(ctx, name, L, m):
         if untruncated:
             ov = abs(float(np.dot(got, c["psi_new"]))) / np.linalg.norm(got)
             assert ov >= 1 - 1e-10, (c["p"], ov)
+
+
+def test_checkpoint_resume(ctx, tmp_path):
+    """A run stopped after twelve steps (inside the first finite sweep) with
+    checkpoints, then resumed from them, gives the uninterrupted run's steps
+    and energies (to the solver's tolerance: the resumed run's steps start
+    from carried vectors again); the superblock fixture written at the stop
+    rebuilds that step's superblock, of which the saved vector is the ground
+    state."""
+    import torch
+    from paper_0902_3185_amd import checkpoint as CK
+    from paper_0902_3185_amd import driver as DR
+    from paper_0902_3185_amd.superblock import Superblock
+    L = 16
+    model = DR.heisenberg(DR.chain(1.0))
+    full = DR.run(model, L, 32, 2, _init, ctx=ctx, prec="fp64", tol=1e-10)
+    pre = str(tmp_path / "run")
+    part = DR.run(model, L, 32, 2, _init, ctx=ctx, prec="fp64", tol=1e-10, checkpoint=pre, stop_after=12)
+    assert len(part) == 12
+    for a, b in zip(part, full):
+        assert a["energy"] == b["energy"]
+    desc, psi = CK.load_superblock(pre + ".superblock.npz")
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    r = sb.lanczos(torch.tensor(psi, dtype=torch.float64, device="cuda"), max_iter=50, tol=1e-9)
+    assert r["iters"] == 1 and abs(r["energy"] - part[-1]["energy"]) <= 1e-12 * L
+    rest = DR.run(model, L, 32, 2, _init, ctx=ctx, prec="fp64", tol=1e-10, checkpoint=pre, resume=pre)
+    assert len(rest) == len(full)
+    for a, b in zip(rest, full):
+        assert (a["phase"], a["n"], a["p"]) == (b["phase"], b["n"], b["p"])
+        assert abs(a["energy"] - b["energy"]) <= 1e-9 * L, (a, b)
+    with pytest.raises(ValueError):
+        DR.run(model, L, 16, 2, _init, ctx=ctx, prec="fp64", resume=pre)
