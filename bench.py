@@ -125,10 +125,10 @@ def sustained_fp32_gemm(n=8192, reps=5):
     return 2.0 * n ** 3 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12
 
 
-def kernel_only(sb, ctx, psi, flops, n):
+def kernel_only(sb, ctx, psi, flops, n, prec="fp32"):
     import torch
     y = torch.empty_like(psi)
-    us = time_products(sb, ctx, psi, y, "fp32", n)
+    us = time_products(sb, ctx, psi, y, prec, n)
     # calibration copies: 512 MiB, larger than the last-level cache, so every
     # byte read comes from HBM
     big = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
@@ -137,21 +137,24 @@ def kernel_only(sb, ctx, psi, flops, n):
     for _ in range(3):
         dst.copy_(big)
     torch.cuda.synchronize()
-    print(json.dumps({"kernel_only": n, "fp32_product_us": round(us, 3),
+    print(json.dumps({"kernel_only": n, "prec": prec, "product_us": round(us, 3),
                       "tflops": round(flops / us / 1e6, 3),
                       "copy_bytes_read": 8 * big.numel(), "copy_bytes_written": 8 * big.numel()}),
           flush=True)
 
 
-def traffic_per_launch():
-    """HBM bytes per launch of the FP32 product kernel from the committed
-    counter summary, or None if the kernel source changed since it was taken."""
+def traffic_per_launch(workload, variant):
+    """HBM bytes per launch of the FP32 product from the committed counter
+    summary of this workload and kernel variant, or None if there is none or
+    the kernel sources changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hpsi_tiles_hubbard_L64_U4_m512.traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
+    if rec.get("workload_name") != workload or rec.get("variant") != variant:
+        return None
     h = hashlib.sha256()
     for src in rec.get("sources", []):
         with open(os.path.join(ROOT, src), "rb") as f:
@@ -227,8 +230,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="N",
-                    help="for profilers: N FP32 products, then N plain copies of a vector of "
-                         "the same length (the copy calibrates HBM byte counters), and exit")
+                    help="for profilers: N products, then plain copies of a 512 MiB buffer "
+                         "(the copy calibrates HBM byte counters), and exit")
+    ap.add_argument("--kernel-prec", default="fp32", choices=["fp32", "bf16x3"],
+                    help="precision of the --kernel-only products")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -247,7 +252,12 @@ def main():
     ctx = Context(0)
     t0 = time.perf_counter()
     sb = Superblock(desc, prec="fp32", ctx=ctx)
-    variant = sb.autotune(reps=20)   # tile-kernel variant for this superblock (same results)
+    sb.set_prec("bf16x3")
+    variant_bf16 = sb.autotune(reps=20)   # product variants for this superblock
+    sb.set_prec("fp32")
+    variant = sb.autotune(reps=20)
+    if args.kernel_only:
+        sb.set_prec(args.kernel_prec)
     torch.cuda.synchronize()
     build_ms = 1e3 * (time.perf_counter() - t0)
     st = sb.stats()
@@ -256,12 +266,12 @@ def main():
     log(f"[bench] {args.workload}: D={sb.D} pairs={len(sb.s_sec)} terms={sb.nterms} "
         f"tiles={st['ntiles']} F_alg={F:.3e} flop/product build={build_ms:.0f} ms")
     if args.kernel_only:
-        kernel_only(sb, ctx, psi0, F, args.kernel_only)
+        kernel_only(sb, ctx, psi0, F, args.kernel_only, args.kernel_prec)
         return
 
     parts = {"lanczos": 0.0, "rho_S": 0.0, "adjoint": 0.0}
 
-    def step():
+    def step(acc=parts):
         t = time.perf_counter()
         r = sb.lanczos(psi0, max_iter=4000, tol=1e-8)
         t1 = time.perf_counter()
@@ -269,8 +279,8 @@ def main():
         t2 = time.perf_counter()
         sb.adjoint(r["psi"], r["psi"], want_psi=False, want_c=True)
         t3 = time.perf_counter()
-        for k, v in zip(parts, (t1 - t, t2 - t1, t3 - t2)):
-            parts[k] += v
+        for k, v in zip(acc, (t1 - t, t2 - t1, t3 - t2)):
+            acc[k] += v
         return r
 
     for i in range(args.warmup):
@@ -300,6 +310,30 @@ def main():
     hpsi_us32 = 1e3 * ms32 / max(n32, 1)
     achieved = F / (hpsi_us32 * 1e-6) / 1e12
 
+    # the same steps with the Lanczos steps between host checks replayed
+    # from captured HIP graphs (outside the timed region: the replayed
+    # products carry no timing events); one untimed step captures them
+    graphs = None
+    try:
+        sb.set_graphs(True)
+        rg = step({k: 0.0 for k in parts})
+        gparts = {k: 0.0 for k in parts}
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for i in range(args.steps):
+            rg = step(gparts)
+        torch.cuda.synchronize()
+        g_elapsed = time.perf_counter() - tg
+        caps, reps = sb.graph_stats()
+        sb.set_graphs(False)
+        graphs = {"ms_per_step": round(1e3 * g_elapsed / args.steps, 3),
+                  "step_breakdown_ms": {k: round(1e3 * v / args.steps, 3) for k, v in gparts.items()},
+                  "captures": caps, "graph_launches": reps,
+                  "same_energy_bits": rg["energy"] == E32}
+        log(f"[bench] with Lanczos graphs: {graphs}")
+    except Exception as e:   # report, do not fail the run
+        log(f"[bench] Lanczos graphs unavailable: {e}")
+
     # side measurements (outside the timed region): precision variants and accuracy
     y = torch.empty_like(psi0)
     us = {p: time_products(sb, ctx, psi0, y, p, 200 if p != "fp64_plain" else 20)
@@ -327,11 +361,13 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": describe(args.workload),
                    "D": sb.D, "sector_pairs": int(len(sb.s_sec)), "terms": sb.nterms,
-                   "tiles": st["ntiles"], "flops_alg_per_product": F, "kernel_variant": variant},
+                   "tiles": st["ntiles"], "flops_alg_per_product": F, "kernel_variant": variant,
+                   "kernel_variant_bf16x3": variant_bf16},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK["fp32"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32"], 5),
-                     "traffic": traffic_per_launch(),
+                     "traffic": traffic_per_launch(args.workload, variant),
                      "timed_launches": n32, "timing_stride": TIMING_STRIDE},
+        "lanczos_graphs": graphs,
         "product_us": {k: round(v, 3) for k, v in us.items()},
         "product_us_graph_median": {k: round(v, 3) for k, v in us_graph.items()},
         "product_tflops_graph": {k: round(F / (v * 1e-6) / 1e12, 3) for k, v in us_graph.items()},

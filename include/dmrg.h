@@ -142,6 +142,22 @@ void dmrg_ctx_destroy(dmrg_ctx ctx);
 /* Set the stream later work is queued on (e.g. the caller's current stream). */
 dmrg_status dmrg_ctx_set_stream(dmrg_ctx ctx, void* hip_stream);
 
+/* Device-memory cap (failure injection and budgeting; not a paper
+ * passage).  dmrg_ctx_set_mem_cap(ctx, bytes): the device memory the
+ * library holds on the context's device -- every context and superblock on
+ * that device together: staged operators, tile images, Lanczos and
+ * density-matrix workspaces -- may not exceed `bytes` (0: no cap, the
+ * default).  An allocation that would pass it fails, and the call that
+ * needed it returns DMRG_E_NOMEM (as it does when the device itself is out
+ * of memory) with nothing half-built: the superblock or context stays
+ * usable and the call can be repeated after the cap is raised.  A cap below
+ * what is already held frees nothing; it refuses further growth.
+ * DMRG_E_ARG for bytes < 0.  dmrg_ctx_mem: bytes held and the cap (either
+ * pointer may be NULL).  Memory the caller allocates (vectors passed in) and
+ * the fixed scratch array of dmrg_hpsi_noalloc are not counted.            */
+dmrg_status dmrg_ctx_set_mem_cap(dmrg_ctx ctx, int64_t bytes);
+dmrg_status dmrg_ctx_mem(dmrg_ctx ctx, int64_t* used, int64_t* cap);
+
 /* Timing of the product kernels.  dmrg_ctx_set_timing(ctx, every): with
  * every >= 1, every every-th product launch the library makes on this
  * context (dmrg_hpsi and the products inside dmrg_lanczos_ground, counted
@@ -245,6 +261,27 @@ dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant);
  * working precision, about twice the passes over the basis).  DMRG_E_ARG
  * for another mode.                                                          */
 dmrg_status dmrg_sb_set_reorth(dmrg_sb sb, int32_t mode);
+
+/* Launch batching of dmrg_lanczos_ground (Sec. 3.3's recursion, one product
+ * and its orthogonalisation per step).  enable 1: the steps between two of
+ * the host's convergence checks (every fourth step) are captured into a HIP
+ * graph the first time their position in a restart cycle is reached, on a
+ * non-blocking stream the context owns, and replayed on the context's
+ * stream at that position in every later cycle and solve on this
+ * superblock; a restart cycle's first step and the steps near the end of a
+ * cycle or of the product cap run as ordinary launches.  Results are the
+ * same bits as with enable 0 (the same kernels with the same arguments in
+ * the same order).  Products inside the graphs take no timing events
+ * (dmrg_ctx_set_timing still counts them).  The graphs hold the context's
+ * Lanczos buffers and the superblock's staged operators at the time of
+ * capture; a solve that finds any of them moved, or another precision,
+ * kernel variant or reorthogonalisation mode, captures afresh.  enable 0
+ * (the default) synchronises the context's stream and frees the graphs.
+ * DMRG_E_ARG for another value or a superblock without a device context.
+ * dmrg_sb_graph_stats: the number of captures and of graph launches so far
+ * (either pointer may be NULL).                                             */
+dmrg_status dmrg_sb_set_graphs(dmrg_sb sb, int32_t enable);
+dmrg_status dmrg_sb_graph_stats(dmrg_sb sb, int64_t* captures, int64_t* replays);
 
 /* y_d = alpha * H psi_d + beta * y_d (paper Sec. 3.3: the Lanczos solver's
  * only need, x += H y, with alpha = beta = 1).  psi_d and y_d are device FP64

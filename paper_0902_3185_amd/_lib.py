@@ -93,6 +93,10 @@ _SIGS = {
     "dmrg_sb_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32)]),
     "dmrg_sb_set_variant": (C.c_int, [_P, C.c_int32]),
     "dmrg_sb_set_reorth": (C.c_int, [_P, C.c_int32]),
+    "dmrg_sb_set_graphs": (C.c_int, [_P, C.c_int32]),
+    "dmrg_ctx_set_mem_cap": (C.c_int, [_P, C.c_int64]),
+    "dmrg_ctx_mem": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "dmrg_sb_graph_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "dmrg_host_tridiag_lowest": (C.c_int, [C.c_int32, _D, _D, _D, _D]),
 }
 

@@ -119,27 +119,61 @@ dmrg_status fail(dmrg_status st, const std::string& msg) {
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
     if (e_ != hipSuccess)                                                              \
-      return fail(DMRG_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+      return fail(e_ == hipErrorOutOfMemory ? DMRG_E_NOMEM : DMRG_E_DEVICE,            \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
   } while (0)
 
-// Device allocation owned by the library.
+// Device memory the library holds per device, and the cap set with
+// dmrg_ctx_set_mem_cap (0: none).
+constexpr int kMaxDevices = 64;
+struct MemAccount {
+  std::atomic<int64_t> used{0}, cap{0};
+};
+MemAccount g_mem[kMaxDevices];
+
+// Device allocation owned by the library, counted against its device's cap.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  int dev = -1;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      if (dev >= 0 && dev < kMaxDevices) g_mem[dev].used.fetch_sub((int64_t)bytes);
+    }
     p = nullptr;
     bytes = 0;
+    dev = -1;
   }
   hipError_t ensure(size_t n) {
     if (n <= bytes && p) return hipSuccess;
     release();
-    hipError_t e = hipMalloc(&p, std::max<size_t>(n, 256));
-    if (e == hipSuccess) bytes = std::max<size_t>(n, 256);
+    const size_t want = std::max<size_t>(n, 256);
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return e;
+    MemAccount* acct = d >= 0 && d < kMaxDevices ? &g_mem[d] : nullptr;
+    if (acct) {
+      // reserve first, so that concurrent callers cannot pass the cap together
+      const int64_t cap = acct->cap.load();
+      const int64_t now = acct->used.fetch_add((int64_t)want) + (int64_t)want;
+      if (cap > 0 && now > cap) {
+        acct->used.fetch_sub((int64_t)want);
+        return hipErrorOutOfMemory;
+      }
+    }
+    e = hipMalloc(&p, want);
+    if (e == hipSuccess) {
+      bytes = want;
+      dev = acct ? d : -1;
+    } else {
+      p = nullptr;
+      if (acct) acct->used.fetch_sub((int64_t)want);
+    }
     return e;
   }
   template <class T>
@@ -219,6 +253,7 @@ struct dmrg_ctx_s {
   size_t host_small_n = 0;
   double* host_rho = nullptr;     // pinned, density-matrix blocks on their way to the host
   size_t host_rho_n = 0;
+  hipStream_t cap_stream = nullptr;   // non-blocking, default priority: where Lanczos graphs are captured
 };
 
 struct dmrg_sb_s {
@@ -237,6 +272,28 @@ struct dmrg_sb_s {
   std::unique_ptr<Staged> adj;
   int variant[3] = {0, 0, 0};   // fused-kernel variant per kernel precision (autotuner)
   int reorth = 0;               // Lanczos reorthogonalisation (dmrg_sb_set_reorth)
+  // dmrg_sb_set_graphs: the Lanczos steps between two host checks, captured
+  // once per position in a restart cycle and replayed.  The graphs bake in
+  // the buffers and launch choices of `key`; a call with another key drops
+  // them all.
+  struct LzGraphs {
+    bool on = false;
+    struct Key {
+      const void* ptr[8];
+      int64_t D;
+      int32_t nvec, prec, variant, twice;
+      bool operator==(const Key& o) const { return std::memcmp(this, &o, sizeof(Key)) == 0; }
+    } key;
+    std::vector<hipGraphExec_t> seg;   // by position: steps 1..kCheck-1, then kCheck runs of kCheck
+    int64_t replays = 0, captures = 0;
+    LzGraphs() { std::memset(&key, 0, sizeof(key)); }
+    void drop() {
+      for (hipGraphExec_t& g : seg)
+        if (g) (void)hipGraphExecDestroy(g);
+      seg.clear();
+    }
+    ~LzGraphs() { drop(); }
+  } lzg;
   // density-matrix blocks: tile images per side (built on first use), output
   struct RhoPlan {
     bool built = false;
@@ -558,6 +615,7 @@ void dmrg_ctx_destroy(dmrg_ctx ctx) {
     if (e) (void)hipEventDestroy(e);
   if (ctx->host_small) (void)hipHostFree(ctx->host_small);
   if (ctx->host_rho) (void)hipHostFree(ctx->host_rho);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
 }
 
@@ -600,6 +658,22 @@ dmrg_status dmrg_ctx_timing(dmrg_ctx ctx, int32_t prec, double* ms_total, int64_
 dmrg_status dmrg_ctx_set_stream(dmrg_ctx ctx, void* hip_stream) {
   if (!ctx) return fail(DMRG_E_ARG, "null context");
   ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_ctx_set_mem_cap(dmrg_ctx ctx, int64_t bytes) {
+  if (!ctx) return fail(DMRG_E_ARG, "null context");
+  if (bytes < 0) return fail(DMRG_E_ARG, "memory cap must be >= 0");
+  if (ctx->device < 0 || ctx->device >= kMaxDevices) return fail(DMRG_E_DEVICE, "device index out of range");
+  g_mem[ctx->device].cap.store(bytes);
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_ctx_mem(dmrg_ctx ctx, int64_t* used, int64_t* cap) {
+  if (!ctx) return fail(DMRG_E_ARG, "null context");
+  if (ctx->device < 0 || ctx->device >= kMaxDevices) return fail(DMRG_E_DEVICE, "device index out of range");
+  if (used) *used = g_mem[ctx->device].used.load();
+  if (cap) *cap = g_mem[ctx->device].cap.load();
   return DMRG_OK;
 }
 
@@ -800,6 +874,26 @@ dmrg_status dmrg_sb_set_reorth(dmrg_sb sb, int32_t mode) {
   if (!sb) return fail(DMRG_E_ARG, "null superblock");
   if (mode != 0 && mode != 1) return fail(DMRG_E_ARG, "reorthogonalisation mode must be 0 or 1");
   sb->reorth = mode;
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_sb_set_graphs(dmrg_sb sb, int32_t enable) {
+  dmrg_status st = need_device(sb);
+  if (st != DMRG_OK) return st;
+  if (enable != 0 && enable != 1) return fail(DMRG_E_ARG, "enable must be 0 or 1");
+  sb->lzg.on = enable == 1;
+  if (!sb->lzg.on) {
+    DeviceGuard g(sb->ctx->device);
+    HIP_TRY(hipStreamSynchronize(sb->ctx->stream));   // no replay of them is still queued
+    sb->lzg.drop();
+  }
+  return DMRG_OK;
+}
+
+dmrg_status dmrg_sb_graph_stats(dmrg_sb sb, int64_t* captures, int64_t* replays) {
+  if (!sb) return fail(DMRG_E_ARG, "null superblock");
+  if (captures) *captures = sb->lzg.captures;
+  if (replays) *replays = sb->lzg.replays;
   return DMRG_OK;
 }
 
@@ -1040,17 +1134,20 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       const bool breakdown = bl <= 1e-13 * std::max(1.0, std::fabs(theta)) || steps < jc + 1;
       return jc > 0 && (est <= ctol || breakdown);
     };
-    int pend = -1, pbuf = 0, nbuf = 0;   // check in flight: its step and buffer
-    for (int j = 0;; ++j) {
+    // The launches of step j (product, then the orthogonalisation of its
+    // kind); at a check point also the norm record the check reads.  Under
+    // capture the product takes no timing events.
+    auto issue_step = [&](int j, bool check, bool capture, hipStream_t s) -> dmrg_status {
       double* vj = V + (size_t)j * D;
       const dmrg_prec p = (j == 0 && reduced) ? DMRG_FP64 : sb->prec;
       const bool two = j == 0 || twice;
       const bool recurrence = !two && !(j & 1);
       // a reduced-precision product reads the FP32 copy of its input that the
       // previous step wrote beside it (no conversion pass)
-      if ((st = run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0, p == sb->prec ? v32 : nullptr)) != DMRG_OK)
-        return st;
-      ++total;
+      const float* in32 = p == sb->prec ? v32 : nullptr;
+      dmrg_status r = capture ? run_product_inner(sb, sb->fwd, p, vj, w, 1.0, 0.0, nullptr, nullptr, in32)
+                              : run_product(sb, sb->fwd, p, vj, w, 1.0, 0.0, in32);
+      if (r != DMRG_OK) return r;
       double* vnext = j + 1 < nvec ? V + (size_t)(j + 1) * D : nullptr;
       if (two) {
         HIP_TRY(launch_lz_step(w, V, D, j + 1, D, h1, h2, part, ab + 2 * j, vnext, s, v32));
@@ -1066,10 +1163,78 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
         HIP_TRY(launch_lz_step_recurrence(w, V, D, j + 1, D, part, npb[(j - 1) & 1], npb[j & 1],
                                           ab + 2 * j, vnext, s, v32));
       }
+      // a single-pass step's beta_j is otherwise formed by the next step
+      if (check && !two) HIP_TRY(launch_lz_record_norm(npb[j & 1], D, ab + 2 * j + 1, s));
+      return DMRG_OK;
+    };
+    // Steps j0 .. j1 (no check point before j1, none of them the last step
+    // allowed) from the graph of their position, captured on first use.
+    auto replay = [&](int j0, int j1) -> dmrg_status {
+      dmrg_sb_s::LzGraphs& G = sb->lzg;
+      dmrg_sb_s::LzGraphs::Key k;
+      std::memset(&k, 0, sizeof(k));
+      const Staged& f = sb->fwd;
+      const void* ptrs[8] = {V, w, part, h1, v32, f.images.p, f.dense32.p, f.mtiles.p};
+      std::copy(ptrs, ptrs + 8, k.ptr);
+      k.D = D;
+      k.nvec = nvec;
+      k.prec = (int32_t)sb->prec;
+      k.variant = sb->variant[kernel_prec(sb->prec)];
+      k.twice = twice;
+      if (!(k == G.key)) {
+        G.drop();
+        G.key = k;
+      }
+      const size_t pos = (size_t)(j0 / kCheck);
+      if (G.seg.size() <= pos) G.seg.resize(pos + 1, nullptr);
+      if (!G.seg[pos]) {
+        // captured on the context's own side stream (the caller's stream may
+        // be the default one, which cannot be captured); nothing runs
+        // during the capture, and the graph is launched on the caller's
+        // stream
+        if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipStream_t cs = ctx->cap_stream;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        ctx->stream = cs;   // the products queue on the context's stream
+        dmrg_status r = DMRG_OK;
+        for (int j = j0; j <= j1 && r == DMRG_OK; ++j) r = issue_step(j, j == j1, true, cs);
+        ctx->stream = s;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (r != DMRG_OK || e != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          if (r != DMRG_OK) return r;
+          HIP_TRY(e);
+        }
+        const hipError_t ei = hipGraphInstantiate(&G.seg[pos], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) G.seg[pos] = nullptr;
+        HIP_TRY(ei);
+        ++G.captures;
+      }
+      HIP_TRY(hipGraphLaunch(G.seg[pos], s));
+      ++G.replays;
+      if (ctx->timing > 0) ctx->products[(int)sb->prec] += j1 - j0 + 1;
+      return DMRG_OK;
+    };
+    int pend = -1, pbuf = 0, nbuf = 0;   // check in flight: its step and buffer
+    for (int j = 0;; ++j) {
+      int j1 = j;   // last step of a captured run starting at j (== j: none)
+      if (sb->lzg.on && j >= 1) {   // a run up to the next check point
+        while ((j1 + 1) % kCheck != 0) ++j1;
+        if (!(j1 + 2 < nvec && total + (j1 - j + 1) < max_iter) || j1 == j) j1 = j;
+      }
+      if (j1 > j) {
+        if ((st = replay(j, j1)) != DMRG_OK) return st;
+        total += j1 - j + 1;
+        j = j1;
+      } else {
+        const bool check = j == 0 || (j + 1) % kCheck == 0 || j + 2 >= nvec || total + 1 >= max_iter;
+        if ((st = issue_step(j, check, false, s)) != DMRG_OK) return st;
+        ++total;
+      }
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
-      // a single-pass step's beta_j is otherwise formed by the next step
-      if (!two) HIP_TRY(launch_lz_record_norm(npb[j & 1], D, ab + 2 * j + 1, s));
       HIP_TRY(hipMemcpyAsync(hbuf[nbuf], ab, 2 * (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipEventRecord(ctx->chk[nbuf], s));
       if (pend >= 0) {   // the previous check: its copy is behind older steps only

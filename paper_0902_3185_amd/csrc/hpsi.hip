@@ -960,8 +960,29 @@ __global__ __launch_bounds__(256) void plain_segment(SegDesc sg, TileDesc t,
 // psi in FP32 for the products that read an FP32 copy (one pass), and
 // kPoolPad zeros after it: the products' masked vector loads may reach
 // them, and a zero scale must not meet a NaN left in the buffer.
+// A thread converts four consecutive elements with two 16-byte loads and one
+// 16-byte store (x 16-byte aligned); the last partial group and the padding
+// element by element.
 __global__ __launch_bounds__(256) void psi_to_f32(const double* __restrict__ x, float* __restrict__ out,
                                                   int64_t n) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int64_t i = 4 * ((int64_t)blockIdx.x * 256 + threadIdx.x);
+  if (i + 4 <= n) {
+    const d2 a = *reinterpret_cast<const d2*>(x + i);
+    const d2 b = *reinterpret_cast<const d2*>(x + i + 2);
+    *reinterpret_cast<f4*>(out + i) = f4{(float)a[0], (float)a[1], (float)b[0], (float)b[1]};
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t j = i + e;
+    if (j < n) out[j] = (float)x[j];
+    else if (j < n + kPoolPad) out[j] = 0.f;
+  }
+}
+// the same, one element per thread, for an x that is not 16-byte aligned
+__global__ __launch_bounds__(256) void psi_to_f32_unaligned(const double* __restrict__ x,
+                                                            float* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) out[i] = (float)x[i];
   else if (i < n + kPoolPad) out[i] = 0.f;
@@ -1014,7 +1035,11 @@ hipError_t launch_patch_coeffs(void* base, const CoefRef* refs, int64_t n, const
 hipError_t launch_psi_to_f32(const double* psi, float* out, int64_t n, hipStream_t stream) {
   if (n < 0) return hipErrorInvalidValue;
   const int64_t m = n + kPoolPad;
-  hipLaunchKernelGGL(psi_to_f32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, psi, out, n);
+  if ((reinterpret_cast<uintptr_t>(psi) & 15) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0)
+    hipLaunchKernelGGL(psi_to_f32, dim3((unsigned)((m + 1023) / 1024)), dim3(256), 0, stream, psi, out, n);
+  else
+    hipLaunchKernelGGL(psi_to_f32_unaligned, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, psi,
+                       out, n);
   return hipGetLastError();
 }
 

@@ -397,29 +397,31 @@ __global__ __launch_bounds__(kMacThreads, kMacWGsPerCU) void hpsi_macro(
 }
 
 // The shared tiles' partial sums in share order (FP64), their elementwise
-// terms, and y: one workgroup of 1024 threads per shared tile, thread T the
-// four stored entries 4T .. 4T + 3 (entry e = (w * 16 + r) * 64 + lane of
-// the storing wave w, register r, lane).  The loads of four shares, and of
-// four elementwise terms, go out together before their sums.
-constexpr int kCombineThreads = 1024;
+// terms, and y: four workgroups of 256 threads per shared tile, workgroup q
+// the 32 x 32 quarter that wave q of the main kernel stored, thread T of it
+// the four stored entries e = 1024 q + 4T .. + 3 (entry e = (w * 16 + r) * 64
+// + lane of the storing wave w, register r, lane).  The loads of eight
+// shares, and of four elementwise terms, go out together before their sums.
+constexpr int kCombineThreads = 256;
+constexpr int kCombineBatch = 8;
 
 __global__ __launch_bounds__(kCombineThreads) void hpsi_macro_combine(
     const MacTile* __restrict__ tiles, const int32_t* __restrict__ shared, const MacGG* __restrict__ mggs,
     const float* __restrict__ part, const double* __restrict__ psi64, double* __restrict__ y, double alpha,
     double beta) {
-  const MacTile T = tiles[shared[blockIdx.x]];
+  const MacTile T = tiles[shared[blockIdx.x >> 2]];
   const int nsplit = rfl(T.nsplit), ngg = rfl(T.ngg);
-  const int e0 = threadIdx.x * 4;
+  const int e0 = (blockIdx.x & 3) * (kMac * kMac / 4) + threadIdx.x * 4;
   const float* p0 = part + (int64_t)T.part0 * (kMac * kMac) + e0;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int s = 0; s < nsplit; s += 4) {
-    f4 x[4];
+  for (int s = 0; s < nsplit; s += kCombineBatch) {
+    f4 x[kCombineBatch];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kCombineBatch; ++u)
       x[u] = s + u < nsplit ? *reinterpret_cast<const f4*>(p0 + (int64_t)(s + u) * (kMac * kMac))
                             : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kCombineBatch; ++u)
       if (s + u < nsplit) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] += (double)x[u][k];
@@ -479,7 +481,7 @@ hipError_t launch_hpsi_macro(bool bf16, int nwg, int nshared, const MacTile* til
     hipExtLaunchKernelGGL(hpsi_macro<false>, dim3(nwg), dim3(kMacThreads), 0, stream, t0, end_main, 0, tiles,
                           segs, ggs, items, wg_start, dense, ndense, psi32, npsi, psi64, y, alpha, beta, part);
   if (nshared > 0)
-    hipExtLaunchKernelGGL(hpsi_macro_combine, dim3(nshared), dim3(kCombineThreads), 0, stream, nullptr, t1,
+    hipExtLaunchKernelGGL(hpsi_macro_combine, dim3(4 * nshared), dim3(kCombineThreads), 0, stream, nullptr, t1,
                           0, tiles, shared, ggs, part, psi64, y, alpha, beta);
   return hipGetLastError();
 }

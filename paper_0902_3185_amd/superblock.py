@@ -42,6 +42,18 @@ class Context:
         self._stream = stream
         check(lib().dmrg_ctx_set_stream(self.handle, C.c_void_p(stream.cuda_stream)))
 
+    def set_mem_cap(self, nbytes):
+        """dmrg_ctx_set_mem_cap: cap the device memory the library holds on
+        this context's device (0: no cap)."""
+        check(lib().dmrg_ctx_set_mem_cap(self.handle, int(nbytes)))
+
+    def mem(self):
+        """dmrg_ctx_mem: (bytes the library holds on the device, cap)."""
+        u = C.c_int64()
+        c = C.c_int64()
+        check(lib().dmrg_ctx_mem(self.handle, C.byref(u), C.byref(c)))
+        return u.value, c.value
+
     def set_timing(self, every=1):
         """Time every `every`-th product launch with HIP events (0 or False:
         off); all product launches are counted while it is on."""
@@ -195,6 +207,18 @@ class Superblock:
         step after the local recurrence (default), 1 = classical
         Gram-Schmidt twice at every step."""
         check(lib().dmrg_sb_set_reorth(self.handle, int(mode)))
+
+    def set_graphs(self, enable):
+        """dmrg_sb_set_graphs: replay the Lanczos steps between two host
+        checks from captured HIP graphs (True) or launch them one by one."""
+        check(lib().dmrg_sb_set_graphs(self.handle, int(bool(enable))))
+
+    def graph_stats(self):
+        """dmrg_sb_graph_stats: (captures, graph launches) so far."""
+        c = C.c_int64()
+        r = C.c_int64()
+        check(lib().dmrg_sb_graph_stats(self.handle, C.byref(c), C.byref(r)))
+        return c.value, r.value
 
     def set_prec(self, prec):
         check(lib().dmrg_sb_set_prec(self.handle, PREC[prec]))

@@ -127,6 +127,93 @@ def test_lanczos_reorth_modes(ctx, prec):
         sb.set_reorth(2)
 
 
+@pytest.mark.parametrize("name,prec,variant", [("hubbard_L64_U4_m512", "fp32", 0),
+                                               ("hubbard_L64_U4_m512", "fp64", 0),
+                                               ("ladder_2x32_m1024", "bf16x3", 1),
+                                               ("heisenberg_L16_m32", "fp32", 0)])
+def test_lanczos_graphs_replay_bitwise(ctx, name, prec, variant):
+    """dmrg_sb_set_graphs: the steps between two host checks replayed from
+    captured HIP graphs give the same bits as the launches one by one --
+    on the solve that captures them (its later restart cycles replay), on a
+    solve that only replays, and after the coefficients change (the graphs
+    read the coefficients that dmrg_sb_set_coeffs patches in place).  The
+    cases cover both product variants, the single-pass steps (large D) and
+    the two-pass steps (D = 822)."""
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock(name, seed=0)
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    if prec != "fp64":
+        sb.set_variant(variant)
+    psi0 = _dev(seeded_vector(sb.D, 3))
+
+    def solve():
+        r = sb.lanczos(psi0, max_iter=2000, tol=1e-8)
+        assert r["converged"]
+        return r["energy"], _host(r["psi"]), r["iters"], r["resid"]
+
+    def same(a, b):
+        assert a[0] == b[0] and a[2] == b[2] and a[3] == b[3], (a[0], b[0], a[2], b[2])
+        assert np.array_equal(a[1], b[1])
+
+    eager = solve()
+    sb.set_graphs(True)
+    first = solve()
+    caps1, reps1 = sb.graph_stats()
+    second = solve()
+    caps2, reps2 = sb.graph_stats()
+    assert caps1 > 0 and caps2 == caps1 and reps2 > reps1 >= caps1, (caps1, reps1, caps2, reps2)
+    same(first, eager)
+    same(second, eager)
+    c = np.array([t["c"] for t in desc["terms"]], dtype=np.float64)
+    c[0] *= 1.25
+    sb.set_coeffs(c)
+    replayed = solve()
+    caps3, reps3 = sb.graph_stats()
+    # the positions captured before are replayed, not captured again (a
+    # longer solve may add positions past the old end)
+    assert reps3 - reps2 > caps3 - caps2, (caps2, reps2, caps3, reps3)
+    sb.set_graphs(False)
+    same(replayed, solve())
+    assert replayed[0] != eager[0]
+
+
+def test_memory_cap_gives_nomem(ctx):
+    """dmrg_ctx_set_mem_cap: a call whose allocation would pass the cap
+    returns DMRG_E_NOMEM, frees what it took, and succeeds once the cap is
+    raised -- for a superblock build and for the Lanczos workspace of a
+    fresh context."""
+    from paper_0902_3185_amd import _lib
+    from paper_0902_3185_amd.superblock import Context, Superblock
+    desc = workload_superblock("hubbard_L64_U4_m512", seed=0)
+    fresh = Context(0)
+    used0, cap0 = fresh.mem()
+    assert cap0 == 0 and used0 >= 0
+    try:
+        fresh.set_mem_cap(used0 + (1 << 20))
+        with pytest.raises(_lib.DmrgError) as ei:
+            Superblock(desc, prec="fp32", ctx=fresh)
+        assert ei.value.name == "DMRG_E_NOMEM"
+        assert fresh.mem()[0] == used0
+        fresh.set_mem_cap(0)
+        sb = Superblock(desc, prec="fp32", ctx=fresh)
+        used1 = fresh.mem()[0]
+        assert used1 > used0 + (1 << 20)
+        # about a hundred basis vectors of D doubles do not fit in 1 MiB more
+        fresh.set_mem_cap(used1 + (1 << 20))
+        psi0 = _dev(seeded_vector(sb.D, 3))
+        with pytest.raises(_lib.DmrgError) as ei:
+            sb.lanczos(psi0, max_iter=2000, tol=1e-8)
+        assert ei.value.name == "DMRG_E_NOMEM"
+        fresh.set_mem_cap(0)
+        r = sb.lanczos(psi0, max_iter=2000, tol=1e-8)
+        assert r["converged"]
+        assert fresh.mem()[0] > used1
+        with pytest.raises(_lib.DmrgError):
+            fresh.set_mem_cap(-1)
+    finally:
+        fresh.set_mem_cap(0)
+
+
 def test_lanczos_cap_reports_noconv(ctx):
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock("heisenberg_L16_m32", seed=0)
