@@ -521,29 +521,46 @@ def wf_right_to_left(ctx, old_sb, psi_old, PS_old, PE_old, W_E, right_new, left_
 def mirror_symmetric(model, n):
     b = {(i, j, v, g) for (i, j, v, g) in model.bonds(n)}
     m = {(n - 1 - j, n - 1 - i, v, g) for (i, j, v, g) in b}
-    return not model.fermionic and b == m
+    return b == m
 
 
-def mirrored(block):
+def mirrored(block, model=None, Q=None):
     """The right block equal to a left block read from the other end.
 
-    Its origin is re-expressed in the site (x) block product order of a grown
-    right block, so the wave-function transformation can expand it."""
+    Its basis is the left block's read in reverse site order; for fermions
+    each occupation configuration also takes the sign of reordering its
+    creation operators from left-to-right to right-to-left site order,
+    (-1)^(sum over site pairs i < j of n_i n_j).  With that basis every
+    operator the right block carries (in its own Jordan-Wigner order, sites
+    left to right) has the left block's matrix -- the block Hamiltonian and
+    the site operators of mirrored sites alike -- so the matrices are shared
+    for spins and fermions.  The origin is re-expressed in the site (x) block
+    product order of a grown right block, so the wave-function
+    transformation can expand it; for fermions the row of block state a and
+    site state x takes the sign (-1)^(N_a n_x) that the reordering sign of a
+    grown block adds to that of its block part."""
     origin = None
     if block.origin is not None and block.origin[0] is not None:
         Pl, kept = block.origin          # Pl = Product(left block, site)
         Pr = Product(Pl.right, Pl.left, left_major=True)   # site (x) block
+        fermionic = model is not None and model.fermionic
+        if fermionic:
+            par_a = sector_parity(Pl.left, Q, True)          # (-1)^N_a per block sector
+            n_x = Pl.right.q % Q + Pl.right.q // Q          # particles per site state
         new_kept = []
         for (sec, W) in kept:
             q = int(Pl.basis.q[sec])
             sec_r = Pr.index[q]
             rows = np.empty(W.shape[0], dtype=np.int64)
+            sign = np.ones(W.shape[0])
             where = {(a, b): o for (a, b, o) in Pl.runs[sec]}
             for (x, a, o_r) in Pr.runs[sec_r]:
                 o_l = where[(a, x)]
                 n_run = int(Pl.left.dim[a] * Pl.right.dim[x])
                 rows[o_r:o_r + n_run] = np.arange(o_l, o_l + n_run)
-            new_kept.append((sec_r, W[rows, :]))
+                if fermionic and n_x[x] % 2 == 1:
+                    sign[o_r:o_r + n_run] = par_a[a]
+            new_kept.append((sec_r, sign[:, None] * W[rows, :]))
         origin = (Pr, new_kept)
     return Block(list(block.labels), block.basis, block.H, dict(block.ops), origin=origin)
 
@@ -710,7 +727,7 @@ def run(model, L, m, sweeps, init, ctx=None, prec="fp64", tol=1e-10, max_iter=20
             Ep = grow_left(right[h - 1], model, Q, n, nb, keep_range)
             if reflect and mirror_symmetric(model, n):
                 out = solve(Sp, Ep, n, (0,), "infinite", h, on=keep_last)
-                left[h], right[h] = out[0], mirrored(out[0])
+                left[h], right[h] = out[0], mirrored(out[0], model, Q)
             else:
                 out = solve(Sp, Ep, n, (0, 1), "infinite", h, on=keep_last)
                 left[h], right[h] = out[0], out[1]

@@ -123,10 +123,27 @@ def test_reflection_in_infinite_phase(fake, bonds):
     assert min(STARTS[n_inf:len(a)]) > 0.99   # run a's finite steps only
 
 
-def test_reflection_skips_fermions(fake):
+@pytest.mark.parametrize("U", [4.0, 0.0])
+def test_reflection_for_fermions(fake, U):
+    """Hubbard chain (spinful fermions): the mirrored system block, with the
+    sign of reversing each configuration's operator order in its basis,
+    serves as the environment with the system block's own matrices -- the
+    energies agree with the explicit environment's, and the carried start
+    vectors, which go through the mirrored blocks' cut records (sign
+    (-1)^(N_a n_x) per row), stay close to the ground states."""
     DR = fake
-    assert not DR.mirror_symmetric(DR.hubbard(1.0), 8)
+    assert DR.mirror_symmetric(DR.hubbard(U), 8)
     assert DR.mirror_symmetric(DR.heisenberg(DR.ladder()), 8)
+    L = 10
+    a = DR.run(DR.hubbard(U), L, 24, 1, _init, ctx=FakeContext(), tol=1e-12, reflect=True)
+    starts = list(STARTS)
+    b = DR.run(DR.hubbard(U), L, 24, 1, _init, ctx=FakeContext(), tol=1e-12, reflect=False)
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        assert abs(x["energy"] - y["energy"]) < 1e-12 * L, (x, y)
+    assert all("eps1" not in r for r in a if r["phase"] == "infinite")
+    n_inf = sum(1 for r in a if r["phase"] == "infinite")
+    assert min(starts[n_inf:]) > 0.999
 
 
 def test_checkpoint_and_resume(fake, tmp_path):

@@ -87,6 +87,21 @@ def test_reflection_on_gpu(ctx):
     assert abs(a[-1]["energy"] - ref[-1]["energy"]) <= 1e-9 * L
 
 
+def test_fermion_reflection_on_gpu(ctx):
+    """Hubbard U=4 (spinful fermions) with the mirrored environment in the
+    infinite phase: every step's energy is the oracle run's (explicit
+    environment), and the finite sweep that follows, which carries its
+    start vectors through the mirrored blocks, ends at the oracle's too."""
+    from paper_0902_3185_amd import driver as DR
+    L = 12
+    a = DR.run(DR.hubbard(4.0), L, 64, 1, _init, ctx=ctx, prec="fp64", tol=1e-10, reflect=True)
+    ref = OD.run(M.hubbard_model(4.0), L, 64, 1, _init, tol=1e-10)
+    assert len(a) == len(ref)
+    assert all("eps1" not in r for r in a if r["phase"] == "infinite")
+    for x, y in zip(a, ref):
+        assert abs(x["energy"] - y["energy"]) <= 1e-9 * L, (x, y)
+
+
 @pytest.mark.parametrize("U,spin", [(1.0, 0), (4.0, 1)])
 def test_ldos_matches_exact_diagonalisation(ctx, U, spin):
     """Eq. (5) on the centre superblock of an untruncated 8-site Hubbard run:
