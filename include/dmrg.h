@@ -248,7 +248,10 @@ dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant);
 
 /* Pin the product variant for the current precision (0 or 1, as
  * dmrg_sb_autotune reports it); DMRG_E_ARG for an unknown variant.  FP64
- * products ignore it.                                                       */
+ * products ignore it.  Variant 1's plan and padded operator pool are built
+ * and uploaded the first time variant 1 is pinned or the autotuner runs
+ * (synchronous, allocates; DMRG_E_NOMEM possible), not when the FP32
+ * operators are staged.                                                     */
 dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant);
 
 /* Reorthogonalisation of dmrg_lanczos_ground's basis (paper Sec. 3.3 gives

@@ -205,8 +205,10 @@ struct Staged {
   DevBuf wg_start;          // persistent launch: each workgroup's slots
   DevBuf coef_img, coef_seg;   // where each coefficient sits in images / segs
   int64_t ncoef_img = 0, ncoef_seg = 0;
-  // the macro-tile plan (FP32 / BF16 variant 1), staged with the FP32 pool
-  bool has_mac = false;
+  // the macro-tile plan (FP32 / BF16 variant 1), staged on first use
+  // (dmrg_sb_set_variant(1) or the autotuner) once the FP32 pool is
+  bool mac_staged = false;   // staging attempted
+  bool has_mac = false;      // staged and non-empty
   int32_t mac_nwg = 0, mac_nshared = 0, mac_nparts = 0;
   DevBuf mtiles, msegs, mggs, mitems, mwg, mshared, mpart, mcoef_seg, mcoef_gg, mdense;
   int64_t mac_ndense = 0;
@@ -348,6 +350,15 @@ dmrg_status stage_images(Staged& st, hipStream_t s) {
 
 // The macro-tile plan of a staged plan: records, work lists and room for
 // the partial tiles on the device.
+dmrg_status stage_macro(Staged& st, hipStream_t s);
+
+// The macro-tile plan of a staged FP32 pool, the first time it is asked for.
+dmrg_status ensure_macro(Staged& st, hipStream_t s) {
+  if (!st.has32 || st.mac_staged) return DMRG_OK;
+  st.mac_staged = true;
+  return stage_macro(st, s);
+}
+
 dmrg_status stage_macro(Staged& st, hipStream_t s) {
   MacroPlan mp;
   {
@@ -404,7 +415,6 @@ dmrg_status stage(dmrg_ctx ctx, Staged& st, bool want32) {
     if ((r = upload(st.dense32, f.data(), f.size() * sizeof(float), s)) != DMRG_OK) return r;
     HIP_TRY(hipStreamSynchronize(s));   // the host staging vector dies here
     st.has32 = true;
-    if ((r = stage_macro(st, s)) != DMRG_OK) return r;
   }
   st.max_nseg = 0;
   st.plain.clear();
@@ -806,7 +816,6 @@ dmrg_status dmrg_sb_set_prec(dmrg_sb sb, dmrg_prec prec) {
     if (r != DMRG_OK) return r;
     HIP_TRY(hipStreamSynchronize(sb->ctx->stream));
     sb->fwd.has32 = true;
-    if ((r = stage_macro(sb->fwd, sb->ctx->stream)) != DMRG_OK) return r;
   }
   sb->prec = prec;
   return DMRG_OK;
@@ -825,6 +834,7 @@ dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant) {
   DeviceGuard g(sb->ctx->device);
   hipStream_t s = sb->ctx->stream;
   Staged& stg = sb->fwd;
+  if ((st = ensure_macro(stg, s)) != DMRG_OK) return st;
   DevBuf x, y;
   HIP_TRY(x.ensure((size_t)std::max<int64_t>(stg.plan.D_in, 1) * sizeof(double)));
   HIP_TRY(y.ensure((size_t)std::max<int64_t>(stg.plan.D, 1) * sizeof(double)));
@@ -866,6 +876,11 @@ dmrg_status dmrg_sb_autotune(dmrg_sb sb, int32_t reps, int32_t* variant) {
 dmrg_status dmrg_sb_set_variant(dmrg_sb sb, int32_t variant) {
   if (!sb) return fail(DMRG_E_ARG, "null superblock");
   if (variant < 0 || variant >= kVariants) return fail(DMRG_E_ARG, "unknown kernel variant");
+  if (variant == 1 && sb->ctx) {
+    DeviceGuard g(sb->ctx->device);
+    const dmrg_status st = ensure_macro(sb->fwd, sb->ctx->stream);
+    if (st != DMRG_OK) return st;
+  }
   sb->variant[kernel_prec(sb->prec)] = variant;
   return DMRG_OK;
 }

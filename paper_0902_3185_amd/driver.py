@@ -174,6 +174,33 @@ def sector_parity(basis, Q, fermionic):
     return np.where(n % 2 == 0, 1.0, -1.0)
 
 
+def _add_kron(blk, o1, o2, Lb, nl, Rb, nr):
+    """blk[o1:, o2:] += Lb (x) Rb (None: the identity of size nl or nr).
+
+    Where one factor is a single entry (a one-state sector, as every sector
+    of a one-site basis with distinct quantum numbers is) the product is the
+    other factor scaled, written straight into blk (the same products, one
+    per entry, as the Kronecker product)."""
+    if (Rb is None and nr == 1) or (Rb is not None and Rb.shape == (1, 1)):
+        r = 1.0 if Rb is None else Rb[0, 0]
+        if Lb is None:
+            i = np.arange(nl)
+            blk[o1 + i, o2 + i] += r
+        else:
+            blk[o1:o1 + Lb.shape[0], o2:o2 + Lb.shape[1]] += Lb * r
+        return
+    if (Lb is None and nl == 1) or (Lb is not None and Lb.shape == (1, 1)):
+        l = 1.0 if Lb is None else Lb[0, 0]
+        if Rb is None:
+            i = np.arange(nr)
+            blk[o1 + i, o2 + i] += l
+        else:
+            blk[o1:o1 + Rb.shape[0], o2:o2 + Rb.shape[1]] += l * Rb
+        return
+    sub = np.kron(np.eye(nl) if Lb is None else Lb, np.eye(nr) if Rb is None else Rb)
+    blk[o1:o1 + sub.shape[0], o2:o2 + sub.shape[1]] += sub
+
+
 class Product:
     """The basis of L (x) R, reordered by q: per product sector, its runs
     (left sector, right sector, offset) in product order."""
@@ -234,14 +261,9 @@ class Product:
                         Rb = ab.get((b1, b2))
                         if Rb is None:
                             continue
-                    if Lb is None:
-                        Lb = np.eye(int(L.dim[a1]))
-                    if Rb is None:
-                        Rb = np.eye(int(R.dim[b1]))
-                    sub = np.kron(Lb, Rb)
                     if blk is None:
                         blk = np.zeros((int(self.basis.dim[s_out]), int(self.basis.dim[s_in])))
-                    blk[o1:o1 + sub.shape[0], o2:o2 + sub.shape[1]] += sub
+                    _add_kron(blk, o1, o2, Lb, int(L.dim[a1]), Rb, int(R.dim[b1]))
             if blk is not None and np.any(blk != 0.0):
                 out[(s_out, s_in)] = blk
         return Op(dA + da, out)

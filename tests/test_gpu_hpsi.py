@@ -17,6 +17,7 @@ import pytest
 
 from oracle import superblock as OS
 from workloads import WORKLOADS, seeded_vector, workload_superblock
+from workloads.superblocks import FIXTURES
 
 import fp_bounds as FB
 
@@ -81,12 +82,13 @@ FULL_CASES = [(p, 0) for p in ("fp64", "fp32", "bf16x3", "fp64_plain")] + [("fp3
 
 
 @pytest.mark.parametrize("prec,variant", FULL_CASES, ids=[f"{p}-v{v}" for p, v in FULL_CASES])
-@pytest.mark.parametrize("name", list(WORKLOADS))
+@pytest.mark.parametrize("name", list(WORKLOADS) + list(FIXTURES))
 def test_full_size_elementwise(ctx, name, prec, variant):
     """Every workload at its full size (the centre superblocks the benchmark
     times, same launch paths: the 32 x 32 tile kernel and the 64 x 64
-    macro-tile kernel): every entry of H psi within its rounding bound, and
-    the error norm within the aggregate tolerance."""
+    macro-tile kernel), the stored physical Hubbard superblock included:
+    every entry of H psi within its rounding bound, and the error norm
+    within the aggregate tolerance."""
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock(name, seed=0)
     sb = Superblock(desc, prec=prec, ctx=ctx)

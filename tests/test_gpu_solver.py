@@ -82,6 +82,25 @@ def test_lanczos_full_size_headline(ctx):
     assert abs(r["energy"] - E_ref) <= 1e-9 * 64, (r["energy"], E_ref)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_lanczos_physical_headline(ctx, prec):
+    """The stored physical Hubbard L=64, U=4, m=512 centre superblock (the
+    oracle's own DMRG run wrote it): the GPU ground state has the energy
+    that run recorded for this step, and it is an eigenvector of the
+    oracle's FP64 product to the requested residual."""
+    from paper_0902_3185_amd.superblock import Superblock
+    desc = workload_superblock("hubbard_L64_U4_m512_physical")
+    sb = Superblock(desc, prec=prec, ctx=ctx)
+    r = sb.lanczos(_dev(seeded_vector(sb.D, 3)), max_iter=2000, tol=1e-8)
+    assert r["converged"]
+    assert abs(r["energy"] - desc["meta"]["energies"][-1]) <= 1e-9 * 64, (r["energy"],)
+    psi = _host(r["psi"])
+    hp = OS.hpsi_blocks(desc, psi)
+    E = float(np.dot(psi, hp))
+    assert np.linalg.norm(hp - E * psi) <= 2e-8
+    assert abs(E - r["energy"]) <= 1e-10 * abs(E)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_lanczos_long_cycles_ladder(ctx, prec):
     """Restart cycles that run past 64 steps on the full 2x32 ladder

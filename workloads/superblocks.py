@@ -29,6 +29,8 @@ numbered rung by rung, cut after an even site) and the J1-J2 chain have
 """
 from __future__ import annotations
 
+import json
+import os
 from math import comb
 
 import numpy as np
@@ -281,8 +283,46 @@ def make_superblock(model, L, m, bonds="chain", sigma=1.5, seed=0, U=4.0, t=1.0,
     return dict(S=S, E=E, q_target=int(q_target), terms=terms, meta=meta)
 
 
+# Stored superblocks (files under data/, written by oracle/write_physical_fixture.py
+# from the oracle's own DMRG run): name -> file
+FIXTURES = {
+    "hubbard_L64_U4_m512_physical": "hubbard_L64_U4_m512_physical.npz",
+}
+DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+def fixture_superblock(name):
+    """A stored superblock description (the layout of the fixture files:
+    numeric arrays plus one JSON header, read without unpickling)."""
+    with np.load(os.path.join(DATA, FIXTURES[name]), allow_pickle=False) as z:
+        arrays = {k: z[k] for k in z.files}
+    head = json.loads(str(arrays["header"]))
+    terms = []
+    for k, rec in enumerate(head["terms"]):
+        t = dict(c=rec["c"], group=rec["group"])
+        for side in ("A", "B"):
+            if rec[side] is None:
+                t[side] = None
+                continue
+            key = f"t{k}_{side}"
+            blocks, off = [], 0
+            data = arrays[key + "_data"]
+            for (r, c), (mr, nc) in zip(arrays[key + "_rc"], arrays[key + "_shape"]):
+                blocks.append((int(r), int(c), data[off:off + mr * nc].reshape(mr, nc)))
+                off += int(mr) * int(nc)
+            t[side] = dict(delta=rec[side], blocks=blocks)
+        terms.append(t)
+    return dict(S=dict(q=arrays["S_q"], dim=arrays["S_dim"]), E=dict(q=arrays["E_q"], dim=arrays["E_dim"]),
+                q_target=head["q_target"], terms=terms, meta=head.get("meta", {}))
+
+
 def workload_superblock(name, seed=0, m=None, L=None):
-    """The synthetic superblock of a named workload (optionally a reduced m or L)."""
+    """The superblock of a named workload: synthetic (optionally a reduced m
+    or L), or a stored one (no size options)."""
+    if name in FIXTURES:
+        if m is not None or L is not None:
+            raise ValueError(f"{name} is a stored superblock: no m or L")
+        return fixture_superblock(name)
     p = dict(WORKLOADS[name])
     kw = dict(model=p["model"], L=p["L"] if L is None else L, m=p["m"] if m is None else m,
               bonds=p["bonds"], sigma=p["sigma"], seed=seed)
