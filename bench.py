@@ -2,8 +2,9 @@
 """Benchmark of the superblock hot path on one MI355X.
 
 One step = one pass of the whole hot path over the Hubbard L=64, U=4, m=512
-centre superblock (synthetic sectors and operators, seed 0; already built
-and staged in HBM before timing):
+centre superblock (by default the stored one from the oracle's own DMRG run
+of that chain, with its physical sectors and operators; --workload names a
+synthetic one instead; already built and staged in HBM before timing):
 
   ground state   dmrg_lanczos_ground: FP32 matrix-core products, FP64
                  vectors and reorthogonalisation, FP64 restart cycles,
@@ -14,8 +15,8 @@ and staged in HBM before timing):
 
 value = algorithmic H*psi flops executed in the timed steps / wall time
 (TFLOP/s).  roofline = the FP32 product kernel alone: algorithmic flops per
-launch / mean launch time from HIP events around every launch in the timed
-region.  The oracle's per-block numpy product on the host cores is reported
+launch / mean launch time from HIP events around every 16th launch in the
+timed region.  The oracle's per-block numpy product on the host cores is reported
 beside it (cpu_baseline), with the oracle's own Lanczos ground state of the
 same superblock, against which the GPU solves' energy and wave-function
 errors are given (cpu_baseline.accuracy_vs_oracle).
@@ -44,9 +45,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def describe(name):
-    """Human-readable workload description from its generator parameters."""
+def describe(name, desc=None):
+    """Human-readable workload description from its generator parameters (or,
+    for a stored superblock, from the record of the run that wrote it)."""
     from workloads import WORKLOADS
+    from workloads.superblocks import FIXTURES
+    if name in FIXTURES:
+        mt = desc["meta"]
+        return (f"{name}: Hubbard open chain L={mt['L']}, U={mt['U']:g}, t={mt['t']:g}, half filling, "
+                f"m={mt['m']}; the centre superblock of the last step of the oracle's own "
+                f"infinite-phase DMRG run (stored; physical sectors and operators)")
     p = WORKLOADS[name]
     geo = {"chain": "open chain", "ladder": "2-leg ladder (snake order)", "j1j2": "J1-J2 open chain"}
     if p["model"] == "hubbard":
@@ -148,7 +156,8 @@ def traffic_per_launch(workload, variant):
     summary of this workload and kernel variant, or None if there is none or
     the kernel sources changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hpsi_tiles_hubbard_L64_U4_m512.traffic.json")
+    kind = "macro" if variant == 1 else "tiles"
+    path = os.path.join(ROOT, "profiles", f"hpsi_{kind}_{workload}.traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -226,7 +235,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hubbard_L64_U4_m512")
+    ap.add_argument("--workload", default="hubbard_L64_U4_m512_physical")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-only", type=int, default=0, metavar="N",
@@ -359,7 +368,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": describe(args.workload),
+        "config": {"workload": describe(args.workload, desc),
                    "D": sb.D, "sector_pairs": int(len(sb.s_sec)), "terms": sb.nterms,
                    "tiles": st["ntiles"], "flops_alg_per_product": F, "kernel_variant": variant,
                    "kernel_variant_bf16x3": variant_bf16},

@@ -307,6 +307,9 @@ struct F32S {
   // waves per SIMD the register budget must allow (one workgroup of
   // sixteen waves per compute unit)
   static constexpr int kMinWavesPerEU = 4;
+  // a workgroup whose list holds two tiles of at most kWaves / 2 chunks
+  // each runs them at once, half of the waves on each
+  static constexpr bool kPair = true;
   static constexpr int kLdn = 36;                      // [k][w] window row stride (floats)
   static constexpr int kAFloats = kTile * kChunk;      // A panel [m][k]
   static constexpr int kBFloats = kChunk * kLdn;       // B panel ([k][w]; [n][k] uses 512)
@@ -505,11 +508,12 @@ struct F32S {
   // Fetches are unconditional (one past the wave's last chunk reads
   // nothing), so that every step issues the same loads and the compiler
   // keeps them ahead of the work.
+  // stride: the waves sharing the tile (wave is the index among them)
   __device__ static void contract(Acc& acc, const uint32_t* img, int ngemm, int nchunk, const TileGeo& g,
                                   int wave, int lane, const float* dense, const float* psi, int64_t ndense,
-                                  int64_t npsi, float* stage_area) {
+                                  int64_t npsi, float* stage_area, int stride = kWaves) {
     const __amdgpu_buffer_rsrc_t rd = buf_rsrc(dense, 4 * ndense), rp = buf_rsrc(psi, 4 * npsi);
-    const int nmy = (nchunk - wave + kWaves - 1) / kWaves;
+    const int nmy = (nchunk - wave + stride - 1) / stride;
     int si = 0;   // segment of the latest chunk fetched (chunks come in increasing order)
     Fetch f;
     f.seg = -1;
@@ -517,7 +521,7 @@ struct F32S {
     u.seg = -1;
     auto fetch = [&](Raw& R, int i, int& gc, int& s) {
       const bool live = i < nmy;
-      gc = wave + kWaves * (live ? i : nmy - 1);
+      gc = wave + stride * (live ? i : nmy - 1);
       while (si + 1 < ngemm && gc >= rfl(img_seg(img, si + 1).ch0)) ++si;
       s = si;
       const ImgSeg& sg = img_seg(img, s);
@@ -563,6 +567,7 @@ struct F64Tile {
   using red_t = double;
   static constexpr int kWaves = 8;
   static constexpr int kMinWavesPerEU = 2;   // one workgroup per compute unit
+  static constexpr bool kPair = false;
   struct Acc {
     f64x4 d[4];
   };
@@ -732,6 +737,118 @@ __device__ inline double img_gg_coef(const ImgGG& G, int mi, int nj) {
   return G.c * G.rs[mi] * G.cs[nj];
 }
 
+// Two tiles at once (configurations with kPair): a workgroup whose list
+// holds two tiles of at most kWaves / 2 chunks each gives the first half of
+// its waves the first tile and the other half the second, each half with
+// its own image, chunk stages, partial tiles and elementwise sums.  Every
+// wave then holds at most one chunk, as it does when the tiles run one
+// after the other, and the sums keep their order, so the results are the
+// same bits.  Returns false, having done nothing but read the two images,
+// when the tiles do not both qualify.
+template <class Cfg>
+__device__ bool pair_tiles(const uint32_t* __restrict__ images, int32_t stride, int slot,
+                           const typename Cfg::op_t* __restrict__ dense,
+                           const typename Cfg::psi_t* __restrict__ psi, double* __restrict__ y, double alpha,
+                           double beta, int64_t ndense, int64_t npsi, uint32_t* img, uint32_t* img2,
+                           char* pool, double* ggs, double* ggs2) {
+  using psi_t = typename Cfg::psi_t;
+  using red_t = typename Cfg::red_t;
+  constexpr int kW = Cfg::kWaves, kH = kW / 2;
+  static_assert(kW * 64 == kTile * kTile, "one output element per thread and tile");
+  for (int t = 0; t < 2; ++t) {
+    const uint4* src = reinterpret_cast<const uint4*>(images + (int64_t)(slot + t) * stride);
+    uint4* dst = reinterpret_cast<uint4*>(t ? img2 : img);
+    for (int x = threadIdx.x; x < stride / 4; x += kW * 64) dst[x] = src[x];
+  }
+  __syncthreads();
+  {
+    const ImgHeader& HA = img_header(img);
+    const ImgHeader& HB = img_header(img2);
+    const bool both = rfl(HA.a) != 0 && rfl(HB.a) != 0 && rfl(HA.nchunk) <= kH && rfl(HB.nchunk) <= kH;
+    if (!both) {
+      __syncthreads();   // every thread has read the headers before the images are rewritten
+      return false;
+    }
+  }
+  const int wave = rfl((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int grp = wave >= kH ? 1 : 0;   // uniform per wave
+  const int gw = wave - grp * kH;       // the wave's index among its tile's waves
+  const uint32_t* im = grp ? img2 : img;
+  double* gs = grp ? ggs2 : ggs;
+  const ImgHeader& H = img_header(im);
+  TileGeo g;
+  g.a = rfl(H.a);
+  g.b = rfl(H.b);
+  g.m0 = rfl(H.m0);
+  g.n0 = rfl(H.n0);
+  const int ngemm = rfl(H.ngemm), ngg = rfl(H.ngg), nchunk = rfl(H.nchunk);
+  int tid = (int)threadIdx.x - grp * kH * 64;   // the thread's index among its tile's threads
+  asm volatile("" : "+v"(tid));
+  const bool gg_thread = ngg > 0 && gw < kGGThreads / 64;
+  const int gmi = tid >> 3, gnj = (tid & 7) * 4;
+  typename Cfg::Acc acc;
+  Cfg::zero(acc);
+  if (gw < nchunk)
+    Cfg::contract(acc, im, ngemm, nchunk, g, gw, lane, dense, psi, ndense, npsi,
+                  reinterpret_cast<float*>(pool) + wave * Cfg::kStageFloats, kH);
+  psi_t gr[kGGEarly][4];
+  if (gg_thread) {
+#pragma unroll
+    for (int q = 0; q < kGGEarly; ++q) gg_load4(img_gg(im, ngemm, q < ngg ? q : 0), gmi, gnj, psi, gr[q]);
+  }
+  __syncthreads();   // every wave is done with its chunk stage
+  auto red = reinterpret_cast<red_t(*)[kTile * kTile]>(pool);
+  if (gw < nchunk) {
+#pragma unroll
+    for (int r = 0; r < Cfg::kRegs; ++r) {
+      int row, col;
+      Cfg::coords(lane, r, row, col);
+      red[wave][row * kTile + col] = Cfg::value(acc, r);
+    }
+  }
+  if (gg_thread) {
+#pragma unroll
+    for (int q = 0; q < kGGEarly; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(gr[q][e]));
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < kGGEarly; ++q)
+      if (q < ngg) {
+        const ImgGG& G = img_gg(im, ngemm, q);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] += img_gg_coef(G, gmi, gnj + e) * (double)gr[q][e];
+      }
+    for (int q = kGGEarly; q < ngg; ++q) {
+      const ImgGG& G = img_gg(im, ngemm, q);
+      psi_t t[4];
+      gg_load4(G, gmi, gnj, psi, t);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] += img_gg_coef(G, gmi, gnj + e) * (double)t[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) gs[gmi * kTile + gnj + e] = v[e];
+  }
+  __syncthreads();
+  // one element of each tile per thread: the waves' partial tiles in wave
+  // order, the elementwise terms, y
+  const int el = threadIdx.x;
+  const int mi = el / kTile, nj = el % kTile;
+  for (int t = 0; t < 2; ++t) {
+    const ImgHeader& Ht = img_header(t ? img2 : img);
+    const int nw = rfl(Ht.nchunk), ngt = rfl(Ht.ngg);
+    double v = 0.0;
+    for (int w = 0; w < nw; ++w) v += (double)red[t * kH + w][el];
+    if (ngt > 0) v += (t ? ggs2 : ggs)[el];
+    const int m = rfl(Ht.m0) + mi, n = rfl(Ht.n0) + nj;
+    if (m < rfl(Ht.a) && n < rfl(Ht.b)) {
+      const int64_t idx = Ht.y_off + (int64_t)m * rfl(Ht.ldy) + n;
+      y[idx] = beta == 0.0 ? alpha * v : alpha * v + beta * y[idx];
+    }
+  }
+  return true;
+}
+
 template <class Cfg, bool kStage>
 __global__ __launch_bounds__(Cfg::kWaves * 64, Cfg::kMinWavesPerEU) void hpsi_tiles(
     const uint32_t* __restrict__ images, int32_t stride,
@@ -749,12 +866,22 @@ __global__ __launch_bounds__(Cfg::kWaves * 64, Cfg::kMinWavesPerEU) void hpsi_ti
   constexpr size_t kStageBytes = kStage ? sizeof(float) * kW * Cfg::kStageFloats : 0;
   __shared__ __align__(16) char pool[kRedBytes > kStageBytes ? kRedBytes : kStageBytes];
   __shared__ double ggs[kTile * kTile];   // elementwise terms' sum per tile element
+  // the second tile of a pair run at once (pair_tiles)
+  __shared__ __align__(16) uint32_t img2[Cfg::kPair ? kImgWords : 4];
+  __shared__ double ggs2[Cfg::kPair ? kTile * kTile : 1];
   auto red = reinterpret_cast<red_t(*)[kTile * kTile]>(pool);
 
   // the workgroup's slots: a list (persistent launch) or its own index
   const int slot0 = wg_start ? wg_start[blockIdx.x] : (int)blockIdx.x;
   const int slot1 = wg_start ? wg_start[blockIdx.x + 1] : (int)blockIdx.x + 1;
-  for (int slot = slot0; slot < slot1; ++slot) {
+  int first = slot0;
+  if constexpr (Cfg::kPair) {
+    if (slot1 - slot0 == 2 &&
+        pair_tiles<Cfg>(images, stride, slot0, dense, psi, y, alpha, beta, ndense, npsi, img, img2, pool, ggs,
+                        ggs2))
+      first = slot1;
+  }
+  for (int slot = first; slot < slot1; ++slot) {
   // phase 0: the slot's image into LDS
   if (slot > slot0) __syncthreads();   // the previous tile is done with LDS
   {
