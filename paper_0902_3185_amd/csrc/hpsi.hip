@@ -1,12 +1,14 @@
 // Superblock product kernels for gfx950 (CDNA4).
 //
-// One workgroup owns one 32 x 32 output tile of one target block Y_q and
-// reduces every term that writes it (Y_q += c A Psi_q' B^T; paper Sec. 3.3,
-// blocking by effective symmetry).  The dense products run on the matrix
-// cores: the workgroup's waves (16 for FP32 and the BF16 split, 8 for FP64)
-// split the contraction chunks of all of the tile's terms, and their
-// partial tiles are summed in LDS in a fixed order, so the result does not
-// depend on scheduling.  Terms with identity or gather operators on both
+// A workgroup owns one 32 x 32 output tile of one target block Y_q at a time
+// and reduces every term that writes it (Y_q += c A Psi_q' B^T; paper Sec.
+// 3.3, blocking by effective symmetry); a persistent launch gives each
+// workgroup a list of tiles, and a list of two small tiles runs both at
+// once on the two halves of the waves.  The dense products run on the
+// matrix cores: the waves of a tile (16 for FP32 and the BF16 split, 8 for
+// FP64) split the contraction chunks of all of its terms, and their partial
+// tiles are summed in LDS in a fixed order, so the result does not depend
+// on scheduling.  Terms with identity or gather operators on both
 // sides are elementwise and are added in FP64 afterwards.  No atomics are
 // used on y.
 #include <hip/hip_runtime.h>
