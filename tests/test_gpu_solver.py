@@ -299,6 +299,59 @@ def test_rho_truncate_parity(ctx, name, m, keep, no_split):
         assert abs(weight - np.sum(ref["lam"])) <= 1e-13
 
 
+def _tied_superblock():
+    """Three target pairs whose psi blocks are U diag(sqrt w) V^T with the
+    weights tied exactly across sectors (S side: sector 0 {0.2, 0.2, 0.05},
+    sector 1 {0.2, 0.1, 0.05}, sector 2 {0.1, 0.05, 0.025, 0.025}; the E side
+    sees the same spectra), seeded random orthogonal U, V."""
+    rng = np.random.default_rng(12)
+    dS, dE = np.array([3, 3, 4]), np.array([4, 3, 3])
+    ident = [(s, s, np.eye(int(d))) for s, d in enumerate(dS)]
+    desc = dict(S=dict(q=np.array([0, 1, 2]), dim=dS), E=dict(q=np.array([0, 1, 2]), dim=dE), q_target=2,
+                terms=[dict(c=1.0, A=dict(delta=0, blocks=ident), B=None, group=0)])
+    weights = {0: [0.2, 0.2, 0.05], 1: [0.2, 0.1, 0.05], 2: [0.1, 0.05, 0.025, 0.025]}
+    pairs, D = OS.target_pairs(desc)
+    psi = np.zeros(D)
+    for (s, e, off) in pairs:
+        a, b = int(dS[s]), int(dE[e])
+        U, _ = np.linalg.qr(rng.standard_normal((a, a)))
+        V, _ = np.linalg.qr(rng.standard_normal((b, b)))
+        S = np.zeros((a, b))
+        S[np.arange(a), np.arange(a)] = np.sqrt(weights[s])
+        psi[off:off + a * b] = (U @ S @ V.T).reshape(-1)
+    return desc, psi
+
+
+@pytest.mark.parametrize("no_split", [False, True])
+@pytest.mark.parametrize("keep", [1, 2, 3, 4, 6, 9])
+def test_rho_truncate_exact_ties(ctx, keep, no_split):
+    """The truncation's tie rule on exactly degenerate weights within and
+    across sectors (cuts inside the 0.2, 0.1 and 0.05 clusters): the same
+    kept count, straddle flag, sector order of the kept weights and
+    discarded weight as the oracle, and kept columns that are eigenvectors
+    of the oracle's density blocks spanning the kept weight."""
+    from paper_0902_3185_amd.superblock import Superblock
+    desc, psi = _tied_superblock()
+    assert abs(np.linalg.norm(psi) - 1.0) < 1e-14
+    sb = Superblock(desc, prec="fp64", ctx=ctx)
+    for side in (0, 1):
+        ref = OR.truncate(desc, psi, side, keep, no_split=no_split)
+        got = sb.rho_truncate(_dev(psi), side, keep, no_split=no_split)
+        assert got["kept"] == ref["kept"] and got["straddle"] == ref["straddle"], (side, got["kept"], ref["kept"])
+        assert list(got["lam_sec"]) == list(ref["lam_sec"]), (side, got["lam_sec"], ref["lam_sec"])
+        assert abs(got["eps"] - ref["eps"]) <= 1e-14
+        assert np.allclose(got["lam"], ref["lam"], atol=1e-14)
+        rho = OR.density_blocks(desc, psi, side)
+        weight = 0.0
+        for s_, W in got["W"].items():
+            assert np.allclose(W.T @ W, np.eye(W.shape[1]), atol=1e-13)
+            lam_s = np.sort(got["lam"][got["lam_sec"] == s_])[::-1]
+            assert np.linalg.norm(rho[s_] @ W - W * lam_s[None, :]) <= 1e-13
+            weight += np.trace(W.T @ rho[s_] @ W)
+        assert abs(weight - np.sum(ref["lam"])) <= 1e-13
+    sb.close()
+
+
 def test_autograd_hellmann_feynman(ctx):
     """dE/dc_k = <psi|A_k (x) B_k|psi> at the ground state, through autograd."""
     import torch
