@@ -124,7 +124,7 @@ def test_deterministic_and_hermitian(ctx, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("name,m", [("j1j2_L64_m256", 48), ("ladder_2x32_m1024", 48),
                                     ("hubbard_L64_U4_m512", 64), ("j1j2_L64_m256", None),
-                                    ("hubbard_L64_U4_m512", None)])
+                                    ("hubbard_L64_U4_m512", None), ("hubbard_L64_U4_m512_physical", None)])
 def test_adjoint_parity(ctx, name, m, prec):
     from paper_0902_3185_amd.superblock import Superblock
     desc = workload_superblock(name, m=m, seed=3)

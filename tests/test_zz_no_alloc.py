@@ -52,9 +52,10 @@ CASES = [("fp32", 0), ("bf16x3", 0), ("fp64", 0), ("fp32", 1), ("bf16x3", 1)]
 def test_noalloc_matches_hpsi_on_two_calls(ctx, prec, variant):
     """Variant 1 (the macro-tile kernel) also keeps its partial tiles and
     tile counters in the scratch; the ladder superblock shares most of its
-    tiles between workgroups."""
+    tiles between workgroups.  Variant 0 runs on the physical headline
+    superblock."""
     from paper_0902_3185_amd.superblock import Superblock
-    first = ("ladder_2x32_m1024", None, 0) if variant else ("hubbard_L64_U4_m512", None, 0)
+    first = ("ladder_2x32_m1024", None, 0) if variant else ("hubbard_L64_U4_m512_physical", None, 0)
     for name, m, seed in [first, ("heisenberg_L100_m256", 64, 1)]:
         desc = workload_superblock(name, m=m, seed=seed)
         sb = Superblock(desc, prec=prec, ctx=ctx)
