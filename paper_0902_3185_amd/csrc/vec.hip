@@ -361,7 +361,11 @@ __global__ __launch_bounds__(kLzThreads) void lz_dotk(const double* __restrict__
   }
 }
 
-constexpr int kDotkE = 1, kDotkB = 32;   // the configuration the step launches
+// the configuration the step launches: one element per thread, batches of
+// 16 basis vectors (measured on three superblocks against 1 x 32, 2 x 16,
+// 2 x 32 and 4 x 8: 1 x 16 was fastest on all three, by 1-2 % of a solve
+// over 1 x 32; the larger shapes hold more registers and fewer waves)
+constexpr int kDotkE = 1, kDotkB = 16;
 
 // Coefficients of the single Gram-Schmidt pass that follows the local
 // three-term recurrence (see launch_lz_step_onepass).  With j = nv - 1, the
