@@ -312,6 +312,8 @@ struct F32S {
   // a workgroup whose list holds two tiles of at most kWaves / 2 chunks
   // each runs them at once, half of the waves on each
   static constexpr bool kPair = true;
+  // the next fetch goes out before a chunk's matrix instructions (contract)
+  static constexpr bool kEarlyFetch = !kBF16;
   static constexpr int kLdn = 36;                      // [k][w] window row stride (floats)
   static constexpr int kAFloats = kTile * kChunk;      // A panel [m][k]
   static constexpr int kBFloats = kChunk * kLdn;       // B panel ([k][w]; [n][k] uses 512)
@@ -452,16 +454,20 @@ struct F32S {
       lo[j] = __builtin_bit_cast(short, l);
     }
   }
-  __device__ static void mma(Acc& acc, const Raw& R, const Use& u, int kind, int K, int ch, int lane,
-                             float* stage_area) {
-    float* As = stage_area;
-    float* Bs = stage_area + kAFloats;
+  // a chunk's raw registers -> its panels in the wave's LDS area; the
+  // registers are free for the next fetch once this has been issued
+  __device__ static void put(const Raw& R, const Use& u, int kind, int K, int ch, int lane, float* stage_area) {
     // the previous chunk's reads of this area were issued before this point
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    stage(R, u, kind, K, ch, lane, As, Bs);
+    stage(R, u, kind, K, ch, lane, stage_area, stage_area + kAFloats);
+  }
+  // the staged chunk through the matrix cores
+  __device__ static void mma(Acc& acc, const Use& u, int kind, int lane, const float* stage_area) {
+    const float* As = stage_area;
+    const float* Bs = stage_area + kAFloats;
     // the wave's LDS operations complete in order: its reads below see the
-    // writes above
+    // writes of put
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -506,10 +512,14 @@ struct F32S {
     }
   }
   // The wave's chunks are wave, wave + kW, ... of the tile's chunk
-  // sequence; two are in flight ahead of the one on the matrix cores.
-  // Fetches are unconditional (one past the wave's last chunk reads
-  // nothing), so that every step issues the same loads and the compiler
-  // keeps them ahead of the work.
+  // sequence; two are in flight ahead of the one on the matrix cores.  In
+  // the FP32 form a chunk's registers are refilled with the fetch two
+  // chunks ahead as soon as the chunk is staged in LDS, before its matrix
+  // instructions, which may wait for the other waves of the SIMD; the BF16
+  // form fetches after them (its split operands leave no registers for the
+  // fetch while they are live).  Fetches are unconditional (one past the
+  // wave's last chunk reads nothing), so that every step issues the same
+  // loads and the compiler keeps them ahead of the work.
   // stride: the waves sharing the tile (wave is the index among them)
   __device__ static void contract(Acc& acc, const uint32_t* img, int ngemm, int nchunk, const TileGeo& g,
                                   int wave, int lane, const float* dense, const float* psi, int64_t ndense,
@@ -530,11 +540,13 @@ struct F32S {
       if (s != f.seg) setup_fetch(f, s, sg, rfl(sg.kind), rfl(sg.K), g, lane);
       load(R, f, gc - rfl(sg.ch0), live, rd, rp);
     };
-    auto run = [&](const Raw& R, int gc, int s) {
+    // stage chunk gc (segment s) from R; returns the segment's kind
+    auto stage_chunk = [&](const Raw& R, int gc, int s) {
       const ImgSeg& sg = img_seg(img, s);
       const int kind = rfl(sg.kind);
       if (s != u.seg) setup_use(u, s, sg, kind, g, lane);
-      mma(acc, R, u, kind, rfl(sg.K), gc - rfl(sg.ch0), lane, stage_area);
+      put(R, u, kind, rfl(sg.K), gc - rfl(sg.ch0), lane, stage_area);
+      return kind;
     };
     Raw ra, rb;
     int gA, sA, gB, sB;
@@ -542,11 +554,19 @@ struct F32S {
     fetch(rb, 1, gB, sB);
     __builtin_amdgcn_sched_barrier(0);
     for (int i = 0; i < nmy; i += 2) {
-      run(ra, gA, sA);
-      fetch(ra, i + 2, gA, sA);
+      int kind = stage_chunk(ra, gA, sA);
+      if constexpr (kEarlyFetch) fetch(ra, i + 2, gA, sA);
+      mma(acc, u, kind, lane, stage_area);
+      if constexpr (!kEarlyFetch) fetch(ra, i + 2, gA, sA);
       __builtin_amdgcn_sched_barrier(0);
-      if (i + 1 < nmy) run(rb, gB, sB);
-      fetch(rb, i + 3, gB, sB);
+      if (i + 1 < nmy) {
+        kind = stage_chunk(rb, gB, sB);
+        if constexpr (kEarlyFetch) fetch(rb, i + 3, gB, sB);
+        mma(acc, u, kind, lane, stage_area);
+        if constexpr (!kEarlyFetch) fetch(rb, i + 3, gB, sB);
+      } else {
+        fetch(rb, i + 3, gB, sB);
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
