@@ -145,7 +145,7 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 //   finish  (alpha, beta) and v_next = w / beta
 // or the local three-term recurrence followed by one Gram-Schmidt pass,
 // w' = w - alpha V_j - beta_{j-1} V_{j-1}, w -= V (V^T w'), in two passes:
-//   dotk    partial sums of V^T w and V^T V_j in one sweep
+//   dotk    partial sums of V^T w and V^T V_j in one sweep (lz_dotk_groups)
 //   reduce  the pass's coefficients (lz_reduce_local)
 //   axpy    the combined update and partial sums of ||w||^2 (lz_axpy_local)
 // or the recurrence alone, w' = w - alpha V_j - beta_{j-1} V_{j-1}, which
@@ -163,7 +163,9 @@ __global__ void record_kernel(const double* h1, const double* h2, int j, const d
 // Every pass gives each thread one element of w (256 per block, a grid of
 // ceil(n / 256) blocks) and walks the basis vectors in batches whose loads
 // are all issued before the first use, so a wave keeps a batch of basis
-// elements in flight instead of one memory latency per vector.  Partial sums
+// elements in flight instead of one memory latency per vector (the
+// single-pass step's sweep instead splits the basis over waves, each with
+// four elements per lane: lz_dotk_groups).  Partial sums
 // are added in a fixed order by the next launch, so results are repeatable;
 // the kernel boundary makes them visible across the chip without any cache
 // maintenance inside the kernels.
@@ -291,82 +293,65 @@ __global__ __launch_bounds__(kLzThreads) void lz_dot(const double* __restrict__ 
   }
 }
 
-// kS sets of products in one pass over the basis: for s < kS and i < nv,
-// partial[(s * nv + i) * gridDim.x + blockIdx.x] = the block's part of
-// <V_i, x_s> with x_0 = w, x_1 = V_{nv-1}, x_2 = V_{nv-2} (nv >= 2).  A
-// thread takes kE elements (256 kE per block) and the basis in batches of
-// kB vectors, loaded once and used for every set; the thread's products are
-// summed over its elements before the wave's butterfly.
-template <int kE, int kB, int kS>
-__global__ __launch_bounds__(kLzThreads) void lz_dotk(const double* __restrict__ V, int64_t ldv,
-                                                      int nv, const double* __restrict__ w,
-                                                      int64_t n, double* __restrict__ partial) {
-  static_assert(kS == 2 || kS == 3, "two or three sets");
-  __shared__ double sh[2][kLzThreads / 64][kBatch];
-  static_assert(kB <= kBatch, "batch larger than the block's staging");
-  const int64_t e0 = (int64_t)blockIdx.x * kLzThreads * kE + threadIdx.x;
-  bool ok[kE];
-  int64_t ec[kE];
-  double x[3][kE];
+
+// The sweep of a single-pass step: for i < nv and s < 2,
+// partial[(s * nv + i) * gridDim.x + blockIdx.x] = the part of <V_i, x_s>
+// over elements 256 blockIdx.x .. + 255, with x_0 = w and x_1 = V_{nv-1}
+// (nv >= 2).  The basis is split over waves: wave g of block (r, y) takes
+// basis vectors kGrpVecs (4 y + g) .. + kGrpVecs - 1 and elements 256 r ..
+// 256 r + 255, four per lane (lane, lane + 64, ...), and keeps its
+// 2 kGrpVecs sums in registers over them, in element order; one
+// reduce-scatter of those sums per wave then gives the wave's parts, so
+// there is one cross-lane reduction per 256 elements rather than one per
+// 64, and no LDS or barrier.  x_0 and x_1 are read by every wave of a block
+// (from the L1 after the first).  OffT: the type of an element offset
+// (32 bits below 2^31 elements: fewer registers).  Measured on the
+// physical Hubbard headline against one element per thread with a
+// reduction per batch of 16 vectors (19.0 us per sweep): groups of 16
+// vectors 17.0 us, of 8 vectors (twice the waves, 64 registers) faster
+// again by 1-2 % of a solve.
+constexpr int kGrpSteps = kLzThreads / 64;   // elements per lane
+constexpr int kDotkVecs = 8;                 // basis vectors per wave in the step's sweep
+
+template <int kGrpVecs, class OffT>
+__global__ __launch_bounds__(kLzThreads) void lz_dotk_groups(const double* __restrict__ V, int64_t ldv,
+                                                             int nv, const double* __restrict__ w,
+                                                             int64_t n, double* __restrict__ partial) {
+  // the wave index is uniform in a wave: say so, so that the vectors' start
+  // addresses stay in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int g0 = (blockIdx.y * (kLzThreads / 64) + wave) * kGrpVecs;
+  if (g0 >= nv) return;
+  const int nvg = min(kGrpVecs, nv - g0);
+  const int64_t eb = (int64_t)blockIdx.x * kLzThreads + lane;
+  const double* x1 = V + (int64_t)(nv - 1) * ldv;
+  double p[2 * kGrpVecs];
 #pragma unroll
-  for (int q = 0; q < kE; ++q) {
-    const int64_t e = e0 + (int64_t)q * kLzThreads;
-    ok[q] = e < n;
-    ec[q] = ok[q] ? e : 0;   // in-range address for the tail block
-    x[0][q] = ok[q] ? w[e] : 0.0;
-    x[1][q] = ok[q] ? V[(int64_t)(nv - 1) * ldv + e] : 0.0;
-    x[2][q] = (kS > 2 && ok[q]) ? V[(int64_t)(nv - 2) * ldv + e] : 0.0;
-  }
-  int i0 = 0, parity = 0;
+  for (int q = 0; q < 2 * kGrpVecs; ++q) p[q] = 0.0;
 #pragma unroll 1
-  for (; i0 + kB <= nv; i0 += kB) {
-    double t[kB][kE];
+  for (int st = 0; st < kGrpSteps; ++st) {
+    const int64_t e = eb + 64 * st;
+    const bool ok = e < n;
+    const OffT ec = ok ? (OffT)e : OffT(0);
+    double t[kGrpVecs];
 #pragma unroll
-    for (int b = 0; b < kB; ++b)
+    for (int b = 0; b < kGrpVecs; ++b) {
+      const double* row = V + (int64_t)(g0 + (b < nvg ? b : 0)) * ldv;   // uniform
+      t[b] = row[ec];
+    }
+    const double x0 = ok ? w[ec] : 0.0, xv = ok ? x1[ec] : 0.0;
 #pragma unroll
-      for (int q = 0; q < kE; ++q) t[b][q] = V[(int64_t)(i0 + b) * ldv + ec[q]];
-#pragma unroll 1
-    for (int s = 0; s < kS; ++s, parity ^= 1) {
-      double p[kB];
-#pragma unroll
-      for (int b = 0; b < kB; ++b) {
-        double a = 0.0;
-#pragma unroll
-        for (int q = 0; q < kE; ++q) a += ok[q] ? t[b][q] * x[s][q] : 0.0;
-        p[b] = a;
-      }
-      block_batch_partials<kB>(p, sh, parity, s * nv + i0, kB, partial);
+    for (int b = 0; b < kGrpVecs; ++b) {
+      p[b] += t[b] * x0;
+      p[kGrpVecs + b] += t[b] * xv;
     }
   }
-#pragma unroll 1
-  for (; i0 < nv; i0 += kTailBatch) {
-    const int nb = min(kTailBatch, nv - i0);
-    double t[kTailBatch][kE];
-#pragma unroll
-    for (int b = 0; b < kTailBatch; ++b)
-#pragma unroll
-      for (int q = 0; q < kE; ++q) t[b][q] = V[(int64_t)(i0 + (b < nb ? b : 0)) * ldv + ec[q]];
-#pragma unroll 1
-    for (int s = 0; s < kS; ++s, parity ^= 1) {
-      double p[kTailBatch];
-#pragma unroll
-      for (int b = 0; b < kTailBatch; ++b) {
-        double a = 0.0;
-#pragma unroll
-        for (int q = 0; q < kE; ++q) a += (ok[q] && b < nb) ? t[b][q] * x[s][q] : 0.0;
-        p[b] = a;
-      }
-      block_batch_partials<kTailBatch>(p, sh, parity, s * nv + i0, nb, partial);
-    }
+  const double tot = wave_reduce_scatter<2 * kGrpVecs>(p);   // lane l: value l % (2 kGrpVecs)
+  if (lane < 2 * kGrpVecs) {
+    const int set = lane / kGrpVecs, b = lane % kGrpVecs;
+    if (b < nvg) partial[((int64_t)set * nv + g0 + b) * gridDim.x + blockIdx.x] = tot;
   }
 }
-
-// the configuration the step launches: one element per thread, batches of
-// 16 basis vectors (measured on three superblocks against 1 x 32, 2 x 16,
-// 2 x 32 and 4 x 8: 1 x 16 was fastest on all three, by 1-2 % of a solve
-// over 1 x 32; the larger shapes hold more registers and fewer waves)
-constexpr int kDotkE = 1, kDotkB = 16;
-
 // Coefficients of the single Gram-Schmidt pass that follows the local
 // three-term recurrence (see launch_lz_step_onepass).  With j = nv - 1, the
 // true current vector v_j = s u where u is the stored V_j and s = 1 / ||u||
@@ -701,9 +686,15 @@ hipError_t launch_lz_step_onepass(double* w, double* V, int64_t ldv, int nv, int
                                   hipStream_t stream, float* out32) {
   if (nv < 2 || !nout || !scale || (!npend && !beta_prev)) return hipErrorInvalidValue;
   const int nb = lz_blocks(n);
-  const int nbk = (int)std::max<int64_t>(1, (n + kLzThreads * kDotkE - 1) / (kLzThreads * kDotkE));
-  hipLaunchKernelGGL((lz_dotk<kDotkE, kDotkB, 2>), dim3(nbk), dim3(kLzThreads), 0, stream, V, ldv, nv,
-                     w, n, partial);
+  const int nbk = nb;   // the sweep's blocks: 256 elements each
+  constexpr int kG = kDotkVecs;
+  const dim3 grid(nbk, (nv + kG * (kLzThreads / 64) - 1) / (kG * (kLzThreads / 64)));
+  if (n < (int64_t(1) << 31))
+    hipLaunchKernelGGL((lz_dotk_groups<kG, uint32_t>), grid, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n,
+                       partial);
+  else
+    hipLaunchKernelGGL((lz_dotk_groups<kG, int64_t>), grid, dim3(kLzThreads), 0, stream, V, ldv, nv, w, n,
+                       partial);
   // beta_{j-1} into ab[-1] (when pending), alpha_j into ab[0]
   hipLaunchKernelGGL(lz_reduce_local, dim3(nv), dim3(320), 0, stream, partial, nbk, nv, beta_prev, h,
                      npend, nb, scale, ab - 1, ab);
