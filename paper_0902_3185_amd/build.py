@@ -95,7 +95,7 @@ def build_sanitized(verbose=False):
     cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(BUILD_SAN, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        lang = ["-x", "hip"] if src.endswith(".hip") else ["-Xarch_host", "-march=x86-64-v3"]
         cmds.append(([HIPCC] + base + SANITIZE + lang + ["-c", os.path.join(CSRC, src), "-o", obj], src))
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as ex:

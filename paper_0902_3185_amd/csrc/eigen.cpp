@@ -14,6 +14,8 @@
 //   those only.
 #include "eigen.h"
 
+#include <immintrin.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -227,6 +229,81 @@ inline void row_pass(double* __restrict__ ai, int i, int lo, const double* __res
   acc[i] += (((s0 + s1) + (s2 + s3)) + t) + a * xi;
 }
 
+// Rows i and i + 1 of the lower triangle at once (a0 = A + i n, a1 = A +
+// (i + 1) n): with kUpd the rank-2 update of both rows first, then their
+// part of A x.  Over the columns [lo, i) the two rows share every load of
+// u, w, x and acc (AVX2, four columns per step); column i (row i's
+// diagonal, row i + 1's last off-diagonal entry) and row i + 1's diagonal
+// follow.  Each row's dot is kept in four lanes added as (l0 + l1) +
+// (l2 + l3), then the tail, in a fixed order.
+template <bool kUpd>
+inline void row_pass2(double* __restrict__ a0, double* __restrict__ a1, int i, int lo,
+                      const double* __restrict__ u, const double* __restrict__ w,
+                      const double* __restrict__ x, double* __restrict__ acc) {
+  const double u0 = kUpd ? u[i] : 0.0, w0 = kUpd ? w[i] : 0.0;
+  const double u1 = kUpd ? u[i + 1] : 0.0, w1 = kUpd ? w[i + 1] : 0.0;
+  const double x0 = x[i], x1 = x[i + 1];
+  const __m256d vu0 = _mm256_set1_pd(u0), vw0 = _mm256_set1_pd(w0);
+  const __m256d vu1 = _mm256_set1_pd(u1), vw1 = _mm256_set1_pd(w1);
+  const __m256d vx0 = _mm256_set1_pd(x0), vx1 = _mm256_set1_pd(x1);
+  __m256d s0 = _mm256_setzero_pd(), s1 = _mm256_setzero_pd();
+  int j = lo;
+  for (; j + 4 <= i; j += 4) {
+    __m256d A0 = _mm256_loadu_pd(a0 + j), A1 = _mm256_loadu_pd(a1 + j);
+    if (kUpd) {
+      const __m256d W = _mm256_loadu_pd(w + j), U = _mm256_loadu_pd(u + j);
+      A0 = _mm256_fnmadd_pd(vw0, U, _mm256_fnmadd_pd(vu0, W, A0));
+      A1 = _mm256_fnmadd_pd(vw1, U, _mm256_fnmadd_pd(vu1, W, A1));
+      _mm256_storeu_pd(a0 + j, A0);
+      _mm256_storeu_pd(a1 + j, A1);
+    }
+    const __m256d X = _mm256_loadu_pd(x + j);
+    __m256d C = _mm256_loadu_pd(acc + j);
+    C = _mm256_fmadd_pd(A1, vx1, _mm256_fmadd_pd(A0, vx0, C));
+    _mm256_storeu_pd(acc + j, C);
+    s0 = _mm256_fmadd_pd(A0, X, s0);
+    s1 = _mm256_fmadd_pd(A1, X, s1);
+  }
+  double t0 = 0.0, t1 = 0.0;
+  for (; j < i; ++j) {
+    double b0 = a0[j], b1 = a1[j];
+    if (kUpd) {
+      b0 = std::fma(-w0, u[j], std::fma(-u0, w[j], b0));
+      b1 = std::fma(-w1, u[j], std::fma(-u1, w[j], b1));
+      a0[j] = b0;
+      a1[j] = b1;
+    }
+    acc[j] = std::fma(b1, x1, std::fma(b0, x0, acc[j]));
+    t0 = std::fma(b0, x[j], t0);
+    t1 = std::fma(b1, x[j], t1);
+  }
+  double d0 = a0[i], e1 = a1[i], d1 = a1[i + 1];
+  if (kUpd) {
+    d0 = std::fma(-w0, u[i], std::fma(-u0, w[i], d0));
+    e1 = std::fma(-w1, u[i], std::fma(-u1, w[i], e1));
+    d1 = std::fma(-w1, u[i + 1], std::fma(-u1, w[i + 1], d1));
+    a0[i] = d0;
+    a1[i] = e1;
+    a1[i + 1] = d1;
+  }
+  alignas(32) double l0[4], l1[4];
+  _mm256_store_pd(l0, s0);
+  _mm256_store_pd(l1, s1);
+  acc[i] += ((((l0[0] + l0[1]) + (l0[2] + l0[3])) + t0) + d0 * x0) + e1 * x1;
+  acc[i + 1] += ((((l1[0] + l1[1]) + (l1[2] + l1[3])) + t1) + e1 * x0) + d1 * x1;
+}
+
+// Rows [r0, n) of the lower triangle, columns [lo, i] of row i, in pairs
+// (row_pass2) and a last single row.
+template <bool kUpd>
+inline void rows_pass(double* A, int n, int r0, int lo, const double* u, const double* w, const double* x,
+                      double* acc) {
+  int i = r0;
+  for (; i + 1 < n; i += 2)
+    row_pass2<kUpd>(A + (size_t)i * n, A + (size_t)(i + 1) * n, i, lo, u, w, x, acc);
+  if (i < n) row_pass<kUpd, true>(A + (size_t)i * n, i, lo, u, w, x, acc);
+}
+
 }  // namespace
 
 bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
@@ -278,7 +355,7 @@ bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
     if (!have) {
       if (!reflector(k, v.data(), beta, sub)) continue;
       for (int i = k + 1; i < n; ++i) p[i] = 0.0;
-      for (int i = k + 1; i < n; ++i) row_pass<false, true>(&A[(size_t)i * n], i, k + 1, nullptr, nullptr, v.data(), p.data());
+      rows_pass<false>(A.data(), n, k + 1, k + 1, nullptr, nullptr, v.data(), p.data());
     }
     double vtp = 0.0;
     for (int i = k + 1; i < n; ++i) {
@@ -293,7 +370,7 @@ bool sym_eigen_reduce(int n, const double* Ain, SymEig& out, int nthreads) {
     const bool next = k + 3 < n && reflector(k + 1, v2.data(), beta2, sub2);
     if (next) {
       for (int i = k + 2; i < n; ++i) p2[i] = 0.0;
-      for (int i = k + 2; i < n; ++i) row_pass<true, true>(&A[(size_t)i * n], i, k + 2, v.data(), p.data(), v2.data(), p2.data());
+      rows_pass<true>(A.data(), n, k + 2, k + 2, v.data(), p.data(), v2.data(), p2.data());
     } else {
       for (int i = k + 2; i < n; ++i) row_pass<true, false>(&A[(size_t)i * n], i, k + 2, v.data(), p.data(), nullptr, nullptr);
     }
