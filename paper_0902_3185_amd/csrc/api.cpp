@@ -1446,6 +1446,15 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     failed[i].store(0, std::memory_order_relaxed);
   }
   std::atomic<int> done(0), spec_next(0), spec_ready(0);
+  // threads with nothing to do wait here (blocked, not spinning: the host
+  // CPUs are shared hardware threads, and a spinning sibling slows the
+  // thread still reducing the largest sector)
+  std::mutex wait_mu;
+  std::condition_variable wait_cv;
+  auto wake = [&]() {
+    { std::lock_guard<std::mutex> lk(wait_mu); }
+    wait_cv.notify_all();
+  };
   auto publish = [&]() {
     struct FE {
       double lam;
@@ -1486,6 +1495,7 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
     spec_done.reset(new std::atomic<char>[std::max<size_t>(spec.size(), 1)]);
     for (size_t i = 0; i < spec.size(); ++i) spec_done[i].store(0, std::memory_order_relaxed);
     spec_ready.store(1, std::memory_order_release);
+    wake();
   };
   auto solve = [&](int) {
     for (;;) {
@@ -1525,13 +1535,18 @@ dmrg_status dmrg_rho_truncate(dmrg_sb sb, const double* psi_d, int32_t side, int
         failed[sec].store(1, std::memory_order_relaxed);
       }
       finished[sec].store(1, std::memory_order_release);
-      if (done.fetch_add(1, std::memory_order_acq_rel) + 1 == nsec - 1) publish();
+      const int d = done.fetch_add(1, std::memory_order_acq_rel) + 1;
+      if (d == nsec - 1) publish();
+      if (d == nsec) wake();
     }
     // speculative eigenvectors until the last sector is done
     for (;;) {
       if (done.load(std::memory_order_acquire) >= nsec) return;
       if (!spec_ready.load(std::memory_order_acquire)) {
-        std::this_thread::yield();
+        std::unique_lock<std::mutex> lk(wait_mu);
+        wait_cv.wait(lk, [&] {
+          return spec_ready.load(std::memory_order_acquire) || done.load(std::memory_order_acquire) >= nsec;
+        });
         continue;
       }
       const int i = spec_next.fetch_add(1);
