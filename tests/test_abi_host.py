@@ -136,6 +136,25 @@ def test_host_sym_eigen_matches_numpy():
         assert np.allclose(A @ V, V * w[None, :], atol=1e-12 * scale * n)
 
 
+def test_host_sym_eigen_every_small_size():
+    """Every size from 1 to 40 (the Householder passes take rows in pairs
+    and columns four at a time, so every parity of the row count and every
+    remainder of the column loop is met), against NumPy's eigenvalues and the
+    eigen-equation itself."""
+    rng = np.random.default_rng(3)
+    for n in range(1, 41):
+        X = rng.standard_normal((n, n))
+        A = X @ X.T / n + np.diag(rng.standard_normal(n))
+        a = np.ascontiguousarray(A.copy())
+        w = np.zeros(n)
+        _lib.check(_lib.lib().dmrg_host_sym_eigen(n, a.ctypes.data_as(C.POINTER(C.c_double)),
+                                                  w.ctypes.data_as(C.POINTER(C.c_double))))
+        scale = np.abs(np.linalg.eigvalsh(A)).max()
+        assert np.allclose(w, np.linalg.eigvalsh(A), atol=1e-13 * n * scale), n
+        assert np.allclose(a.T @ a, np.eye(n), atol=1e-13 * n), n
+        assert np.allclose(A @ a, a * w[None, :], atol=1e-13 * n * scale), n
+
+
 def test_host_sym_eigen_rank_deficient_density_matrices():
     """rho = Psi Psi^T of rank r < n (the untruncated small blocks of a run),
     with its null space at rounding level: all eigenpairs, no stall."""
