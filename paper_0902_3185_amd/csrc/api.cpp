@@ -31,6 +31,26 @@ thread_local std::string g_err;
 
 // Host threads for the per-sector eigen-solves: OMP_NUM_THREADS when set
 // (the machine's share for this process), else the hardware count; at most 32.
+// The sum of row[0..cnt) in the order of one wave's row sum on the device
+// (lane l adds entries l, l + 64, ... in batches of 16 per lane, then a
+// butterfly over the 64 lanes): the same bits as that device sum.
+double wave_order_sum(const double* row, int cnt) {
+  double s[64];
+  for (int l = 0; l < 64; ++l) s[l] = 0.0;
+  for (int b0 = 0; b0 < cnt; b0 += 64 * 16)
+    for (int l = 0; l < 64; ++l)
+      for (int u = 0; u < 16; ++u) {
+        const int b = b0 + l + 64 * u;
+        s[l] += b < cnt ? row[b] : 0.0;
+      }
+  for (int off = 32; off > 0; off >>= 1) {
+    double t[64];
+    for (int l = 0; l < 64; ++l) t[l] = s[l] + s[l ^ off];
+    for (int l = 0; l < 64; ++l) s[l] = t[l];
+  }
+  return s[0];
+}
+
 int host_threads() {
   int n = (int)std::max(1u, std::thread::hardware_concurrency());
   if (const char* e = std::getenv("OMP_NUM_THREADS")) {
@@ -1030,11 +1050,14 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   const size_t nsmall = (size_t)5 * nvec + 16;
   HIP_TRY(ctx->small.ensure(nsmall * sizeof(double)));
   HIP_TRY(hipMemsetAsync(ctx->small.p, 0, nsmall * sizeof(double), s));
-  if (ctx->host_small_n < nsmall) {
+  // host: the two check buffers of (alpha, beta), the Ritz coefficients and
+  // the two buffers of a check's norm partials
+  const size_t nhost = nsmall + 2 * nnorm;
+  if (ctx->host_small_n < nhost) {
     if (ctx->host_small) (void)hipHostFree(ctx->host_small);
     ctx->host_small = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&ctx->host_small, nsmall * sizeof(double), hipHostMallocDefault));
-    ctx->host_small_n = nsmall;
+    HIP_TRY(hipHostMalloc((void**)&ctx->host_small, nhost * sizeof(double), hipHostMallocDefault));
+    ctx->host_small_n = nhost;
   }
   // reduced precision: the FP32 copy of the next product's input, with the
   // zero padding past its end that the products' masked loads may reach
@@ -1082,6 +1105,19 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
   }
   double* hbuf[2] = {hs, hs + 2 * nvec};
   double* uh = hs + 4 * nvec;   // Ritz coefficients on their way to the device
+  // A single-pass step leaves its beta to the next step.  At a check point
+  // the step's norm partials travel with the (alpha, beta) copy and the host
+  // adds them in the device's order (the same bits as a device sum, without
+  // a launch on the queue); hnp_step[b] is the step whose partials hnp[b]
+  // holds, or -1.
+  double* hnp[2] = {hs + nsmall, hs + nsmall + nnorm};
+  int hnp_step[2] = {-1, -1};
+  auto fill_beta = [&](int b) {
+    const int jc = hnp_step[b];
+    if (jc < 0) return;
+    const double t = wave_order_sum(hnp[b], (int)nnorm);
+    hbuf[b][2 * jc + 1] = std::sqrt(t > 0.0 ? t : 0.0);
+  };
   double prev_ctol = tol;   // tolerance the previous cycle stopped at
   for (int cycle = 0; !converged && total < max_iter; ++cycle) {
     double beta0 = 0.0;
@@ -1178,8 +1214,8 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
         HIP_TRY(launch_lz_step_recurrence(w, V, D, j + 1, D, part, npb[(j - 1) & 1], npb[j & 1],
                                           ab + 2 * j, vnext, s, v32));
       }
-      // a single-pass step's beta_j is otherwise formed by the next step
-      if (check && !two) HIP_TRY(launch_lz_record_norm(npb[j & 1], D, ab + 2 * j + 1, s));
+      (void)check;   // a single-pass step's beta_j is formed by the next step, or
+                     // by the host from the partials copied at a check point
       return DMRG_OK;
     };
     // Steps j0 .. j1 (no check point before j1, none of them the last step
@@ -1251,9 +1287,15 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       const bool last = j + 2 >= nvec || total >= max_iter;
       if (!(j == 0 || (j + 1) % kCheck == 0 || last)) continue;
       HIP_TRY(hipMemcpyAsync(hbuf[nbuf], ab, 2 * (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      hnp_step[nbuf] = -1;
+      if (j >= 1 && !twice) {   // step j left its beta pending
+        HIP_TRY(hipMemcpyAsync(hnp[nbuf], npb[j & 1], nnorm * sizeof(double), hipMemcpyDeviceToHost, s));
+        hnp_step[nbuf] = j;
+      }
       HIP_TRY(hipEventRecord(ctx->chk[nbuf], s));
       if (pend >= 0) {   // the previous check: its copy is behind older steps only
         HIP_TRY(hipEventSynchronize(ctx->chk[pbuf]));
+        fill_beta(pbuf);
         if (evaluate(pend, hbuf[pbuf])) break;
         pend = -1;
       }
@@ -1270,6 +1312,7 @@ dmrg_status dmrg_lanczos_ground(dmrg_sb sb, const double* psi0_d, int32_t max_it
       // residual cannot be met yet, so its check is pipelined like the rest.
       if ((j == 0 && (cycle == 0 || prev_ctol <= tol)) || last || likely) {
         HIP_TRY(hipEventSynchronize(ctx->chk[nbuf]));
+        fill_beta(nbuf);
         if (evaluate(j, hbuf[nbuf]) || last) break;
       } else {
         pend = j;

@@ -149,10 +149,6 @@ hipError_t launch_lz_step_recurrence(const double* w, double* V, int64_t ldv, in
                                      double* ab, double* out, hipStream_t stream,
                                      float* out32 = nullptr);
 
-// *out = sqrt(sum of the lz_norm_partials(n) partial sums at npart), in the
-// order launch_lz_step_onepass and launch_lz_step_recurrence add them.
-hipError_t launch_lz_record_norm(const double* npart, int64_t n, double* out, hipStream_t stream);
-
 // Record alpha_j = h1[j] + h2[j] and beta_j = sqrt(nrm2) into ab[2*it], ab[2*it+1].
 hipError_t launch_record(const double* h1, const double* h2, int j, const double* nrm2,
                          double* ab, int it, hipStream_t stream);

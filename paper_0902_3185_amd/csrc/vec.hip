@@ -195,7 +195,7 @@ __device__ inline double wave_sum(double v) {
 // up to 64 * kRowBatch partials costs one memory latency rather than one per
 // value (the partials were written by the previous launch and are read from
 // another XCD's cache or from memory).
-constexpr int kRowBatch = 16;
+constexpr int kRowBatch = 16;   // the host's wave_order_sum (api.cpp) adds in this order too
 __device__ inline double wave_row_sum(const double* __restrict__ row, int cnt) {
   const int lane = threadIdx.x & 63;
   double s = 0.0;
@@ -568,13 +568,6 @@ __global__ __launch_bounds__(kLzThreads) void lz_local_update(
   }
 }
 
-// *out = sqrt(sum of partial[0..np)), summed as lz_reduce_local sums them.
-__global__ __launch_bounds__(64) void lz_record_norm(const double* __restrict__ partial, int np,
-                                                     double* __restrict__ out) {
-  const double t = wave_row_sum(partial, np);
-  if (threadIdx.x == 0) *out = sqrt(t > 0.0 ? t : 0.0);
-}
-
 // beta = sqrt(sum of partial[0..np)) (every block adds the same partials in
 // the same order); block 0 writes ab[0] = h1[j] + h2[j] and ab[1] = beta;
 // v_next = w / beta where v_next is given.
@@ -716,10 +709,6 @@ hipError_t launch_lz_step_recurrence(const double* w, double* V, int64_t ldv, in
   return hipGetLastError();
 }
 
-hipError_t launch_lz_record_norm(const double* npart, int64_t n, double* out, hipStream_t stream) {
-  hipLaunchKernelGGL(lz_record_norm, dim3(1), dim3(64), 0, stream, npart, lz_blocks(n), out);
-  return hipGetLastError();
-}
 
 hipError_t launch_multi_dot(const double* V, int64_t ldv, int nv, const double* w, int64_t n,
                             double* partial, double* h, hipStream_t stream) {
