@@ -233,7 +233,9 @@ def oracle_accuracy(desc, psi0, L, solves):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    # 20 steps: about 0.15 s of timed work on the headline, long enough that
+    # a single host hiccup does not move the figure
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="hubbard_L64_U4_m512_physical")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
